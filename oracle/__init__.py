@@ -1,0 +1,228 @@
+"""Plain FP64 CPU oracle for the direct N-body hot path (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline``
+leg may use this package.  The GPU product path never imports it.
+
+The arithmetic lives in ``nbody_oracle.c`` (plain C, FP64, no contraction, no
+fast-math); this module loads it with ctypes and adds the block-step driver loop
+(select -> predict all -> force on the active block -> correct), written in the
+order of the paper's Sec. 2 items 1-2.  Arrays of vectors are numpy (n, 3) float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nbody_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so and return its path."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        L.orc_num_threads.restype = C.c_int
+        L.orc_force.restype = C.c_int
+        L.orc_force.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64, C.c_int64,
+                                C.c_double, _dp, _dp]
+        L.orc_energy.restype = None
+        L.orc_energy.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_predict.restype = None
+        L.orc_predict.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp]
+        L.orc_select.restype = C.c_int64
+        L.orc_select.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_double), _ip]
+        L.orc_init_dt.restype = C.c_int
+        L.orc_init_dt.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_correct.restype = C.c_int
+        L.orc_correct.argtypes = [C.c_int64, C.c_int64, _ip, C.c_double, _dp, _dp, _dp, _dp,
+                                  _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                                  C.c_double, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+_CODES = {-1: "index or range out of bounds", -4: "time step below dt_min",
+          -5: "non-finite acceleration, jerk or step"}
+
+
+def _check(rc):
+    if rc != 0:
+        raise OracleError(_CODES.get(rc, "error %d" % rc))
+
+
+def force(x, v, m, eps, ilist=None, j0=0, j1=None):
+    """Acceleration and jerk of bodies `ilist` from j in [j0, j1): Eq. 1-2 and d/dt."""
+    x, v, m = _c(x), _c(v), _c(m)
+    n = m.shape[0]
+    if ilist is None:
+        ilist = np.arange(n, dtype=np.int64)
+    ilist = _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    acc = np.zeros((ilist.size, 3))
+    jerk = np.zeros((ilist.size, 3))
+    _check(lib().orc_force(n, x, v, m, ilist.size, ilist, int(j0), j1, float(eps), acc, jerk))
+    return acc, jerk
+
+
+def energy(x, v, m, eps):
+    """(kinetic, potential, total) with the softened pair potential, self term excluded."""
+    x, v, m = _c(x), _c(v), _c(m)
+    k, p = C.c_double(), C.c_double()
+    lib().orc_energy(m.shape[0], x, v, m, float(eps), C.byref(k), C.byref(p))
+    return k.value, p.value, k.value + p.value
+
+
+def predict(x, v, a, jk, t, t_next):
+    x, v, a, jk, t = _c(x), _c(v), _c(a), _c(jk), _c(t)
+    xp = np.empty_like(x)
+    vp = np.empty_like(v)
+    lib().orc_predict(t.shape[0], x, v, a, jk, t, float(t_next), xp, vp)
+    return xp, vp
+
+
+def select(t, dt):
+    t, dt = _c(t), _c(dt)
+    idx = np.empty(t.shape[0], dtype=np.int64)
+    tn = C.c_double()
+    mcount = lib().orc_select(t.shape[0], t, dt, C.byref(tn), idx)
+    return tn.value, idx[:mcount].copy()
+
+
+def init_dt(a, jk, eta_s, dt_max, dt_min):
+    a, jk = _c(a), _c(jk)
+    dt = np.empty(a.shape[0])
+    _check(lib().orc_init_dt(a.shape[0], a, jk, float(eta_s), float(dt_max), float(dt_min), dt))
+    return dt
+
+
+@dataclass
+class State:
+    """Per-body Hermite state: x, v, a, j (n, 3); m, t, dt (n,).  All FP64."""
+
+    x: np.ndarray
+    v: np.ndarray
+    m: np.ndarray
+    a: np.ndarray = None
+    j: np.ndarray = None
+    t: np.ndarray = None
+    dt: np.ndarray = None
+
+    @property
+    def n(self):
+        return int(self.m.shape[0])
+
+    def copy(self):
+        return State(*(None if f is None else f.copy() for f in
+                       (self.x, self.v, self.m, self.a, self.j, self.t, self.dt)))
+
+
+def correct(st: State, ilist, t_next, xp, vp, acc, jerk, eta, dt_max, dt_min, want_dta=False):
+    """Hermite-4 correction of the active bodies plus the new power-of-two step (in place)."""
+    ilist = _c(ilist, np.int64)
+    acc, jerk = _c(acc), _c(jerk)
+    dta = np.empty(ilist.size) if want_dta else None
+    ptr = dta.ctypes.data_as(C.c_void_p) if want_dta else None
+    rc = lib().orc_correct(st.n, ilist.size, ilist, float(t_next), _c(xp), _c(vp), acc, jerk,
+                           st.x, st.v, st.a, st.j, st.t, st.dt, float(eta), float(dt_max),
+                           float(dt_min), ptr)
+    _check(rc)
+    return dta
+
+
+@dataclass
+class Params:
+    eps: float
+    eta: float = 0.02
+    eta_s: float = 0.01
+    dt_max: float = 2.0 ** -3
+    dt_min: float = 2.0 ** -40
+
+
+def startup(x, v, m, p: Params) -> State:
+    """t = 0: every body active; compute a, j and the startup steps."""
+    st = State(_c(x).copy(), _c(v).copy(), _c(m).copy())
+    n = st.n
+    st.a, st.j = force(st.x, st.v, st.m, p.eps)
+    st.t = np.zeros(n)
+    st.dt = init_dt(st.a, st.j, p.eta_s, p.dt_max, p.dt_min)
+    return st
+
+
+@dataclass
+class StepRecord:
+    t_next: float
+    ilist: np.ndarray
+    xp: np.ndarray = None
+    vp: np.ndarray = None
+    acc: np.ndarray = None
+    jerk: np.ndarray = None
+
+
+def block_step(st: State, p: Params, keep=False) -> StepRecord:
+    """One block step: select the active block, predict all, force, correct."""
+    t_next, ilist = select(st.t, st.dt)
+    xp, vp = predict(st.x, st.v, st.a, st.j, st.t, t_next)
+    acc, jerk = force(xp, vp, st.m, p.eps, ilist)
+    rec = StepRecord(t_next, ilist)
+    if keep:
+        rec.xp, rec.vp, rec.acc, rec.jerk = xp, vp, acc, jerk
+    correct(st, ilist, t_next, xp, vp, acc, jerk, p.eta, p.dt_max, p.dt_min)
+    return rec
+
+
+def integrate(x, v, m, t_end, p: Params, log=None):
+    """Block-step Hermite-4 integration from t = 0 to t_end (a multiple of dt_max).
+
+    Returns (state, n_steps, interactions) where interactions = sum of m * N.
+    If `log` is a list, each step's (t_next, active indices) is appended.
+    """
+    st = startup(x, v, m, p)
+    n = st.n
+    steps, inter = 0, n * n
+    while True:
+        tmin = float(np.min(st.t + st.dt))
+        if tmin > t_end:
+            break
+        rec = block_step(st, p)
+        steps += 1
+        inter += rec.ilist.size * n
+        if log is not None:
+            log.append((rec.t_next, rec.ilist))
+        if np.all(st.t == t_end):
+            break
+    return st, steps, inter

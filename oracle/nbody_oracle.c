@@ -1,0 +1,282 @@
+/*
+ * nbody_oracle.c -- plain FP64 CPU reference for the direct N-body hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
+ * CPU-baseline leg call this library; the GPU product path never does, and the
+ * two share no source.
+ *
+ * What it computes (Spera 2014, "Using GPUs to solve the classical N-body
+ * problem", GPUHEP2014):
+ *   - the gravitational pair sum of Eq. 1 with G = 1, softened as in Eq. 2
+ *     (Plummer softening, Sec. 1), together with its time derivative (the jerk),
+ *     which the Hermite scheme of Sec. 2 item 1 needs;
+ *   - the 4th-order Hermite predictor and corrector (Sec. 2 item 1; the
+ *     standard Makino-Aarseth form from Aarseth's book, cited there);
+ *   - power-of-two block time steps (Sec. 2 item 2) with Aarseth's step
+ *     criterion and the active-block selection;
+ *   - the total energy, kinetic plus softened potential, used as the
+ *     conservation diagnostic (Sec. 3, Fig. 3 right).
+ *
+ * Conventions: FP64 throughout, round to nearest, compiled without contraction
+ * or fast-math.  Arrays of vectors are (n, 3) row-major.  The pair vector is
+ * r_ij = r_j - r_i with a plus sign, which is Eq. 1 with its minus sign folded
+ * into the direction of r_ij.  Sums over j run sequentially j = j0 .. j1-1 with
+ * Neumaier's compensated summation, so the reference's own rounding error does
+ * not grow with N.  OpenMP parallelises over i only; each i's sum is computed
+ * by one thread in fixed order, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- compensated summation (Neumaier 1974) ---------------------------------- */
+typedef struct { double s, c; } csum;
+
+static void cs_add(csum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double cs_val(const csum *a) { return a->s + a->c; }
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---- acceleration and jerk (Eq. 1 with the softening of Eq. 2) --------------
+ *
+ * For each listed body i (ilist[k], k < ni) and each j in [j0, j1) with j != i:
+ *   r  = x_j - x_i,  w = v_j - v_i,  s = r.r + eps^2
+ *   a_i += m_j r / s^(3/2)
+ *   jerk_i += m_j [ w / s^(3/2) - 3 (r.w) r / s^(5/2) ]
+ * The jerk term is the time derivative of the acceleration term.  Positions and
+ * velocities are those of the (predicted) j-set for both i and j.
+ * Returns 0, or -1 if an index is out of range.
+ */
+int orc_force(int64_t n, const double *x, const double *v, const double *m,
+              int64_t ni, const int64_t *ilist, int64_t j0, int64_t j1,
+              double eps, double *acc, double *jerk)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        csum a[3] = {{0, 0}, {0, 0}, {0, 0}};
+        csum jk[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double r[3], w[3];
+            for (int d = 0; d < 3; d++) {
+                r[d] = x[3 * j + d] - x[3 * i + d];
+                w[d] = v[3 * j + d] - v[3 * i + d];
+            }
+            const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double rinv2 = rinv * rinv;
+            const double mu = m[j] * rinv * rinv2;                  /* m_j s^(-3/2) */
+            const double rw = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+            const double alpha = 3.0 * rw * rinv2;                  /* 3 (r.w) / s  */
+            for (int d = 0; d < 3; d++) {
+                cs_add(&a[d], mu * r[d]);
+                cs_add(&jk[d], mu * (w[d] - alpha * r[d]));
+            }
+        }
+        for (int d = 0; d < 3; d++) {
+            acc[3 * k + d] = cs_val(&a[d]);
+            jerk[3 * k + d] = cs_val(&jk[d]);
+        }
+    }
+    return 0;
+}
+
+/* ---- total energy ------------------------------------------------------------
+ * E = sum_i m_i |v_i|^2 / 2  -  sum_{i<j} m_i m_j / sqrt(|r_ij|^2 + eps^2)
+ * (the softened potential whose gradient is the force of Eq. 2; the self term
+ * i = j is excluded).  Kinetic and potential parts are returned separately.
+ * Each row i sums j > i in order; rows are then combined in order i = 0..n-1.
+ */
+void orc_energy(int64_t n, const double *x, const double *v, const double *m,
+                double eps, double *kinetic, double *potential)
+{
+    const double eps2 = eps * eps;
+    double *row = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < n; i++) {
+        csum p = {0, 0};
+        for (int64_t j = i + 1; j < n; j++) {
+            double r2 = 0.0;
+            for (int d = 0; d < 3; d++) {
+                const double dr = x[3 * j + d] - x[3 * i + d];
+                r2 += dr * dr;
+            }
+            cs_add(&p, m[i] * m[j] / sqrt(r2 + eps2));
+        }
+        row[i] = cs_val(&p);
+    }
+    csum pot = {0, 0}, kin = {0, 0};
+    for (i = 0; i < n; i++) {
+        cs_add(&pot, row[i]);
+        const double v2 = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+        cs_add(&kin, 0.5 * m[i] * v2);
+    }
+    free(row);
+    *kinetic = cs_val(&kin);
+    *potential = -cs_val(&pot);
+}
+
+/* ---- predictor (Hermite 4th order) -------------------------------------------
+ * Every body is Taylor-expanded from its own time t_i to t_next (Sec. 2 item 2:
+ * bodies outside the active block are only predicted), with d = t_next - t_i:
+ *   xp = x + v d + a d^2/2 + j d^3/6,   vp = v + a d + j d^2/2
+ */
+void orc_predict(int64_t n, const double *x, const double *v, const double *a,
+                 const double *jk, const double *t, double t_next,
+                 double *xp, double *vp)
+{
+    for (int64_t i = 0; i < n; i++) {
+        const double d = t_next - t[i];
+        for (int c = 0; c < 3; c++) {
+            const int64_t q = 3 * i + c;
+            xp[q] = x[q] + v[q] * d + a[q] * d * d / 2.0 + jk[q] * d * d * d / 6.0;
+            vp[q] = v[q] + a[q] * d + jk[q] * d * d / 2.0;
+        }
+    }
+}
+
+/* ---- active block (Sec. 2 item 2) ---------------------------------------------
+ * t_next = min_i (t_i + dt_i); the active block is every i with t_i + dt_i equal
+ * to t_next, in ascending order of i.  Returns the block size m.
+ */
+int64_t orc_select(int64_t n, const double *t, const double *dt, double *t_next,
+                   int64_t *ilist)
+{
+    double tn = INFINITY;
+    for (int64_t i = 0; i < n; i++)
+        if (t[i] + dt[i] < tn)
+            tn = t[i] + dt[i];
+    int64_t mcount = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (t[i] + dt[i] == tn)
+            ilist[mcount++] = i;
+    *t_next = tn;
+    return mcount;
+}
+
+static double norm3(const double *u)
+{
+    return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
+
+/* ---- startup step --------------------------------------------------------------
+ * At t = 0 every body gets dt = the largest power of two not above
+ * min(eta_s |a| / |j|, dt_max).  Returns 0, -4 if a step falls below dt_min,
+ * -5 on a non-finite value.
+ */
+int orc_init_dt(int64_t n, const double *a, const double *jk, double eta_s,
+                double dt_max, double dt_min, double *dt)
+{
+    for (int64_t i = 0; i < n; i++) {
+        const double an = norm3(a + 3 * i), jn = norm3(jk + 3 * i);
+        if (!isfinite(an) || !isfinite(jn))
+            return -5;
+        double want = (jn > 0.0) ? eta_s * an / jn : dt_max;
+        if (want > dt_max)
+            want = dt_max;
+        double step = dt_max;
+        while (step > want)
+            step /= 2.0;
+        if (step < dt_min)
+            return -4;
+        dt[i] = step;
+    }
+    return 0;
+}
+
+/* ---- corrector and new step (Hermite 4th order, block steps) ------------------
+ * For active body i with h = t_next - t_i, old (a0, j0) at t_i, new (a1, j1) at
+ * t_next and predicted (xp, vp):
+ *   a2 = [-6 (a0 - a1) - h (4 j0 + 2 j1)] / h^2       (second derivative at t_i)
+ *   a3 = [12 (a0 - a1) + 6 h (j0 + j1)] / h^3          (third derivative)
+ *   x  = xp + a2 h^4/24 + a3 h^5/120,   v = vp + a2 h^3/6 + a3 h^4/24
+ * The new step follows Aarseth's criterion evaluated at t_next, with the second
+ * derivative there a2' = a2 + a3 h:
+ *   dtA = sqrt( eta (|a1| |a2'| + |j1|^2) / (|j1| |a3| + |a2'|^2) )
+ * and is kept a power of two (Sec. 2 item 2): halve while larger than dtA; if no
+ * halving was needed, double once when dtA >= 2 h, t_next is a multiple of 2 h
+ * and 2 h <= dt_max.  The body's time becomes t_next.
+ * dta_out (may be NULL) receives the unquantised dtA of each active body.
+ * Returns 0, -4 if a new step falls below dt_min, -5 on a non-finite value.
+ */
+int orc_correct(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
+                const double *xp, const double *vp, const double *acc_new,
+                const double *jerk_new, double *x, double *v, double *a,
+                double *jk, double *t, double *dt, double eta, double dt_max,
+                double dt_min, double *dta_out)
+{
+    int status = 0;
+    for (int64_t k = 0; k < mcount; k++) {
+        const int64_t i = ilist[k];
+        if (i < 0 || i >= n)
+            return -1;
+        const double h = t_next - t[i];
+        double a2[3], a3[3], a2e[3];
+        for (int c = 0; c < 3; c++) {
+            const double a0 = a[3 * i + c], j0 = jk[3 * i + c];
+            const double a1 = acc_new[3 * k + c], j1 = jerk_new[3 * k + c];
+            a2[c] = (-6.0 * (a0 - a1) - h * (4.0 * j0 + 2.0 * j1)) / (h * h);
+            a3[c] = (12.0 * (a0 - a1) + 6.0 * h * (j0 + j1)) / (h * h * h);
+            x[3 * i + c] = xp[3 * i + c] + a2[c] * h * h * h * h / 24.0
+                           + a3[c] * h * h * h * h * h / 120.0;
+            v[3 * i + c] = vp[3 * i + c] + a2[c] * h * h * h / 6.0
+                           + a3[c] * h * h * h * h / 24.0;
+            a[3 * i + c] = a1;
+            jk[3 * i + c] = j1;
+            a2e[c] = a2[c] + a3[c] * h;
+        }
+        const double an = norm3(acc_new + 3 * k), jn = norm3(jerk_new + 3 * k);
+        const double sn = norm3(a2e), cn = norm3(a3);
+        const double num = an * sn + jn * jn, den = jn * cn + sn * sn;
+        double dta;
+        if (den > 0.0)
+            dta = sqrt(eta * num / den);
+        else
+            dta = INFINITY;
+        if (isnan(dta) || !isfinite(an) || !isfinite(jn))
+            return -5;
+        if (dta_out)
+            dta_out[k] = dta;
+        double step = h;
+        if (step > dta) {
+            while (step > dta)
+                step /= 2.0;
+        } else if (dta >= 2.0 * h && fmod(t_next, 2.0 * h) == 0.0 && 2.0 * h <= dt_max) {
+            step = 2.0 * h;
+        }
+        if (step < dt_min)
+            status = -4;
+        t[i] = t_next;
+        dt[i] = step;
+    }
+    return status;
+}

@@ -1,0 +1,57 @@
+"""Pins for the oracle's total energy (kinetic plus softened pair potential).
+
+Checks: the gradient of the potential part reproduces m_i a_i of the independently
+pinned force; a circular Kepler binary has T = -W/2 and E = -m1 m2 / (2 a) (virial
+theorem and Kepler's closed form); the kinetic part is independent of positions.
+"""
+import numpy as np
+import pytest
+
+
+def test_potential_gradient_matches_force(orc):
+    from paper_1411_5234_amd import inputs
+    s = inputs.plummer(64, 21, masses=inputs.salpeter_masses(64, 22))
+    eps = 0.02
+    acc, _ = orc.force(s.x, s.v, s.m, eps)
+    h = 1e-5
+    for i in (0, 13, 63):
+        for c in range(3):
+            xp = s.x.copy()
+            xm = s.x.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            wp = orc.energy(xp, s.v, s.m, eps)[1]
+            wm = orc.energy(xm, s.v, s.m, eps)[1]
+            grad = (wp - wm) / (2 * h)
+            # -dW/dx_i = m_i a_i
+            assert -grad == pytest.approx(s.m[i] * acc[i, c], rel=1e-6, abs=1e-9 * s.m[i] * np.abs(acc[i]).max())
+
+
+@pytest.mark.parametrize("m1,m2,a", [(0.5, 0.5, 1.0), (0.8, 0.2, 0.37)])
+def test_circular_binary_virial_and_kepler_energy(orc, m1, m2, a):
+    mt = m1 + m2
+    vrel = np.sqrt(mt / a)                       # circular speed, G = 1
+    x = np.array([[m2 / mt * a, 0, 0], [-m1 / mt * a, 0, 0]])
+    v = np.array([[0, m2 / mt * vrel, 0], [0, -m1 / mt * vrel, 0]])
+    T, W, E = orc.energy(x, v, np.array([m1, m2]), 1e-12)
+    assert T == pytest.approx(-W / 2, rel=1e-12)
+    assert E == pytest.approx(-m1 * m2 / (2 * a), rel=1e-12)
+
+
+def test_kinetic_part_ignores_positions_and_is_quadratic(orc):
+    from paper_1411_5234_amd import inputs
+    s = inputs.plummer(50, 3)
+    T1, W1, _ = orc.energy(s.x, s.v, s.m, 1e-3)
+    T2, W2, _ = orc.energy(s.x * 3.0, 2.0 * s.v, s.m, 1e-3)
+    assert T2 == pytest.approx(4.0 * T1, rel=1e-14)
+    # far apart, the unsoftened potential scales like 1/size
+    T3, W3, _ = orc.energy(s.x * 1e3, s.v, s.m, 0.0)
+    T4, W4, _ = orc.energy(s.x * 2e3, s.v, s.m, 0.0)
+    assert W4 == pytest.approx(W3 / 2.0, rel=1e-12)
+    assert T3 == T1
+
+
+def test_self_term_excluded(orc):
+    # one body: no potential even though eps > 0 would give -m^2/eps
+    T, W, E = orc.energy(np.zeros((1, 3)), np.ones((1, 3)), np.array([2.0]), 0.1)
+    assert W == 0.0 and T == pytest.approx(3.0)

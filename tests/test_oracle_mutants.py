@@ -1,0 +1,98 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case compiles a copy of the oracle's C source with one planted mistake (a
+dropped term, a wrong sign, index, coefficient or condition) into a temporary
+directory, points the oracle module at that copy, and runs the pin that should
+fail.  Everything here runs on the CPU; the real oracle is restored afterwards.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle as real_oracle
+import test_oracle_blocksteps as tb
+import test_oracle_energy as te
+import test_oracle_force as tf
+import test_oracle_hermite as th
+
+SRC = os.path.join(os.path.dirname(real_oracle.__file__), "nbody_oracle.c")
+
+MUTANTS = [
+    ("jerk drops the radial term", "mu * (w[d] - alpha * r[d])", "mu * (w[d])",
+     lambda o: tf.test_jerk_is_time_derivative_of_acc(o, 3)),
+    ("jerk coefficient 2 instead of 3", "3.0 * rw * rinv2", "2.0 * rw * rinv2",
+     lambda o: tf.test_jerk_is_time_derivative_of_acc(o, 3)),
+    ("pair vector reversed", "r[d] = x[3 * j + d] - x[3 * i + d];", "r[d] = x[3 * i + d] - x[3 * j + d];",
+     lambda o: tf.test_acc_is_minus_gradient_of_potential(o, 0)),
+    ("mass of i instead of j", "m[j] * rinv * rinv2", "m[i] * rinv * rinv2",
+     lambda o: tf.test_acc_is_minus_gradient_of_potential(o, 0)),
+    ("eps instead of eps^2", "r[2] * r[2] + eps2;", "r[2] * r[2] + eps;",
+     lambda o: tf.test_acc_is_minus_gradient_of_potential(o, 0)),
+    ("kinetic energy missing the half", "cs_add(&kin, 0.5 * m[i] * v2)", "cs_add(&kin, m[i] * v2)",
+     lambda o: te.test_circular_binary_virial_and_kepler_energy(o, 0.5, 0.5, 1.0)),
+    ("potential halved", "cs_add(&p, m[i] * m[j] / sqrt(r2 + eps2))", "cs_add(&p, 0.5 * m[i] * m[j] / sqrt(r2 + eps2))",
+     lambda o: te.test_potential_gradient_matches_force(o)),
+    ("potential ignores softening", "sqrt(r2 + eps2))", "sqrt(r2))",
+     lambda o: te.test_potential_gradient_matches_force(o)),
+    ("predictor a d^2/6", "a[q] * d * d / 2.0", "a[q] * d * d / 6.0",
+     lambda o: th.test_predictor_is_exact_for_cubic_motion(o)),
+    ("predictor drops jerk in v", "vp[q] = v[q] + a[q] * d + jk[q] * d * d / 2.0;", "vp[q] = v[q] + a[q] * d;",
+     lambda o: th.test_predictor_is_exact_for_cubic_motion(o)),
+    ("corrector jerk weights swapped", "h * (4.0 * j0 + 2.0 * j1)", "h * (2.0 * j0 + 4.0 * j1)",
+     lambda o: th.test_corrector_is_exact_for_quintic_motion(o, 2.0 ** -4)),
+    ("corrector a3 h^5/24", "h * h * h * h * h / 120.0", "h * h * h * h * h / 24.0",
+     lambda o: th.test_corrector_is_exact_for_quintic_motion(o, 0.5)),
+    ("corrector sign of a3 term", "a3[c] = (12.0 * (a0 - a1) + 6.0 * h * (j0 + j1))",
+     "a3[c] = (12.0 * (a0 - a1) - 6.0 * h * (j0 + j1))",
+     lambda o: th.test_kepler_orbit_matches_closed_form(o, 0.5, 1e-5)),
+    ("Aarseth numerator |j| instead of |j|^2", "an * sn + jn * jn", "an * sn + jn",
+     lambda o: th.test_aarseth_step_on_circular_orbit(o)),
+    ("Aarseth without sqrt", "dta = sqrt(eta * num / den);", "dta = eta * num / den;",
+     lambda o: th.test_aarseth_step_on_circular_orbit(o)),
+    ("doubling ignores commensurability", "fmod(t_next, 2.0 * h) == 0.0", "1",
+     lambda o: tb.test_block_step_invariants_over_a_run(o)),
+    ("select takes everything due within twice the block time", "if (t[i] + dt[i] == tn)", "if (t[i] + dt[i] <= 2.0 * tn)",
+     lambda o: tb.test_select_against_brute_scan(o)),
+    ("startup step not a power of two", "        dt[i] = step;\n    }\n    return 0;", "        dt[i] = want;\n    }\n    return 0;",
+     lambda o: th.test_aarseth_step_on_circular_orbit(o)),
+]
+
+
+def _load(path):
+    """Bind a mutant library with the same signatures as the real one."""
+    saved_lib, saved_path = real_oracle._lib, real_oracle._LIB_PATH
+    real_oracle._lib, real_oracle._LIB_PATH = None, path
+    orig_build = real_oracle.build
+    real_oracle.build = lambda force=False: path
+    try:
+        return real_oracle.lib()
+    finally:
+        real_oracle.build = orig_build
+        real_oracle._lib, real_oracle._LIB_PATH = saved_lib, saved_path
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_planted_mistake(tmp_path, name, old, new, pin):
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor must match exactly once: %r" % old
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", so, str(mutant), "-lm"], check=True)
+    mlib = _load(so)
+    real_oracle.build(force=False)
+    saved = real_oracle._lib
+    real_oracle._lib = mlib
+    try:
+        with pytest.raises((AssertionError, real_oracle.OracleError)):
+            pin(real_oracle)
+    finally:
+        real_oracle._lib = saved
+
+
+def test_unmutated_oracle_passes_the_same_pins():
+    real_oracle.build(force=False)
+    for _, _, _, pin in MUTANTS:
+        pin(real_oracle)
