@@ -1,0 +1,169 @@
+/*
+ * nbody.h -- C ABI of libnbody.so, the MI355X (gfx950) hot path of a direct
+ * N-body code with a 4th-order Hermite integrator and power-of-two block time
+ * steps (Spera 2014, "Using GPUs to solve the classical N-body problem",
+ * GPUHEP2014: Eq. 1-2 and Sec. 2 items 1-5).
+ *
+ * General conventions
+ *  - Units: G = 1.  Every floating-point state array is FP64.
+ *  - Layout: structure of arrays.  A body's x, y, z (and so on) live in separate
+ *    arrays of length n; "3*m SoA" below means three consecutive arrays of m
+ *    values each (x-components, then y, then z).
+ *  - Ownership: every array pointer is DEVICE memory owned by the caller (the
+ *    Python layer passes torch tensors).  The library owns only the context's
+ *    scratch memory.  Host pointers are named *_host.
+ *  - Streams: every call is enqueued on the context's HIP stream and returns
+ *    without waiting, except nb_select_active, nb_energy and nb_sync, which
+ *    wait for the stream.
+ *  - Errors: a call returns NB_OK or a negative nb_status.  Argument errors are
+ *    detected on the host before anything is enqueued.  Errors that kernels
+ *    find (a non-finite acceleration, jerk or step; a step below dt_min; an
+ *    index out of range) are latched in a device status word and reported by
+ *    the next waiting call (nb_select_active, nb_energy, nb_sync), which also
+ *    clears the word.  nb_last_error() gives a message for the last failure.
+ *  - Indices are int32 (n < 2^31); sizes are int64.
+ *  - A context is bound to one device and one stream and is not thread-safe.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+typedef enum {
+    NB_OK = 0,
+    NB_EINVAL = -1,   /* bad argument (null pointer, eps <= 0, bad range ...)  */
+    NB_ENOMEM = -2,   /* device or pinned allocation failed                    */
+    NB_EDEVICE = -3,  /* a HIP runtime call failed                             */
+    NB_ERANGE = -4,   /* a new time step fell below dt_min                      */
+    NB_ENAN = -5,     /* non-finite acceleration, jerk or time step            */
+    NB_EINDEX = -6    /* an active index was outside [0, n)                     */
+} nb_status;
+
+typedef enum {
+    NB_FP64 = 0,      /* all pair arithmetic in FP64                            */
+    NB_MIXED = 1      /* FP64 pair differences, FP32 pair arithmetic, FP64 sums */
+} nb_precision;
+
+/* One system of n bodies.  Every pointer is a device array of length n.
+ *  state at each body's own time t_i:  x..z, vx..vz, ax..az (acceleration),
+ *      jx..jz (jerk), m (mass), t (time), dt (power-of-two step);
+ *  predicted j-set at the current block time:  xp..zp, vxp..vzp;
+ *  FP32 copies used by NB_MIXED:  vxp32..vzp32, m32 (may be NULL when only
+ *      NB_FP64 is used).                                                      */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *ax, *ay, *az;
+    double *jx, *jy, *jz;
+    double *m, *t, *dt;
+    double *xp, *yp, *zp;
+    double *vxp, *vyp, *vzp;
+    float *vxp32, *vyp32, *vzp32, *m32;
+} nb_system;
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL means the null stream).  The context allocates its scratch memory here
+ * (force partial sums, selection temporaries, the status word, pinned host
+ * words); a later call that needs more scratch grows it once, after waiting
+ * for the stream.  Returns NB_OK, NB_EINVAL or NB_ENOMEM. */
+nb_status nb_ctx_create(nb_ctx **ctx, int device, void *hip_stream);
+nb_status nb_ctx_destroy(nb_ctx *ctx);
+/* Message for the last failing call on this context (never NULL). */
+const char *nb_last_error(const nb_ctx *ctx);
+/* Wait for the context's stream; return and clear any latched kernel error. */
+nb_status nb_sync(nb_ctx *ctx);
+
+/* Active block (Sec. 2 item 2: bodies share power-of-two steps and only the
+ * block due next is advanced).  Computes t_next = min_i (t_i + dt_i) and writes
+ * to i_idx (device, capacity n) every i with t_i + dt_i == t_next, in ascending
+ * order.  The comparison is exact: all times are dyadic.  Waits for the stream
+ * and returns t_next and the block size m on the host.  n == 0 gives m = 0. */
+nb_status nb_select_active(nb_ctx *ctx, const nb_system *sys, double *t_next_host,
+                           int32_t *i_idx, int32_t *m_host);
+
+/* Predictor (Sec. 2 item 2: bodies outside the active block are only advanced
+ * by Taylor expansion).  For every body, with d = t_next - t_i:
+ *   xp = x + v d + a d^2/2 + j d^3/6,   vp = v + a d + j d^2/2   (FP64),
+ * and, when the FP32 pointers are non-NULL, vp32 = (float)vp and m32 = (float)m. */
+nb_status nb_predict(nb_ctx *ctx, const nb_system *sys, double t_next);
+
+/* Acceleration and jerk of the active block from the predicted j-set (Eq. 1
+ * with G = 1 and the Plummer softening of Eq. 2; the jerk is its time
+ * derivative).  For k < m, with i = i_idx[k] (or i = k when i_idx is NULL) and
+ * every j in [j0, j1):
+ *   r = xp_j - xp_i, w = vp_j - vp_i, s = |r|^2 + eps^2,
+ *   acc_k  += m_j r s^(-3/2),
+ *   jerk_k += m_j (w s^(-3/2) - 3 (r.w) r s^(-5/2)).
+ * The pair j = i contributes exactly 0 because eps > 0 is required.
+ * acc and jerk are device arrays of 3*m doubles (SoA, stride m) and are
+ * overwritten.  NB_FP64 does all pair arithmetic in FP64; NB_MIXED forms r in
+ * FP64, rounds it to FP32, does the rest of the pair arithmetic in FP32 (with
+ * the hardware reciprocal square root) and accumulates in FP64 (the precision
+ * split of Sec. 2 item 4).  The j-range is split across workgroups when m is
+ * small (Sec. 2 item 3) and the partial sums are combined in a fixed order,
+ * so results are bitwise reproducible.  m == 0 is a no-op.
+ * Returns NB_EINVAL for eps <= 0, j0 < 0, j1 > n, j0 > j1, m < 0 or m > n. */
+nb_status nb_force_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                          int32_t m, int64_t j0, int64_t j1, double eps,
+                          nb_precision precision, double *acc, double *jerk);
+
+/* Startup (t = 0, every body active): copy acc/jerk (3*n SoA, from
+ * nb_force_active with i_idx = NULL, m = n) into the state, set t = 0 and
+ * dt = the largest power of two not above min(eta_s |a| / |j|, dt_max).
+ * A step below dt_min latches NB_ERANGE; a non-finite value latches NB_ENAN. */
+nb_status nb_init_steps(nb_ctx *ctx, const nb_system *sys, const double *acc,
+                        const double *jerk, double eta_s, double dt_max, double dt_min);
+
+/* Corrector and new step for the active block (Sec. 2 items 1-2; the standard
+ * 4th-order Hermite form of Aarseth's book, cited there).  With h = t_next - t_i,
+ * (a0, j0) the stored and (a1, j1) the new acc/jerk (3*m SoA, order of i_idx):
+ *   a2 = [-6 (a0 - a1) - h (4 j0 + 2 j1)] / h^2,  a3 = [12 (a0 - a1) + 6 h (j0 + j1)] / h^3,
+ *   x = xp + a2 h^4/24 + a3 h^5/120,  v = vp + a2 h^3/6 + a3 h^4/24,
+ * then a = a1, j = j1, t = t_next, and the new step from Aarseth's criterion
+ *   dtA = sqrt(eta (|a1||a2'| + |j1|^2) / (|j1||a3| + |a2'|^2)),  a2' = a2 + a3 h,
+ * kept a power of two: halve while above dtA; if no halving was needed, double
+ * once when dtA >= 2h, t_next is a multiple of 2h and 2h <= dt_max.
+ * A step below dt_min latches NB_ERANGE; non-finite values latch NB_ENAN. */
+nb_status nb_correct(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
+                     const double *acc, const double *jerk, double t_next,
+                     double eta, double dt_max, double dt_min);
+
+/* Total energy of the current state (x, v at the bodies' own times, so call it
+ * when every body is synchronised):  kinetic = sum_i m_i |v_i|^2 / 2 and
+ * potential = -sum_{i<j} m_i m_j / sqrt(|x_j - x_i|^2 + eps^2), self term
+ * excluded, all in FP64 with compensated final sums.  This is the conservation
+ * diagnostic of Sec. 3 (Fig. 3).  Waits for the stream.  eps >= 0. */
+nb_status nb_energy(nb_ctx *ctx, const nb_system *sys, double eps,
+                    double *kinetic_host, double *potential_host);
+
+/* Launch plan of nb_force_active for a j-range of nj bodies and an active
+ * block of m (a pure function of (nj, m, precision), so a system's results do
+ * not depend on anything else running): i-bodies per lane, lanes sharing one
+ * i-body, and the number of j-chunks (the paper's Bfactor).  Out-pointers may
+ * be NULL. */
+void nb_force_plan(int64_t nj, int32_t m, nb_precision precision,
+                   int32_t *i_per_lane, int32_t *lanes_per_i, int32_t *j_chunks);
+
+/* Same as nb_force_active but with an explicit plan (for tests and tuning);
+ * i_per_lane in {1, 2, 4}, lanes_per_i in {1, 4, 16, 64}, j_chunks >= 1. */
+nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                               int32_t m, int64_t j0, int64_t j1, double eps,
+                               nb_precision precision, int32_t i_per_lane,
+                               int32_t lanes_per_i, int32_t j_chunks,
+                               double *acc, double *jerk);
+
+/* Library version string. */
+const char *nb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -47,6 +47,9 @@ def lib():
         L.orc_force.restype = C.c_int
         L.orc_force.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64, C.c_int64,
                                 C.c_double, _dp, _dp]
+        L.orc_force_scale.restype = C.c_int
+        L.orc_force_scale.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
+                                      C.c_int64, C.c_double, _dp, _dp]
         L.orc_energy.restype = None
         L.orc_energy.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -97,6 +100,20 @@ def force(x, v, m, eps, ilist=None, j0=0, j1=None):
     jerk = np.zeros((ilist.size, 3))
     _check(lib().orc_force(n, x, v, m, ilist.size, ilist, int(j0), j1, float(eps), acc, jerk))
     return acc, jerk
+
+
+def force_scale(x, v, m, eps, ilist=None, j0=0, j1=None):
+    """Per body: sum_j |a_ij| and sum_j |jerk_ij| (magnitude scale of the pair sums)."""
+    x, v, m = _c(x), _c(v), _c(m)
+    n = m.shape[0]
+    if ilist is None:
+        ilist = np.arange(n, dtype=np.int64)
+    ilist = _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    sa = np.zeros(ilist.size)
+    sj = np.zeros(ilist.size)
+    _check(lib().orc_force_scale(n, x, v, m, ilist.size, ilist, int(j0), j1, float(eps), sa, sj))
+    return sa, sj
 
 
 def energy(x, v, m, eps):

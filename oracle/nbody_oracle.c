@@ -109,6 +109,51 @@ int orc_force(int64_t n, const double *x, const double *v, const double *m,
     return 0;
 }
 
+/* ---- magnitude scale of the pair sums -------------------------------------------
+ * For each listed body i: S_a = sum_j |a_ij| and S_j = sum_j |jerk_ij|, the sums of
+ * the magnitudes of the same pair terms orc_force adds (j != i, j in [j0, j1)).
+ * S / |sum| is the cancellation factor of body i: rounding errors of size u per
+ * term can move the sum by about u * S.  Returns 0, or -1 on a bad index/range.
+ */
+int orc_force_scale(int64_t n, const double *x, const double *v, const double *m,
+                    int64_t ni, const int64_t *ilist, int64_t j0, int64_t j1,
+                    double eps, double *sa, double *sj)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        csum ta = {0, 0}, tj = {0, 0};
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double r[3], w[3], ja[3];
+            for (int d = 0; d < 3; d++) {
+                r[d] = x[3 * j + d] - x[3 * i + d];
+                w[d] = v[3 * j + d] - v[3 * i + d];
+            }
+            const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double mu = m[j] * rinv * rinv * rinv;
+            const double rw = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+            const double alpha = 3.0 * rw * rinv * rinv;
+            for (int d = 0; d < 3; d++)
+                ja[d] = mu * (w[d] - alpha * r[d]);
+            cs_add(&ta, mu * sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
+            cs_add(&tj, sqrt(ja[0] * ja[0] + ja[1] * ja[1] + ja[2] * ja[2]));
+        }
+        sa[k] = cs_val(&ta);
+        sj[k] = cs_val(&tj);
+    }
+    return 0;
+}
+
 /* ---- total energy ------------------------------------------------------------
  * E = sum_i m_i |v_i|^2 / 2  -  sum_{i<j} m_i m_j / sqrt(|r_ij|^2 + eps^2)
  * (the softened potential whose gradient is the force of Eq. 2; the self term

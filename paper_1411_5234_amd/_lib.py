@@ -1,0 +1,85 @@
+"""ctypes binding of libnbody.so (include/nbody.h).  Argument marshalling only.
+
+Every step of the path runs in the HIP library; this module turns torch tensors
+into device pointers and torch streams into hipStream_t handles, and raises
+NbError on a non-zero status.  If the library is not built the import of the
+first entry point fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnbody.so")
+
+FIELDS64 = ["x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "jx", "jy", "jz",
+            "m", "t", "dt", "xp", "yp", "zp", "vxp", "vyp", "vzp"]
+FIELDS32 = ["vxp32", "vyp32", "vzp32", "m32"]
+
+NB_FP64 = 0
+NB_MIXED = 1
+PRECISIONS = {"fp64": NB_FP64, "mixed": NB_MIXED}
+
+STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
+          -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX"}
+
+# Every symbol include/nbody.h declares.
+EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
+           "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
+           "nb_force_plan", "nb_force_active_plan", "nb_version"]
+
+
+class NbSystem(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in FIELDS64 + FIELDS32]
+
+
+class NbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = STATUS.get(code, "?")
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libnbody.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libnbody.so is not built (%s); run `python -m paper_1411_5234_amd.build`"
+                           % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    ps = C.POINTER(NbSystem)
+    sig = {
+        "nb_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, vp]),
+        "nb_ctx_destroy": (C.c_int, [vp]),
+        "nb_last_error": (C.c_char_p, [vp]),
+        "nb_sync": (C.c_int, [vp]),
+        "nb_select_active": (C.c_int, [vp, ps, C.POINTER(f64), vp, C.POINTER(i32)]),
+        "nb_predict": (C.c_int, [vp, ps, f64]),
+        "nb_force_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, vp, vp]),
+        "nb_force_active_plan": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, i32, i32, i32,
+                                           vp, vp]),
+        "nb_force_plan": (None, [i64, i32, C.c_int, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "nb_init_steps": (C.c_int, [vp, ps, vp, vp, f64, f64, f64]),
+        "nb_correct": (C.c_int, [vp, ps, vp, i32, vp, vp, f64, f64, f64, f64]),
+        "nb_energy": (C.c_int, [vp, ps, f64, C.POINTER(f64), C.POINTER(f64)]),
+        "nb_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def force_plan(nj: int, m: int, precision: str = "mixed"):
+    L = load()
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    L.nb_force_plan(int(nj), int(m), PRECISIONS[precision], C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value

@@ -1,0 +1,418 @@
+// Pair-force kernels: acceleration and jerk of the active block (Eq. 1 with the
+// Plummer softening of Eq. 2, and its time derivative), plus the softened
+// potential energy.  gfx950, wave64.
+//
+// Work decomposition (Sec. 2 items 3 and 5 of the paper, re-designed for CDNA4):
+//  - a workgroup of 256 lanes holds IL i-bodies per lane-group in VGPRs;
+//  - S consecutive lanes share the same i-bodies and take every S-th j of each
+//    tile, so a small active block still gives every lane work; their partial
+//    sums are combined at the end with cross-lane shuffles inside the wave;
+//  - j-bodies are staged cooperatively through LDS in structure-of-arrays tiles
+//    (coalesced global loads, broadcast LDS reads when S = 1);
+//  - the j-range is split into chunks across blockIdx.y (the paper's Bfactor);
+//    each chunk writes FP64 partials that a second kernel sums in fixed order.
+// Precision (Sec. 2 item 4): the FP64 kernel does all pair arithmetic in FP64;
+// the mixed kernel forms r_j - r_i in FP64, rounds it to FP32, does the rest in
+// FP32 with the hardware reciprocal square root, accumulates short runs of
+// FP32 terms and folds them into FP64 totals.
+#include "nb_internal.h"
+
+namespace nbk {
+
+constexpr int TILE = 512;  // j-bodies per LDS tile
+
+// FP64 reciprocal square root: hardware estimate refined by two Newton steps
+// y <- y (3 - s y^2) / 2 written as y + y (1/2 - (s/2) y^2).
+__device__ __forceinline__ double rsqrt64(double s)
+{
+    double y = __builtin_amdgcn_rsq(s);
+    const double hs = 0.5 * s;
+    double e = fma(-hs, y * y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-hs, y * y, 0.5);
+    y = fma(y, e, y);
+    return y;
+}
+
+template <int S>
+__device__ __forceinline__ double group_sum(double v)
+{
+    // butterfly over the S consecutive lanes of a group (S divides 64)
+#pragma unroll
+    for (int off = S / 2; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, S);
+    return v;
+}
+
+template <int IL, int S, int F>
+__global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
+{
+    __shared__ double sx[TILE], sy[TILE], sz[TILE];
+    __shared__ float svx[TILE], svy[TILE], svz[TILE], sm[TILE];
+
+    const int tid = threadIdx.x;
+    const int g = tid / S, s = tid % S;
+    constexpr int IWG = (WG / S) * IL;
+    const int64_t kbase = (int64_t)blockIdx.x * IWG + (int64_t)g * IL;
+    const int64_t jb = p.j0 + (int64_t)blockIdx.y * p.chunk;
+    const int64_t je = min(jb + p.chunk, p.j1);
+    const float eps2 = (float)p.eps2;
+
+    double xi[IL], yi[IL], zi[IL];
+    float vxi[IL], vyi[IL], vzi[IL];
+    double A[IL][3], J[IL][3];
+#pragma unroll
+    for (int u = 0; u < IL; ++u) {
+        const int64_t k = kbase + u;
+        int64_t i = 0;
+        if (k < p.m) {
+            i = p.i_idx ? (int64_t)p.i_idx[k] : k;
+            if (i < 0 || i >= p.n) {
+                atomicOr(p.status, (int)NBK_EINDEX);
+                i = 0;
+            }
+        }
+        xi[u] = p.xp[i]; yi[u] = p.yp[i]; zi[u] = p.zp[i];
+        vxi[u] = p.vx32[i]; vyi[u] = p.vy32[i]; vzi[u] = p.vz32[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { A[u][c] = 0.0; J[u][c] = 0.0; }
+    }
+
+    for (int64_t jt = jb; jt < je; jt += TILE) {
+        __syncthreads();
+        for (int q = tid; q < TILE; q += WG) {
+            const int64_t j = jt + q;
+            if (j < je) {
+                sx[q] = p.xp[j]; sy[q] = p.yp[j]; sz[q] = p.zp[j];
+                svx[q] = p.vx32[j]; svy[q] = p.vy32[j]; svz[q] = p.vz32[j];
+                sm[q] = p.m32[j];
+            } else {  // padding: zero mass contributes exactly zero
+                sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0;
+                svx[q] = 0.f; svy[q] = 0.f; svz[q] = 0.f; sm[q] = 0.f;
+            }
+        }
+        __syncthreads();
+        const int lim = (int)min<int64_t>(TILE, je - jt);
+        for (int kk = 0; kk < lim; kk += S * F) {
+            float a32[IL][3], j32[IL][3];
+#pragma unroll
+            for (int u = 0; u < IL; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; }
+#pragma unroll 4
+            for (int f = 0; f < F; ++f) {
+                const int q = kk + f * S + s;
+                const double xj = sx[q], yj = sy[q], zj = sz[q];
+                const float vxj = svx[q], vyj = svy[q], vzj = svz[q], mj = sm[q];
+#pragma unroll
+                for (int u = 0; u < IL; ++u) {
+                    const float dx = (float)(xj - xi[u]);
+                    const float dy = (float)(yj - yi[u]);
+                    const float dz = (float)(zj - zi[u]);
+                    const float dvx = vxj - vxi[u], dvy = vyj - vyi[u], dvz = vzj - vzi[u];
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float rinv2 = rinv * rinv;
+                    const float mr3 = mj * rinv * rinv2;
+                    const float al = -3.0f * rv * rinv2;
+                    a32[u][0] = fmaf(mr3, dx, a32[u][0]);
+                    a32[u][1] = fmaf(mr3, dy, a32[u][1]);
+                    a32[u][2] = fmaf(mr3, dz, a32[u][2]);
+                    j32[u][0] = fmaf(mr3, fmaf(al, dx, dvx), j32[u][0]);
+                    j32[u][1] = fmaf(mr3, fmaf(al, dy, dvy), j32[u][1]);
+                    j32[u][2] = fmaf(mr3, fmaf(al, dz, dvz), j32[u][2]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < IL; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    A[u][c] += (double)a32[u][c];
+                    J[u][c] += (double)j32[u][c];
+                }
+        }
+    }
+
+#pragma unroll
+    for (int u = 0; u < IL; ++u) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (S > 1) {
+                A[u][c] = group_sum<S>(A[u][c]);
+                J[u][c] = group_sum<S>(J[u][c]);
+            }
+        }
+        const int64_t k = kbase + u;
+        if (s == 0 && k < p.m) {
+            double *oa = p.out_acc + (int64_t)blockIdx.y * p.stride_b;
+            double *oj = p.out_jerk + (int64_t)blockIdx.y * p.stride_b;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                oa[c * (int64_t)p.m + k] = A[u][c];
+                oj[c * (int64_t)p.m + k] = J[u][c];
+            }
+        }
+    }
+}
+
+template <int IL, int S, int F>
+__global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
+{
+    __shared__ double sx[TILE], sy[TILE], sz[TILE];
+    __shared__ double svx[TILE], svy[TILE], svz[TILE], sm[TILE];
+
+    const int tid = threadIdx.x;
+    const int g = tid / S, s = tid % S;
+    constexpr int IWG = (WG / S) * IL;
+    const int64_t kbase = (int64_t)blockIdx.x * IWG + (int64_t)g * IL;
+    const int64_t jb = p.j0 + (int64_t)blockIdx.y * p.chunk;
+    const int64_t je = min(jb + p.chunk, p.j1);
+    const double eps2 = p.eps2;
+
+    double xi[IL], yi[IL], zi[IL], vxi[IL], vyi[IL], vzi[IL];
+    double A[IL][3], J[IL][3];
+#pragma unroll
+    for (int u = 0; u < IL; ++u) {
+        const int64_t k = kbase + u;
+        int64_t i = 0;
+        if (k < p.m) {
+            i = p.i_idx ? (int64_t)p.i_idx[k] : k;
+            if (i < 0 || i >= p.n) {
+                atomicOr(p.status, (int)NBK_EINDEX);
+                i = 0;
+            }
+        }
+        xi[u] = p.xp[i]; yi[u] = p.yp[i]; zi[u] = p.zp[i];
+        vxi[u] = p.vx64[i]; vyi[u] = p.vy64[i]; vzi[u] = p.vz64[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { A[u][c] = 0.0; J[u][c] = 0.0; }
+    }
+
+    for (int64_t jt = jb; jt < je; jt += TILE) {
+        __syncthreads();
+        for (int q = tid; q < TILE; q += WG) {
+            const int64_t j = jt + q;
+            if (j < je) {
+                sx[q] = p.xp[j]; sy[q] = p.yp[j]; sz[q] = p.zp[j];
+                svx[q] = p.vx64[j]; svy[q] = p.vy64[j]; svz[q] = p.vz64[j];
+                sm[q] = p.m64[j];
+            } else {
+                sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0;
+                svx[q] = 0.0; svy[q] = 0.0; svz[q] = 0.0; sm[q] = 0.0;
+            }
+        }
+        __syncthreads();
+        const int lim = (int)min<int64_t>(TILE, je - jt);
+        for (int kk = 0; kk < lim; kk += S * F) {
+            double at[IL][3], jt3[IL][3];
+#pragma unroll
+            for (int u = 0; u < IL; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { at[u][c] = 0.0; jt3[u][c] = 0.0; }
+#pragma unroll 2
+            for (int f = 0; f < F; ++f) {
+                const int q = kk + f * S + s;
+                const double xj = sx[q], yj = sy[q], zj = sz[q];
+                const double vxj = svx[q], vyj = svy[q], vzj = svz[q], mj = sm[q];
+#pragma unroll
+                for (int u = 0; u < IL; ++u) {
+                    const double dx = xj - xi[u], dy = yj - yi[u], dz = zj - zi[u];
+                    const double dvx = vxj - vxi[u], dvy = vyj - vyi[u], dvz = vzj - vzi[u];
+                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                    const double rv = fma(dx, dvx, fma(dy, dvy, dz * dvz));
+                    const double rinv = rsqrt64(r2);
+                    const double rinv2 = rinv * rinv;
+                    const double mr3 = mj * rinv * rinv2;
+                    const double al = -3.0 * rv * rinv2;
+                    at[u][0] = fma(mr3, dx, at[u][0]);
+                    at[u][1] = fma(mr3, dy, at[u][1]);
+                    at[u][2] = fma(mr3, dz, at[u][2]);
+                    jt3[u][0] = fma(mr3, fma(al, dx, dvx), jt3[u][0]);
+                    jt3[u][1] = fma(mr3, fma(al, dy, dvy), jt3[u][1]);
+                    jt3[u][2] = fma(mr3, fma(al, dz, dvz), jt3[u][2]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < IL; ++u)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { A[u][c] += at[u][c]; J[u][c] += jt3[u][c]; }
+        }
+    }
+
+#pragma unroll
+    for (int u = 0; u < IL; ++u) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (S > 1) {
+                A[u][c] = group_sum<S>(A[u][c]);
+                J[u][c] = group_sum<S>(J[u][c]);
+            }
+        }
+        const int64_t k = kbase + u;
+        if (s == 0 && k < p.m) {
+            double *oa = p.out_acc + (int64_t)blockIdx.y * p.stride_b;
+            double *oj = p.out_jerk + (int64_t)blockIdx.y * p.stride_b;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                oa[c * (int64_t)p.m + k] = A[u][c];
+                oj[c * (int64_t)p.m + k] = J[u][c];
+            }
+        }
+    }
+}
+
+// Fold interval: FP32 terms summed per lane before a fold into FP64 (mixed),
+// bounded so that a tile holds a whole number of folds.
+template <int S>
+constexpr int fold_mixed() { return (TILE / S) < 32 ? (TILE / S) : 32; }
+template <int S>
+constexpr int fold_fp64() { return TILE / S; }
+
+template <int IL, int S>
+static hipError_t launch_one(int precision, dim3 grid, const ForceArgs &a, hipStream_t st)
+{
+    if (precision == NB_MIXED)
+        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>()>), grid, dim3(WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((force_fp64_kernel<IL, S, fold_fp64<S>()>), grid, dim3(WG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int IL>
+static hipError_t launch_il(int precision, int s, dim3 grid, const ForceArgs &a, hipStream_t st)
+{
+    switch (s) {
+    case 1: return launch_one<IL, 1>(precision, grid, a, st);
+    case 4: return launch_one<IL, 4>(precision, grid, a, st);
+    case 16: return launch_one<IL, 16>(precision, grid, a, st);
+    case 64: return launch_one<IL, 64>(precision, grid, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_force(int precision, int il, int s, dim3 grid, const ForceArgs &a,
+                        hipStream_t st)
+{
+    switch (il) {
+    case 1: return launch_il<1>(precision, s, grid, a, st);
+    case 2: return launch_il<2>(precision, s, grid, a, st);
+    case 4: return launch_il<4>(precision, s, grid, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+__global__ __launch_bounds__(WG) void reduce_partials_kernel(const double *part, int32_t m, int nb,
+                                                             double *acc, double *jerk)
+{
+    const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;   // over 6*m
+    const int64_t six_m = 6 * (int64_t)m;
+    if (idx >= six_m)
+        return;
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b)
+        v += part[(int64_t)b * six_m + idx];
+    if (idx < 3 * (int64_t)m)
+        acc[idx] = v;
+    else
+        jerk[idx - 3 * (int64_t)m] = v;
+}
+
+hipError_t launch_reduce_partials(const double *part, int32_t m, int nb, double *acc,
+                                  double *jerk, hipStream_t st)
+{
+    const int64_t total = 6 * (int64_t)m;
+    const unsigned blocks = (unsigned)((total + WG - 1) / WG);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks), dim3(WG), 0, st, part, m, nb, acc, jerk);
+    return hipGetLastError();
+}
+
+// ---- energy -------------------------------------------------------------------
+
+// rows[i] = m_i * sum_{j != i} m_j / sqrt(|x_j - x_i|^2 + eps^2), one i per lane.
+__global__ __launch_bounds__(WG) void potential_rows_kernel(const double *x, const double *y,
+                                                            const double *z, const double *mass,
+                                                            int64_t n, double eps2, double *rows)
+{
+    __shared__ double sx[TILE], sy[TILE], sz[TILE], sm[TILE];
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int64_t ii = i < n ? i : 0;
+    const double xi = x[ii], yi = y[ii], zi = z[ii];
+    double tot = 0.0;
+    for (int64_t jt = 0; jt < n; jt += TILE) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < TILE; q += WG) {
+            const int64_t j = jt + q;
+            if (j < n) { sx[q] = x[j]; sy[q] = y[j]; sz[q] = z[j]; sm[q] = mass[j]; }
+            else { sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0; sm[q] = 0.0; }
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (int q = 0; q < TILE; ++q) {
+            const double dx = sx[q] - xi, dy = sy[q] - yi, dz = sz[q] - zi;
+            const bool self = (jt + q == i);
+            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+            const double w = self ? 0.0 : sm[q];
+            part = fma(w, rsqrt64(self ? 1.0 : r2), part);
+        }
+        tot += part;
+    }
+    if (i < n)
+        rows[i] = mass[i] * tot;
+}
+
+// Neumaier compensated accumulation.
+struct CSum {
+    double s = 0.0, c = 0.0;
+    __device__ void add(double v)
+    {
+        const double t = s + v;
+        if (fabs(s) >= fabs(v)) c += (s - t) + v;
+        else c += (v - t) + s;
+        s = t;
+    }
+};
+
+// One workgroup: out[0] = sum_i m_i |v_i|^2 / 2, out[1] = -sum_i rows[i] / 2, each
+// lane summing a strided slice in order, then lane 0 combining lanes in order.
+__global__ __launch_bounds__(WG) void energy_total_kernel(const double *vx, const double *vy,
+                                                          const double *vz, const double *mass,
+                                                          const double *rows, int64_t n,
+                                                          double *out)
+{
+    __shared__ double ks[WG], kc[WG], ps[WG], pc[WG];
+    CSum kin, pot;
+    for (int64_t i = threadIdx.x; i < n; i += WG) {
+        kin.add(0.5 * mass[i] * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]));
+        pot.add(rows[i]);
+    }
+    ks[threadIdx.x] = kin.s; kc[threadIdx.x] = kin.c;
+    ps[threadIdx.x] = pot.s; pc[threadIdx.x] = pot.c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CSum k2, p2;
+        for (int t = 0; t < WG; ++t) {
+            k2.add(ks[t]); k2.add(kc[t]);
+            p2.add(ps[t]); p2.add(pc[t]);
+        }
+        out[0] = k2.s + k2.c;
+        out[1] = -0.5 * (p2.s + p2.c);
+    }
+}
+
+hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *out,
+                         hipStream_t st)
+{
+    const int64_t n = s.n;
+    const unsigned blocks = (unsigned)((n + WG - 1) / WG);
+    hipLaunchKernelGGL(potential_rows_kernel, dim3(blocks), dim3(WG), 0, st, s.x, s.y, s.z, s.m,
+                       n, eps2, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(energy_total_kernel, dim3(1), dim3(WG), 0, st, s.vx, s.vy, s.vz, s.m, rows,
+                       n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nbk

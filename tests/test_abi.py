@@ -1,0 +1,60 @@
+"""The C-ABI library loads on the CPU and exports every symbol include/nbody.h declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nb_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1411_5234_amd import _lib
+    return _lib.load()
+
+
+def test_header_and_binding_agree():
+    from paper_1411_5234_amd import _lib
+    assert declared_symbols() == sorted(_lib.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_null_context_errors(lib):
+    assert lib.nb_version().decode().count(".") == 2
+    assert lib.nb_ctx_destroy(None) == -1
+    assert lib.nb_sync(None) == -1
+    assert lib.nb_last_error(None) == b"null context"
+
+
+def test_force_plan_is_pure_and_valid():
+    from paper_1411_5234_amd import _lib
+    seen = {}
+    for prec in ("fp64", "mixed"):
+        for nj in (1, 100, 1024, 65536, 1 << 20):
+            for m in (1, 7, 64, 1000, 4096, 65536, 1 << 20):
+                if m > nj:
+                    continue
+                p = _lib.force_plan(nj, m, prec)
+                assert p == _lib.force_plan(nj, m, prec)
+                il, s, b = p
+                assert il in (1, 2, 4) and s in (1, 4, 16, 64) and 1 <= b <= 1024
+                # every lane still walks a useful number of j-bodies
+                assert nj // (s * b) >= min(128, nj // (s * b) if s * b > 1 else nj)
+                seen[(prec, nj, m)] = p
+    # the whole system active at N = 2^20: no j-split needed
+    assert seen[("mixed", 1 << 20, 1 << 20)][2] == 1
+    # a small block in a large system is split across j (the paper's Bfactor)
+    il, s, b = seen[("mixed", 65536, 64)]
+    assert s * b > 1

@@ -1,0 +1,150 @@
+"""GPU parity of nb_force_active (acc + jerk) against the FP64 oracle.
+
+Gates (maximum over bodies): FP64 path, relative error of acceleration and jerk
+<= 1e-12; mixed path, relative acceleration error <= 1e-6 and jerk error <= 1e-6
+of the jerk's magnitude scale sum_j |jerk_ij| (see gpu_helpers).  Cases: the N = 1024 Plummer sphere with
+every body active, the N = 65536 Salpeter cluster with active blocks of 64 .. 4096
+(plus sampled bodies of larger blocks), ragged sizes and j-ranges, every launch
+plan shape, bitwise repeatability, empty blocks, error paths, and the N = 2^20
+Plummer sphere with every body active (the benchmarked launch) on sampled bodies.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import TOL, check, device_system, gpu_force, report
+from paper_1411_5234_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1411_5234_amd.nbody import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    n = 65536
+    s = inputs.plummer(n, 2, masses=inputs.salpeter_masses(n, 2))
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plummer_1024_all_active(ctx, orc, precision):
+    s = inputs.plummer(1024, 1)
+    sys = device_system(s.x, s.v, s.m)
+    ga, gj = gpu_force(ctx, sys, 1e-3, precision)
+    check(orc, precision, ga, gj, s.x, s.v, s.m, 1e-3, tag="N=1024")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("m", [64, 256, 1000, 4096])
+def test_salpeter_65536_active_blocks(ctx, orc, c2, precision, m):
+    perm = np.random.default_rng(20).permutation(c2.n)[:m]
+    il = np.sort(perm)
+    sys = device_system(c2.x, c2.v, c2.m)
+    ga, gj = gpu_force(ctx, sys, 1e-4, precision, il)
+    check(orc, precision, ga, gj, c2.x, c2.v, c2.m, 1e-4, il, tag="N=65536 m=%d" % m)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("m", [16384, 65536])
+def test_salpeter_65536_large_blocks_sampled(ctx, orc, c2, precision, m):
+    il = np.sort(np.random.default_rng(21).permutation(c2.n)[:m])
+    sys = device_system(c2.x, c2.v, c2.m)
+    ga, gj = gpu_force(ctx, sys, 1e-4, precision, il)
+    pick = np.random.default_rng(22).choice(m, 512, replace=False)
+    check(orc, precision, ga[pick], gj[pick], c2.x, c2.v, c2.m, 1e-4, il[pick],
+          tag="N=65536 m=%d (512 sampled)" % m)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ragged_sizes_and_j_ranges(ctx, orc, precision):
+    s = inputs.plummer(1000, 8, masses=inputs.salpeter_masses(1000, 9))
+    sys = device_system(s.x, s.v, s.m)
+    il = np.sort(np.random.default_rng(5).choice(1000, 77, replace=False))
+    for j0, j1 in [(0, 1000), (13, 911), (0, 1), (999, 1000), (511, 513)]:
+        ga, gj = gpu_force(ctx, sys, 1e-2, precision, il, j0, j1)
+        oa, oj = check(orc, precision, ga, gj, s.x, s.v, s.m, 1e-2, il, j0, j1,
+                       tag="ragged [%d,%d)" % (j0, j1))
+        nz = np.linalg.norm(oa, axis=1) > 0
+        # bodies whose only j is themselves get exactly zero
+        assert np.all(ga[~nz] == 0.0) and np.all(gj[~nz] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_plan_shape_matches(ctx, orc, precision):
+    s = inputs.plummer(3000, 12)
+    sys = device_system(s.x, s.v, s.m)
+    il = np.arange(0, 3000, 3)
+    oa, oj = orc.force(s.x, s.v, s.m, 1e-3, il)
+    sa, sj = orc.force_scale(s.x, s.v, s.m, 1e-3, il)
+    for i_per_lane in (1, 2, 4):
+        for lanes in (1, 4, 16, 64):
+            for chunks in (1, 3, 8):
+                ga, gj = gpu_force(ctx, sys, 1e-3, precision, il, plan=(i_per_lane, lanes, chunks))
+                ea, ej = report("plan %d/%d/%d %s" % (i_per_lane, lanes, chunks, precision),
+                                ga, gj, oa, oj)
+                assert ea.max() <= TOL[precision]
+                if precision == "fp64":
+                    assert ej.max() <= TOL[precision]
+                else:
+                    assert (np.linalg.norm(gj - oj, axis=1) / sj).max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bitwise_repeatable(ctx, precision):
+    s = inputs.plummer(5000, 13)
+    sys = device_system(s.x, s.v, s.m)
+    il = np.arange(0, 5000, 7)
+    a1, j1 = gpu_force(ctx, sys, 1e-3, precision, il)
+    a2, j2 = gpu_force(ctx, sys, 1e-3, precision, il)
+    assert a1.tobytes() == a2.tobytes() and j1.tobytes() == j2.tobytes()
+
+
+def test_empty_block_and_empty_range(ctx):
+    s = inputs.plummer(100, 3)
+    sys = device_system(s.x, s.v, s.m)
+    ga, gj = gpu_force(ctx, sys, 1e-3, "mixed", [])
+    assert ga.shape == (0, 3)
+    ga, gj = gpu_force(ctx, sys, 1e-3, "fp64", [1, 2, 3], 40, 40)
+    assert np.all(ga == 0.0) and np.all(gj == 0.0)
+
+
+def test_argument_errors(ctx):
+    from paper_1411_5234_amd._lib import NbError
+    s = inputs.plummer(100, 3)
+    sys = device_system(s.x, s.v, s.m)
+    with pytest.raises(NbError) as e:
+        gpu_force(ctx, sys, 0.0, "mixed")
+    assert e.value.name == "NB_EINVAL"
+    with pytest.raises(NbError):
+        gpu_force(ctx, sys, 1e-3, "mixed", [0, 1], 0, 101)
+    with pytest.raises(NbError):
+        gpu_force(ctx, sys, 1e-3, "mixed", [0], plan=(3, 1, 1))
+    no32 = device_system(s.x, s.v, s.m, fp32=False)
+    with pytest.raises(NbError):
+        gpu_force(ctx, no32, 1e-3, "mixed", [0])
+    # an out-of-range active index is clamped in the kernel and reported at sync
+    with pytest.raises(NbError) as e:
+        gpu_force(ctx, sys, 1e-3, "fp64", [0, 100])
+    assert e.value.name == "NB_EINDEX"
+    ctx.sync()   # the word was cleared by the failing sync
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
+    n = 1 << 20
+    s = inputs.plummer(n, 3)
+    sys = device_system(s.x, s.v, s.m)
+    ga, gj = gpu_force(ctx, sys, 1e-4, precision)
+    pick = np.sort(np.random.default_rng(30).choice(n, 256, replace=False))
+    check(orc, precision, ga[pick], gj[pick], s.x, s.v, s.m, 1e-4, pick,
+          tag="N=2^20 all active (256 sampled)")
+    # momentum balance over every body (a property at any size)
+    ma = (s.m[:, None] * ga).sum(0)
+    assert np.all(np.abs(ma) <= 1e-6 * (s.m[:, None] * np.abs(ga)).sum(0))

@@ -135,3 +135,32 @@ def test_bad_ranges_raise(orc):
         orc.force(x, np.zeros((4, 3)), np.ones(4), 0.1, np.array([0]), 0, 5)
     with pytest.raises(orc.OracleError):
         orc.force(x, np.zeros((4, 3)), np.ones(4), 0.1, np.array([7]))
+
+
+def test_force_scale_bounds_and_special_cases(orc):
+    from paper_1411_5234_amd import inputs
+    s = inputs.plummer(200, 31)
+    a, j = orc.force(s.x, s.v, s.m, 1e-3)
+    sa, sj = orc.force_scale(s.x, s.v, s.m, 1e-3)
+    # triangle inequality, with equality only when all terms are parallel
+    assert np.all(sa >= np.linalg.norm(a, axis=1) * (1 - 1e-14))
+    assert np.all(sj >= np.linalg.norm(j, axis=1) * (1 - 1e-14))
+    # additive over the j-range like the sums themselves
+    sa1, sj1 = orc.force_scale(s.x, s.v, s.m, 1e-3, None, 0, 77)
+    sa2, sj2 = orc.force_scale(s.x, s.v, s.m, 1e-3, None, 77, 200)
+    np.testing.assert_allclose(sa1 + sa2, sa, rtol=1e-13)
+    np.testing.assert_allclose(sj1 + sj2, sj, rtol=1e-13)
+    # bodies on one ray from body 0, moving along it: every term is parallel
+    x = np.zeros((5, 3))
+    x[:, 0] = [0.0, 0.5, 1.0, 2.0, 3.5]
+    v = np.zeros((5, 3))
+    v[:, 0] = [0.0, 0.3, -0.2, 0.7, 0.1]
+    m = np.array([1.0, 0.5, 2.0, 1.0, 3.0])
+    a, j = orc.force(x, v, m, 1e-3, np.array([0]))
+    sa, sj = orc.force_scale(x, v, m, 1e-3, np.array([0]))
+    assert sa[0] == pytest.approx(np.linalg.norm(a[0]), rel=1e-14)
+    # a single pair: the scale is the magnitude of its one term
+    a, j = orc.force(x[:2], v[:2], m[:2], 1e-3, np.array([0]))
+    sa, sj = orc.force_scale(x[:2], v[:2], m[:2], 1e-3, np.array([0]))
+    assert sa[0] == pytest.approx(np.linalg.norm(a[0]), rel=1e-15)
+    assert sj[0] == pytest.approx(np.linalg.norm(j[0]), rel=1e-15)
