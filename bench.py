@@ -45,6 +45,16 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve"], default="step",
+                    help="step: the headline (default); sweep: active-block sizes 2^6..2^16 at "
+                         "N=65536 (Salpeter), FP64 vs mixed, planned j-split vs none; integrate: "
+                         "block-step integration of the N=2^20 Plummer sphere to t_end with energy "
+                         "drift; serve: Poisson request stream through the continuous-batching server")
+    ap.add_argument("--t-end", type=float, default=0.125)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--baseline-requests", type=int, default=32)
     return ap.parse_args()
 
 
@@ -55,6 +65,12 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.mode == "sweep":
+        return mode_sweep(args)
+    if args.mode == "integrate":
+        return mode_integrate(args)
+    if args.mode == "serve":
+        return mode_serve(args)
 
     import numpy as np
     import torch
@@ -136,17 +152,19 @@ def main():
         tc = time.perf_counter()
         oa, oj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, il)
         tcpu = time.perf_counter() - tc
-        ga = it.acc.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
-        gj = it.jerk.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
-        ea = np.linalg.norm(ga - oa, axis=1) / np.linalg.norm(oa, axis=1)
-        ej = np.linalg.norm(gj - oj, axis=1) / np.linalg.norm(oj, axis=1)
         cpu = {"value": k * n / tcpu, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": "acc+jerk of the first %d bodies against all %d predicted bodies (FP64, "
                          "compensated sums), %.1f s" % (k, n, tcpu)}
-        extra["error_vs_oracle_sample"] = {
-            "bodies": k, "acc_rel_max": float(ea.max()), "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
-            "jerk_rel_max": float(ej.max()), "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
+        if ms[-1] == n:   # the last block was the whole system, in index order
+            ga = it.acc.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
+            gj = it.jerk.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
+            ea = np.linalg.norm(ga - oa, axis=1) / np.linalg.norm(oa, axis=1)
+            ej = np.linalg.norm(gj - oj, axis=1) / np.linalg.norm(oj, axis=1)
+            extra["error_vs_oracle_sample"] = {
+                "bodies": k, "acc_rel_max": float(ea.max()),
+                "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
+                "jerk_rel_max": float(ej.max()), "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
 
     out = {
         "metric": METRIC,
@@ -175,6 +193,165 @@ def main():
     }
     out.update(extra)
     ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def _timed_force(ctx, system, idx, m, eps, precision, acc, jerk, plan=None, reps=5):
+    import torch
+    ctx.force_active(system, idx, m, 0, system.n, eps, precision, acc, jerk, plan)
+    ctx.sync()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.force_active(system, idx, m, 0, system.n, eps, precision, acc, jerk, plan)
+        e1.record(ctx.stream)
+        ctx.sync()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    return best
+
+
+def mode_sweep(args):
+    """Active-block sweep (the paper's Fig. 1 analogue): N = 65536 Salpeter cluster,
+    eps = 1e-4, m = 2^6 .. 2^16 bodies (first m of a seeded permutation)."""
+    import numpy as np
+    import torch
+
+    from paper_1411_5234_amd import _lib, inputs
+    from paper_1411_5234_amd.nbody import Context, System
+    n = 65536
+    snap = inputs.plummer(n, 2, masses=inputs.salpeter_masses(n, 2))
+    ctx = Context(0)
+    system = System.from_arrays(snap.x, snap.v, snap.m)
+    perm = np.random.default_rng(20).permutation(n)
+    acc = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    jerk = torch.empty_like(acc)
+    rows = []
+    for k in range(6, 17):
+        m = 1 << k
+        idx = torch.as_tensor(np.sort(perm[:m]).astype(np.int32), device="cuda")
+        for prec in ("mixed", "fp64"):
+            planned = _lib.force_plan(n, m, prec)
+            t_plan = _timed_force(ctx, system, idx, m, 1e-4, prec, acc, jerk)
+            t_one = _timed_force(ctx, system, idx, m, 1e-4, prec, acc, jerk, plan=(planned[0], 1, 1))
+            rows.append({"m": m, "precision": prec, "plan": list(planned),
+                         "interactions_per_s": m * n / t_plan,
+                         "interactions_per_s_no_split": m * n / t_one,
+                         "us": t_plan * 1e6, "us_no_split": t_one * 1e6})
+            print("m=%6d %-5s plan %-12s %.3e int/s (%.1f us)   no split %.3e int/s (%.1f us)"
+                  % (m, prec, planned, m * n / t_plan, t_plan * 1e6, m * n / t_one, t_one * 1e6),
+                  file=sys.stderr, flush=True)
+    ctx.close()
+    print(json.dumps({"metric": "pair-interactions/s vs active-block size (N=65536 Salpeter)",
+                      "mode": "sweep", "rows": rows}), flush=True)
+
+
+def mode_integrate(args):
+    """Block-step Hermite-4 integration of the N=2^20 Plummer sphere to t_end."""
+    import torch
+
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.nbody import Context, Integrator, Params, System
+    n = args.n
+    snap = inputs.plummer(n, args.seed)
+    ctx = Context(0)
+    system = System.from_arrays(snap.x, snap.v, snap.m)
+    p = Params(eps=args.eps, precision=args.precision)
+    it = Integrator(ctx, system, p)
+    E0 = ctx.energy(system, args.eps)[2]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it.startup()
+    last = [time.perf_counter()]
+
+    def progress(step_t, m):
+        now = time.perf_counter()
+        if now - last[0] > 10:
+            last[0] = now
+            print("t=%.6f steps=%d interactions=%.3e wall=%.1fs" % (step_t, it.steps, it.interactions,
+                                                                   now - t0), file=sys.stderr, flush=True)
+
+    while True:
+        t_next, m = ctx.select_active(system, it.i_idx)
+        if t_next > args.t_end:
+            break
+        it._advance(t_next, m)
+        progress(t_next, m)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    E1 = ctx.energy(system, args.eps)[2]
+    ctx.close()
+    out = {"metric": "pair-interactions/s over a block-step integration", "mode": "integrate",
+           "value": it.interactions / wall, "unit": "pair-interactions/s",
+           "config": {"workload": "plummer_n%d_eps%g_%s_to_t%g" % (n, args.eps, args.precision, args.t_end),
+                      "n": n, "eps": args.eps, "precision": args.precision, "t_end": args.t_end,
+                      "eta": p.eta, "eta_s": p.eta_s, "dt_max": p.dt_max},
+           "block_steps": it.steps, "interactions": it.interactions, "wall_s": wall,
+           "energy0": E0, "energy1": E1, "energy_drift": abs(E1 - E0) / abs(E0)}
+    print(json.dumps(out), flush=True)
+
+
+def mode_serve(args):
+    """Serve a Poisson stream through the continuous-batching server.
+
+    c4: equal-mass Plummer clusters, N log-uniform in [256, 32768], eps = 1e-3, to
+    t = 1.  c5: Kroupa IMF with 10% binaries, N log-uniform in [1024, 65536],
+    eps = 1e-5, to t = 1/8.  The stream is first served as a closed batch to
+    measure saturated throughput, then replayed in real time with arrivals at
+    0.8 x that rate; a one-at-a-time FP64 baseline serves the first
+    --baseline-requests requests alone, one after another."""
+    import numpy as np
+
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.nbody import Context
+    from paper_1411_5234_amd.serve import Server, summarize
+    if args.stream == "c4":
+        spec = dict(n_lo=256, n_hi=32768, eps=1e-3, t_end=1.0, kind="plummer", seed=4, base=4000)
+    else:
+        spec = dict(n_lo=1024, n_hi=65536, eps=1e-5, t_end=0.125, kind="kroupa_binaries", seed=5,
+                    base=5000)
+
+    def stream(rate, count):
+        return inputs.request_stream(count, spec["seed"], spec["n_lo"], spec["n_hi"], rate=rate,
+                                     eps=spec["eps"], t_end=spec["t_end"], kind=spec["kind"],
+                                     ic_seed_base=spec["base"])
+
+    ctx = Context(0)
+    out = {"metric": "ensemble solves/s and p50/p99 latency", "mode": "serve",
+           "config": {"workload": args.stream, "requests": args.requests, "slots": args.slots,
+                      "precision": args.precision, **{k: v for k, v in spec.items() if k != "base"}}}
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+    t0 = time.perf_counter()
+    res = srv.run(stream(0.0, args.requests), realtime=False)
+    closed = summarize(res, time.perf_counter() - t0)
+    out["closed_batch"] = closed
+    print("closed batch: %s" % closed, file=sys.stderr, flush=True)
+    rate = 0.8 * closed["solves_per_s"]
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+    t0 = time.perf_counter()
+    res = srv.run(stream(rate, args.requests), realtime=True)
+    poisson = summarize(res, time.perf_counter() - t0)
+    poisson["arrival_rate_per_s"] = rate
+    out["poisson"] = poisson
+    print("poisson at %.2f/s: %s" % (rate, poisson), file=sys.stderr, flush=True)
+    k = min(args.baseline_requests, args.requests)
+    if k > 0:
+        srv = Server(ctx, precision="fp64", max_slots=1, energy=True)
+        t0 = time.perf_counter()
+        res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
+        base = summarize(res, time.perf_counter() - t0)
+        base["requests_served"] = k
+        out["one_at_a_time_fp64"] = base
+        print("one at a time fp64: %s" % base, file=sys.stderr, flush=True)
+        # the same k requests through the batched server, for a like-for-like rate
+        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+        t0 = time.perf_counter()
+        res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
+        out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
+    ctx.close()
+    out["value"] = poisson["solves_per_s"]
+    out["unit"] = "solves/s"
     print(json.dumps(out), flush=True)
 
 

@@ -159,6 +159,45 @@ nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t 
                                int32_t lanes_per_i, int32_t j_chunks,
                                double *acc, double *jerk);
 
+/* ---- ragged batches: many independent systems in one launch per phase -------
+ * Ensemble serving advances many systems of different n together.  Each batch
+ * call runs ONE launch per phase (per plan shape for the force) over all items,
+ * with every workgroup working for exactly one item.  Each item is computed
+ * with the same kernels, the same launch plan (a pure function of its own n and
+ * m) and the same arithmetic as the single-system calls above, which are
+ * themselves batches of one, so a system's results are bitwise the same alone
+ * and in any mix.  The block-step parameters (eta, eta_s, dt_max, dt_min) are
+ * shared by the items of a call.  An item whose status word is non-NULL gets its
+ * own kernel error bits there (device int, owned by the caller); otherwise the
+ * context's word is used. */
+typedef struct {
+    nb_system sys;       /* the system's device arrays                              */
+    int32_t *i_idx;      /* device, capacity sys.n: the active list                  */
+    double *acc, *jerk;  /* device, capacity 3*sys.n each (SoA with stride m)        */
+    int32_t *status;     /* device word for this item's kernel errors, or NULL       */
+    double eps;          /* Plummer softening, > 0                                   */
+    double t_next;       /* block time: set by nb_select_active_batch                */
+    int32_t m;           /* active block size: set by nb_select_active_batch         */
+    int32_t startup;     /* 1: the t = 0 step (all bodies active, no selection)      */
+    int32_t error;       /* host: nb_status of this item's latched errors, set by
+                            nb_select_active_batch (the item's word is then cleared) */
+    int32_t reserved;
+} nb_batch_item;
+
+/* a1 for every item (Sec. 2 item 2).  Startup items get m = n, t_next = 0 and no
+ * device work.  Waits for the stream; fills t_next, m and error of every item. */
+nb_status nb_select_active_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items);
+/* a2 for every non-startup item, each to its own t_next (Sec. 2 item 2). */
+nb_status nb_predict_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items);
+/* a3 + a4 for every item: acc/jerk of its m active bodies (all n for startup
+ * items, i = k) from its whole predicted j-set (Eq. 1-2, Sec. 2 items 3-5). */
+nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
+                                nb_precision precision);
+/* a5 for every non-startup item (Sec. 2 items 1-2); the startup step of
+ * nb_init_steps for startup items. */
+nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
+                           double eta, double eta_s, double dt_max, double dt_min);
+
 /* Library version string. */
 const char *nb_version(void);
 

@@ -133,20 +133,19 @@ int orc_force_scale(int64_t n, const double *x, const double *v, const double *m
         for (int64_t j = j0; j < j1; j++) {
             if (j == i)
                 continue;
-            double r[3], w[3], ja[3];
+            double dr[3], dw[3], term[3];
             for (int d = 0; d < 3; d++) {
-                r[d] = x[3 * j + d] - x[3 * i + d];
-                w[d] = v[3 * j + d] - v[3 * i + d];
+                dr[d] = x[3 * j + d] - x[3 * i + d];
+                dw[d] = v[3 * j + d] - v[3 * i + d];
             }
-            const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
-            const double rinv = 1.0 / sqrt(s);
-            const double mu = m[j] * rinv * rinv * rinv;
-            const double rw = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
-            const double alpha = 3.0 * rw * rinv * rinv;
+            const double d2 = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2];
+            const double q = 1.0 / sqrt(d2 + eps2);                /* s^(-1/2) */
+            const double mq3 = m[j] * q * q * q;                    /* m_j s^(-3/2) */
+            const double radial = 3.0 * (dr[0] * dw[0] + dr[1] * dw[1] + dr[2] * dw[2]) * q * q;
             for (int d = 0; d < 3; d++)
-                ja[d] = mu * (w[d] - alpha * r[d]);
-            cs_add(&ta, mu * sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]));
-            cs_add(&tj, sqrt(ja[0] * ja[0] + ja[1] * ja[1] + ja[2] * ja[2]));
+                term[d] = mq3 * (dw[d] - radial * dr[d]);
+            cs_add(&ta, mq3 * sqrt(d2));
+            cs_add(&tj, sqrt(term[0] * term[0] + term[1] * term[1] + term[2] * term[2]));
         }
         sa[k] = cs_val(&ta);
         sj[k] = cs_val(&tj);

@@ -26,11 +26,19 @@ STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
 # Every symbol include/nbody.h declares.
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
-           "nb_force_plan", "nb_force_active_plan", "nb_version"]
+           "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
+           "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch"]
 
 
 class NbSystem(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in FIELDS64 + FIELDS32]
+
+
+class NbBatchItem(C.Structure):
+    _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("acc", C.c_void_p),
+                ("jerk", C.c_void_p), ("status", C.c_void_p), ("eps", C.c_double),
+                ("t_next", C.c_double), ("m", C.c_int32), ("startup", C.c_int32),
+                ("error", C.c_int32), ("reserved", C.c_int32)]
 
 
 class NbError(RuntimeError):
@@ -69,6 +77,10 @@ def load() -> C.CDLL:
         "nb_correct": (C.c_int, [vp, ps, vp, i32, vp, vp, f64, f64, f64, f64]),
         "nb_energy": (C.c_int, [vp, ps, f64, C.POINTER(f64), C.POINTER(f64)]),
         "nb_version": (C.c_char_p, []),
+        "nb_select_active_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32]),
+        "nb_predict_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32]),
+        "nb_force_active_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, C.c_int]),
+        "nb_correct_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, f64, f64, f64, f64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

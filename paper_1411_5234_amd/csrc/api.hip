@@ -1,15 +1,24 @@
 // C ABI of libnbody.so: argument checking, context and scratch management, the
-// force launch plan, and dispatch to the kernels.  See include/nbody.h for the
-// contract of every entry point.
+// force launch plan, item tables, and dispatch to the kernels.  See
+// include/nbody.h for the contract of every entry point.
 #include <math.h>
 #include <stdarg.h>
 #include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <utility>
+#include <vector>
+
 #include "nb_internal.h"
 
-#define NB_VERSION "0.1.0"
+#define NB_VERSION "0.2.0"
+
+using nbk::Item;
+using nbk::SelResult;
+using nbk::Table;
 
 namespace {
 
@@ -31,10 +40,16 @@ nb_status hip_fail(nb_ctx *ctx, hipError_t e, const char *what)
     return fail(ctx, NB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define NB_HIP(ctx, call)                                     \
-    do {                                                      \
-        hipError_t e_ = (call);                               \
+#define NB_HIP(ctx, call)                                      \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+#define NB_TRY(call)                    \
+    do {                                \
+        nb_status s_ = (call);          \
+        if (s_ != NB_OK) return s_;     \
     } while (0)
 
 nb_status check_system(nb_ctx *ctx, const nb_system *s, bool need_pred)
@@ -55,27 +70,105 @@ nb_status check_system(nb_ctx *ctx, const nb_system *s, bool need_pred)
     return NB_OK;
 }
 
-nb_status ensure_scratch(nb_ctx *ctx, size_t bytes)
+// Grow a device buffer to at least `bytes` (waits for the stream before freeing).
+nb_status grow(nb_ctx *ctx, void **buf, size_t *have, size_t bytes, const char *what)
 {
-    if (bytes <= ctx->scratch_bytes) return NB_OK;
+    if (bytes <= *have) return NB_OK;
     NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->scratch) {
-        NB_HIP(ctx, hipFree(ctx->scratch));
-        ctx->scratch = nullptr;
-        ctx->scratch_bytes = 0;
+    if (*buf) {
+        NB_HIP(ctx, hipFree(*buf));
+        *buf = nullptr;
+        *have = 0;
     }
-    size_t want = bytes + bytes / 4;
-    if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
-        ctx->scratch = nullptr;
+    const size_t want = bytes + bytes / 4 + 256;
+    if (hipMalloc(buf, want) != hipSuccess) {
+        *buf = nullptr;
         (void)hipGetLastError();
-        return fail(ctx, NB_ENOMEM, "scratch allocation of %zu bytes failed", want);
+        return fail(ctx, NB_ENOMEM, "%s: allocation of %zu bytes failed", what, want);
     }
-    ctx->scratch_bytes = want;
+    *have = want;
     return NB_OK;
 }
 
-// Convert and clear the latched status word (the caller has synchronised and
-// copied the word to the pinned mirror).
+nb_status ensure_res(nb_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->res_bytes) return NB_OK;
+    size_t have = ctx->res_bytes;
+    NB_TRY(grow(ctx, &ctx->res, &have, bytes, "selection results"));
+    if (ctx->res_host) (void)hipHostFree(ctx->res_host);
+    ctx->res_host = nullptr;
+    if (hipHostMalloc(&ctx->res_host, have, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->res_bytes = 0;
+        return fail(ctx, NB_ENOMEM, "pinned selection results");
+    }
+    ctx->res_bytes = have;
+    return NB_OK;
+}
+
+// Copy `bytes` of host data into the pinned ring and enqueue its upload to the
+// device ring; returns the device address.  Regions are reused only after the
+// stream has drained (a wrap waits for the stream), so an upload is never
+// overwritten before the copy and the kernels that read it have run.
+nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
+{
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (need > ctx->stage_bytes) {
+        NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
+        if (ctx->stage_dev) (void)hipFree(ctx->stage_dev);
+        ctx->stage_host = nullptr;
+        ctx->stage_dev = nullptr;
+        const size_t want = std::max(need * 2, (size_t)8 << 20);
+        if (hipHostMalloc((void **)&ctx->stage_host, want, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&ctx->stage_dev, want) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->stage_bytes = 0;
+            return fail(ctx, NB_ENOMEM, "item table staging");
+        }
+        ctx->stage_bytes = want;
+        ctx->stage_off = 0;
+    }
+    if (ctx->stage_off + need > ctx->stage_bytes) {
+        NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->stage_off = 0;
+    }
+    memcpy(ctx->stage_host + ctx->stage_off, src, bytes);
+    NB_HIP(ctx, hipMemcpyAsync(ctx->stage_dev + ctx->stage_off, ctx->stage_host + ctx->stage_off,
+                               bytes, hipMemcpyHostToDevice, ctx->stream));
+    *dev = ctx->stage_dev + ctx->stage_off;
+    ctx->stage_off += need;
+    return NB_OK;
+}
+
+// Upload the items with a positive workgroup count and their offsets.
+nb_status make_table(nb_ctx *ctx, const std::vector<Item> &items,
+                     const std::vector<int64_t> &blocks, Table *t)
+{
+    std::vector<Item> keep;
+    std::vector<int64_t> starts;
+    int64_t total = 0;
+    for (size_t k = 0; k < items.size(); ++k) {
+        if (blocks[k] <= 0) continue;
+        keep.push_back(items[k]);
+        starts.push_back(total);
+        total += blocks[k];
+    }
+    starts.push_back(total);
+    t->n = (int)keep.size();
+    t->blocks = total;
+    t->items = nullptr;
+    t->starts = nullptr;
+    if (total == 0) return NB_OK;
+    if (total > (int64_t)INT32_MAX) return fail(ctx, NB_EINVAL, "launch too large");
+    const void *d = nullptr;
+    NB_TRY(upload(ctx, keep.data(), keep.size() * sizeof(Item), &d));
+    t->items = (const Item *)d;
+    NB_TRY(upload(ctx, starts.data(), starts.size() * sizeof(int64_t), &d));
+    t->starts = (const int64_t *)d;
+    return NB_OK;
+}
+
 nb_status take_status(nb_ctx *ctx, int word)
 {
     if (word == 0) return NB_OK;
@@ -84,102 +177,261 @@ nb_status take_status(nb_ctx *ctx, int word)
     return fail(ctx, NB_ERANGE, "a time step fell below dt_min");
 }
 
-// Copy the first `bytes` of the small device area to the pinned mirror, clear the
-// status word, wait, and convert the status.
-nb_status sync_small(nb_ctx *ctx, size_t bytes)
+nb_status status_code(int word)
 {
-    NB_HIP(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, bytes, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    NB_HIP(ctx, hipMemsetAsync(&ctx->small->status, 0, sizeof(int), ctx->stream));
-    NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return take_status(ctx, ctx->small_host->status);
+    if (word == 0) return NB_OK;
+    if (word & NBK_EINDEX) return NB_EINDEX;
+    if (word & NBK_ENAN) return NB_ENAN;
+    return NB_ERANGE;
 }
+
+Item base_item(nb_ctx *ctx, const nb_system &s)
+{
+    Item it;
+    memset(&it, 0, sizeof it);
+    it.s = s;
+    it.status = &ctx->small->status;
+    it.b = 1;
+    return it;
+}
+
+// ---- force -------------------------------------------------------------------
 
 struct Plan {
     int il, s, b;
 };
 
-// Launch plan: enough lanes to fill 256 CUs (about 2^18 lane slots: 4 waves of
-// 64 lanes on each of 4 SIMDs per CU) while every lane still walks at least
-// 128 j-bodies, so the fixed cost of the final reduction stays small.  Large
-// mixed-precision blocks hold two i-bodies per lane to halve LDS traffic per
-// interaction.  Pure function of (nj, m, precision).
+// Launch plan.  A wave64 lane holds IL i-bodies; S lanes share them; the j-range
+// is split into B chunks (the paper's Bfactor).  The plan
+//  - uses S > 1 only as far as needed to fill a workgroup's lanes when the
+//    active block is small (S = 1 keeps the LDS reads broadcasts);
+//  - splits j into B chunks while the grid has fewer than about 2^20 lanes --
+//    four times the lanes the force kernels keep resident on 256 CUs, so the
+//    last round of workgroups is a small part of the run -- keeping at least
+//    2048 j-bodies per chunk, so the FP64 partial sums (48 B per body and
+//    chunk) stay a few per cent of the pair work;
+//  - then raises S while lanes are still short and every lane keeps at least
+//    128 j-bodies.
+// Large mixed-precision blocks hold two i-bodies per lane (half the LDS reads
+// per interaction).  Pure function of (nj, m, precision): a system's results
+// never depend on what else runs.
 Plan make_plan(int64_t nj, int32_t m, int precision)
 {
-    const int64_t target_lanes = (int64_t)1 << 18;
-    const int64_t min_j = 128;
+    const int64_t target_lanes = (int64_t)1 << 20;
+    const int64_t min_j_lane = 128, min_j_chunk = 2048;
     Plan p{(precision == NB_MIXED && m >= (1 << 16)) ? 2 : 1, 1, 1};
     if (m <= 0 || nj <= 0) return p;
-    int64_t lanes = (m + p.il - 1) / p.il;
-    while (p.s < 64 && lanes * p.s < target_lanes && nj / (p.s * 4) >= min_j)
+    const int64_t groups = (m + p.il - 1) / p.il;   // lane groups holding distinct i-bodies
+    while (p.s < 64 && groups * p.s < nbk::WG && nj / (p.s * 4) >= min_j_lane)
         p.s *= 4;
-    lanes *= p.s;
     int64_t b = 1;
-    while (lanes * b < target_lanes && nj / (p.s * b * 2) >= min_j && b < 1024)
+    while (groups * p.s * b < target_lanes && nj / (b * 2) >= min_j_chunk &&
+           nj / (p.s * b * 2) >= min_j_lane && b < 1024)
         b *= 2;
     p.b = (int)b;
+    while (p.s < 64 && groups * p.s * b < target_lanes && nj / (p.s * 4 * b) >= min_j_lane)
+        p.s *= 4;
     return p;
 }
 
-bool valid_plan(int il, int s, int b)
+bool valid_plan(const Plan &p)
 {
-    return (il == 1 || il == 2 || il == 4) && (s == 1 || s == 4 || s == 16 || s == 64) &&
-           b >= 1 && b <= 65535;
+    return (p.il == 1 || p.il == 2 || p.il == 4) &&
+           (p.s == 1 || p.s == 4 || p.s == 16 || p.s == 64) && p.b >= 1 && p.b <= 65535;
 }
 
-nb_status force_impl(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
-                     int64_t j0, int64_t j1, double eps, nb_precision prec, Plan plan,
-                     double *acc, double *jerk)
+struct ForceJob {
+    Item it;
+    Plan plan;
+};
+
+// Launch the force kernels (one launch per plan shape) and the partial reduction
+// for a set of jobs; every job's item already has its system, i_idx, m, j-range,
+// eps2, acc/jerk and status set.
+nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
 {
-    nb_status st = check_system(ctx, sys, true);
-    if (st != NB_OK) return st;
+    size_t part_doubles = 0;
+    for (ForceJob &j : jobs) {
+        Item &it = j.it;
+        const int64_t nj = it.j1 - it.j0;
+        int64_t chunk = (nj + j.plan.b - 1) / j.plan.b;
+        chunk = (chunk + nbk::TILE - 1) / nbk::TILE * nbk::TILE;
+        if (chunk < nbk::TILE) chunk = nbk::TILE;
+        it.chunk = chunk;
+        it.b = j.plan.b;
+        if (it.b > 1) part_doubles += 6 * (size_t)it.m * (size_t)it.b;
+    }
+    if (part_doubles) {
+        size_t have = ctx->scratch_bytes;
+        NB_TRY(grow(ctx, &ctx->scratch, &have, part_doubles * sizeof(double), "force partials"));
+        ctx->scratch_bytes = have;
+    }
+    size_t off = 0;
+    for (ForceJob &j : jobs) {
+        if (j.it.b > 1) {
+            j.it.part = (double *)ctx->scratch + off;
+            off += 6 * (size_t)j.it.m * (size_t)j.it.b;
+        }
+    }
+    std::map<std::pair<int, int>, std::vector<size_t>> shapes;
+    for (size_t k = 0; k < jobs.size(); ++k)
+        if (jobs[k].it.m > 0) shapes[{jobs[k].plan.il, jobs[k].plan.s}].push_back(k);
+    for (auto &kv : shapes) {
+        const int il = kv.first.first, s = kv.first.second;
+        const int iwg = (nbk::WG / s) * il;
+        std::vector<Item> items;
+        std::vector<int64_t> blocks;
+        for (size_t k : kv.second) {
+            items.push_back(jobs[k].it);
+            blocks.push_back((int64_t)((jobs[k].it.m + iwg - 1) / iwg) * jobs[k].it.b);
+        }
+        Table t;
+        NB_TRY(make_table(ctx, items, blocks, &t));
+        hipError_t e = nbk::launch_force(prec, il, s, t, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
+    }
+    std::vector<Item> red;
+    std::vector<int64_t> rblocks;
+    for (ForceJob &j : jobs) {
+        if (j.it.b > 1 && j.it.m > 0) {
+            red.push_back(j.it);
+            rblocks.push_back((6 * (int64_t)j.it.m + nbk::WG - 1) / nbk::WG);
+        }
+    }
+    if (!red.empty()) {
+        Table t;
+        NB_TRY(make_table(ctx, red, rblocks, &t));
+        hipError_t e = nbk::launch_reduce(t, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "partial reduction launch");
+    }
+    return NB_OK;
+}
+
+nb_status check_force_args(nb_ctx *ctx, const nb_system *sys, int32_t m, int64_t j0, int64_t j1,
+                           double eps, int prec, const double *acc, const double *jerk)
+{
+    NB_TRY(check_system(ctx, sys, true));
     if (!(eps > 0.0) || !isfinite(eps)) return fail(ctx, NB_EINVAL, "eps must be > 0 and finite");
     if (prec != NB_FP64 && prec != NB_MIXED) return fail(ctx, NB_EINVAL, "unknown precision");
     if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
     if (j0 < 0 || j1 > sys->n || j0 > j1) return fail(ctx, NB_EINVAL, "bad j-range");
-    if (m == 0) return NB_OK;
-    if (!acc || !jerk) return fail(ctx, NB_EINVAL, "acc/jerk is NULL");
-    if (prec == NB_MIXED && !sys->vxp32)
+    if (m > 0 && (!acc || !jerk)) return fail(ctx, NB_EINVAL, "acc/jerk is NULL");
+    if (m > 0 && prec == NB_MIXED && !sys->vxp32)
         return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
-    if (!valid_plan(plan.il, plan.s, plan.b)) return fail(ctx, NB_EINVAL, "invalid plan");
+    return NB_OK;
+}
 
-    constexpr int TILE = 512;
-    const int64_t nj = j1 - j0;
-    int64_t chunk = (nj + plan.b - 1) / plan.b;
-    chunk = (chunk + TILE - 1) / TILE * TILE;
-    if (chunk < TILE) chunk = TILE;
-    const int iwg = (nbk::WG / plan.s) * plan.il;
-    dim3 grid((unsigned)((m + iwg - 1) / iwg), (unsigned)plan.b);
+nb_status force_one(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
+                    int64_t j0, int64_t j1, double eps, nb_precision prec, Plan plan,
+                    double *acc, double *jerk)
+{
+    NB_TRY(check_force_args(ctx, sys, m, j0, j1, eps, prec, acc, jerk));
+    if (!valid_plan(plan)) return fail(ctx, NB_EINVAL, "invalid plan");
+    if (m == 0) return NB_OK;
+    ForceJob job;
+    job.it = base_item(ctx, *sys);
+    job.it.i_idx = i_idx;
+    job.it.m = m;
+    job.it.j0 = j0;
+    job.it.j1 = j1;
+    job.it.eps2 = eps * eps;
+    job.it.acc = acc;
+    job.it.jerk = jerk;
+    job.plan = plan;
+    std::vector<ForceJob> jobs{job};
+    return run_force(ctx, jobs, prec);
+}
 
-    nbk::ForceArgs a{};
-    a.xp = sys->xp; a.yp = sys->yp; a.zp = sys->zp;
-    a.vx64 = sys->vxp; a.vy64 = sys->vyp; a.vz64 = sys->vzp; a.m64 = sys->m;
-    a.vx32 = sys->vxp32; a.vy32 = sys->vyp32; a.vz32 = sys->vzp32; a.m32 = sys->m32;
-    a.i_idx = i_idx;
-    a.m = m;
-    a.n = sys->n;
-    a.j0 = j0; a.j1 = j1; a.chunk = chunk;
-    a.eps2 = eps * eps;
-    a.status = &ctx->small->status;
-    double *part = nullptr;
-    if (plan.b > 1) {
-        st = ensure_scratch(ctx, sizeof(double) * 6 * (size_t)m * (size_t)plan.b);
-        if (st != NB_OK) return st;
-        part = (double *)ctx->scratch;
-        a.out_acc = part;
-        a.out_jerk = part + 3 * (int64_t)m;
-        a.stride_b = 6 * (int64_t)m;
+// ---- selection -------------------------------------------------------------------
+
+void sel_shape(int64_t n, int32_t *blocks_out, int64_t *slice_out)
+{
+    int64_t blocks = (n + 4095) / 4096;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    int64_t slice = (n + blocks - 1) / blocks;
+    slice = (slice + nbk::WG - 1) / nbk::WG * nbk::WG;
+    blocks = (n + slice - 1) / slice;
+    if (blocks < 1) blocks = 1;
+    *blocks_out = (int32_t)blocks;
+    *slice_out = slice;
+}
+
+// Device selection for `items` (each with s, i_idx and status set; every item
+// has n >= 1); fills res (host copy, one SelResult per item).  Waits for the stream.
+nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResult> &res)
+{
+    res.assign(items.size(), SelResult{INFINITY, 0, 0});
+    if (items.empty()) return NB_OK;
+    int64_t total = 0;
+    std::vector<int64_t> blocks;
+    for (Item &it : items) {
+        sel_shape(it.s.n, &it.sel_blocks, &it.sel_slice);
+        it.sel_off = total;
+        total += it.sel_blocks;
+        blocks.push_back(it.sel_blocks);
+    }
+    size_t have = ctx->selbuf_bytes;
+    NB_TRY(grow(ctx, &ctx->selbuf, &have, (size_t)total * (sizeof(double) + sizeof(int32_t)),
+                "selection temporaries"));
+    ctx->selbuf_bytes = have;
+    NB_TRY(ensure_res(ctx, items.size() * sizeof(SelResult)));
+    double *blockval = (double *)ctx->selbuf;
+    int32_t *blockcnt = (int32_t *)(blockval + total);
+    SelResult *dres = (SelResult *)ctx->res;
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    if (t.n != (int)items.size()) return fail(ctx, NB_EINVAL, "selection of an empty system");
+    hipError_t e = nbk::launch_select(t, blockval, blockcnt, dres, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "selection launch");
+    e = nbk::launch_collect_status(t.items, t.n, dres, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "status collection launch");
+    NB_HIP(ctx, hipMemcpyAsync(ctx->res_host, dres, items.size() * sizeof(SelResult),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    memcpy(res.data(), ctx->res_host, items.size() * sizeof(SelResult));
+    return NB_OK;
+}
+
+// ---- batches -----------------------------------------------------------------------
+
+nb_status check_item(nb_ctx *ctx, const nb_batch_item &b, bool need_m)
+{
+    NB_TRY(check_system(ctx, &b.sys, true));
+    if (b.sys.n == 0) return NB_OK;
+    if (!(b.eps > 0.0) || !isfinite(b.eps)) return fail(ctx, NB_EINVAL, "item eps must be > 0");
+    if (!b.i_idx || !b.acc || !b.jerk) return fail(ctx, NB_EINVAL, "item buffers are NULL");
+    if (need_m && !b.startup && (b.m < 0 || (int64_t)b.m > b.sys.n))
+        return fail(ctx, NB_EINVAL, "item m out of range");
+    if (need_m && !b.startup && !isfinite(b.t_next))
+        return fail(ctx, NB_EINVAL, "item t_next must be finite");
+    return NB_OK;
+}
+
+Item batch_item(nb_ctx *ctx, const nb_batch_item &b)
+{
+    Item it = base_item(ctx, b.sys);
+    if (b.status) it.status = b.status;
+    it.eps2 = b.eps * b.eps;
+    it.t_next = b.t_next;
+    it.acc = b.acc;
+    it.jerk = b.jerk;
+    if (b.startup) {
+        it.i_idx = nullptr;
+        it.m = (int32_t)b.sys.n;
     } else {
-        a.out_acc = acc;
-        a.out_jerk = jerk;
-        a.stride_b = 0;
+        it.i_idx = b.i_idx;
+        it.m = b.m;
     }
-    hipError_t e = nbk::launch_force(prec, plan.il, plan.s, grid, a, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
-    if (plan.b > 1) {
-        e = nbk::launch_reduce_partials(part, m, plan.b, acc, jerk, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "partial reduction launch");
-    }
+    it.j0 = 0;
+    it.j1 = b.sys.n;
+    return it;
+}
+
+nb_status check_step_params(nb_ctx *ctx, double eta, double dt_max, double dt_min)
+{
+    if (!(eta > 0.0) || !(dt_max > 0.0) || !(dt_min > 0.0) || dt_min > dt_max)
+        return fail(ctx, NB_EINVAL, "need eta > 0 and 0 < dt_min <= dt_max");
     return NB_OK;
 }
 
@@ -222,6 +474,11 @@ nb_status nb_ctx_destroy(nb_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->selbuf) (void)hipFree(ctx->selbuf);
+    if (ctx->res) (void)hipFree(ctx->res);
+    if (ctx->res_host) (void)hipHostFree(ctx->res_host);
+    if (ctx->stage_dev) (void)hipFree(ctx->stage_dev);
+    if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->small_host) (void)hipHostFree(ctx->small_host);
     delete ctx;
@@ -237,14 +494,17 @@ const char *nb_last_error(const nb_ctx *ctx)
 nb_status nb_sync(nb_ctx *ctx)
 {
     if (!ctx) return NB_EINVAL;
-    return sync_small(ctx, sizeof(int));
+    NB_HIP(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    NB_HIP(ctx, hipMemsetAsync(&ctx->small->status, 0, sizeof(int), ctx->stream));
+    NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return take_status(ctx, ctx->small_host->status);
 }
 
 nb_status nb_select_active(nb_ctx *ctx, const nb_system *sys, double *t_next_host,
                            int32_t *i_idx, int32_t *m_host)
 {
-    nb_status st = check_system(ctx, sys, false);
-    if (st != NB_OK) return st;
+    NB_TRY(check_system(ctx, sys, false));
     if (!t_next_host || !m_host) return fail(ctx, NB_EINVAL, "host outputs are NULL");
     if (sys->n == 0) {
         *m_host = 0;
@@ -252,21 +512,26 @@ nb_status nb_select_active(nb_ctx *ctx, const nb_system *sys, double *t_next_hos
         return NB_OK;
     }
     if (!i_idx) return fail(ctx, NB_EINVAL, "i_idx is NULL");
-    hipError_t e = nbk::launch_select(*sys, ctx->small, i_idx, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "selection launch");
-    st = sync_small(ctx, offsetof(nb_small, energy));
-    *t_next_host = ctx->small_host->t_next;
-    *m_host = ctx->small_host->m;
-    return st;
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].i_idx = i_idx;
+    std::vector<SelResult> res;
+    NB_TRY(run_select(ctx, items, res));
+    *t_next_host = res[0].t_next;
+    *m_host = res[0].m;
+    return take_status(ctx, res[0].status);
 }
 
 nb_status nb_predict(nb_ctx *ctx, const nb_system *sys, double t_next)
 {
-    nb_status st = check_system(ctx, sys, true);
-    if (st != NB_OK) return st;
+    NB_TRY(check_system(ctx, sys, true));
     if (!isfinite(t_next)) return fail(ctx, NB_EINVAL, "t_next must be finite");
     if (sys->n == 0) return NB_OK;
-    hipError_t e = nbk::launch_predict(*sys, t_next, ctx->stream);
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].t_next = t_next;
+    std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_predict(t, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict launch");
 }
 
@@ -274,8 +539,8 @@ nb_status nb_force_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
                           int64_t j0, int64_t j1, double eps, nb_precision precision,
                           double *acc, double *jerk)
 {
-    Plan p = make_plan(j1 - j0, m, precision);
-    return force_impl(ctx, sys, i_idx, m, j0, j1, eps, precision, p, acc, jerk);
+    return force_one(ctx, sys, i_idx, m, j0, j1, eps, precision, make_plan(j1 - j0, m, precision),
+                     acc, jerk);
 }
 
 nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
@@ -283,8 +548,8 @@ nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t 
                                nb_precision precision, int32_t i_per_lane, int32_t lanes_per_i,
                                int32_t j_chunks, double *acc, double *jerk)
 {
-    Plan p{i_per_lane, lanes_per_i, j_chunks};
-    return force_impl(ctx, sys, i_idx, m, j0, j1, eps, precision, p, acc, jerk);
+    return force_one(ctx, sys, i_idx, m, j0, j1, eps, precision,
+                     Plan{i_per_lane, lanes_per_i, j_chunks}, acc, jerk);
 }
 
 void nb_force_plan(int64_t nj, int32_t m, nb_precision precision, int32_t *i_per_lane,
@@ -299,14 +564,17 @@ void nb_force_plan(int64_t nj, int32_t m, nb_precision precision, int32_t *i_per
 nb_status nb_init_steps(nb_ctx *ctx, const nb_system *sys, const double *acc,
                         const double *jerk, double eta_s, double dt_max, double dt_min)
 {
-    nb_status st = check_system(ctx, sys, false);
-    if (st != NB_OK) return st;
-    if (!(eta_s > 0.0) || !(dt_max > 0.0) || !(dt_min > 0.0) || dt_min > dt_max)
-        return fail(ctx, NB_EINVAL, "need eta_s > 0 and 0 < dt_min <= dt_max");
+    NB_TRY(check_system(ctx, sys, false));
+    NB_TRY(check_step_params(ctx, eta_s, dt_max, dt_min));
     if (sys->n == 0) return NB_OK;
     if (!acc || !jerk) return fail(ctx, NB_EINVAL, "acc/jerk is NULL");
-    hipError_t e = nbk::launch_init_steps(*sys, acc, jerk, eta_s, dt_max, dt_min,
-                                          &ctx->small->status, ctx->stream);
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].acc = (double *)acc;
+    items[0].jerk = (double *)jerk;
+    std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
 }
 
@@ -314,24 +582,29 @@ nb_status nb_correct(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, in
                      const double *acc, const double *jerk, double t_next, double eta,
                      double dt_max, double dt_min)
 {
-    nb_status st = check_system(ctx, sys, true);
-    if (st != NB_OK) return st;
+    NB_TRY(check_system(ctx, sys, true));
     if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
-    if (!(eta > 0.0) || !(dt_max > 0.0) || !(dt_min > 0.0) || dt_min > dt_max)
-        return fail(ctx, NB_EINVAL, "need eta > 0 and 0 < dt_min <= dt_max");
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
     if (!isfinite(t_next)) return fail(ctx, NB_EINVAL, "t_next must be finite");
     if (m == 0) return NB_OK;
     if (!acc || !jerk) return fail(ctx, NB_EINVAL, "acc/jerk is NULL");
-    hipError_t e = nbk::launch_correct(*sys, i_idx, m, acc, jerk, t_next, eta, dt_max, dt_min,
-                                       &ctx->small->status, ctx->stream);
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].i_idx = i_idx;
+    items[0].m = m;
+    items[0].acc = (double *)acc;
+    items[0].jerk = (double *)jerk;
+    items[0].t_next = t_next;
+    std::vector<int64_t> blocks{(m + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_correct(t, eta, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "correct launch");
 }
 
 nb_status nb_energy(nb_ctx *ctx, const nb_system *sys, double eps, double *kinetic_host,
                     double *potential_host)
 {
-    nb_status st = check_system(ctx, sys, false);
-    if (st != NB_OK) return st;
+    NB_TRY(check_system(ctx, sys, false));
     if (!(eps >= 0.0) || !isfinite(eps)) return fail(ctx, NB_EINVAL, "eps must be >= 0");
     if (!kinetic_host || !potential_host) return fail(ctx, NB_EINVAL, "host outputs are NULL");
     if (sys->n == 0) {
@@ -339,15 +612,127 @@ nb_status nb_energy(nb_ctx *ctx, const nb_system *sys, double eps, double *kinet
         *potential_host = 0.0;
         return NB_OK;
     }
-    st = ensure_scratch(ctx, sizeof(double) * (size_t)sys->n);
-    if (st != NB_OK) return st;
+    size_t have = ctx->scratch_bytes;
+    NB_TRY(grow(ctx, &ctx->scratch, &have, sizeof(double) * (size_t)sys->n, "energy rows"));
+    ctx->scratch_bytes = have;
     hipError_t e = nbk::launch_energy(*sys, eps * eps, (double *)ctx->scratch, ctx->small->energy,
                                       ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "energy launch");
-    st = sync_small(ctx, offsetof(nb_small, blockval));
+    NB_HIP(ctx, hipMemcpyAsync(ctx->small_host, ctx->small, sizeof(nb_small), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    NB_HIP(ctx, hipMemsetAsync(&ctx->small->status, 0, sizeof(int), ctx->stream));
+    NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *kinetic_host = ctx->small_host->energy[0];
     *potential_host = ctx->small_host->energy[1];
-    return st;
+    return take_status(ctx, ctx->small_host->status);
+}
+
+nb_status nb_select_active_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    std::vector<Item> dev;
+    std::vector<int32_t> which;
+    for (int32_t k = 0; k < n_items; ++k) {
+        NB_TRY(check_item(ctx, items[k], false));
+        items[k].error = NB_OK;
+        if (items[k].sys.n == 0) {
+            items[k].m = 0;
+            items[k].t_next = INFINITY;
+            continue;
+        }
+        if (items[k].startup) {
+            items[k].m = (int32_t)items[k].sys.n;
+            items[k].t_next = 0.0;
+        }
+        // a startup item runs the selection too (its result is ignored), so that
+        // every item's status word is collected by the same launch
+        Item it = base_item(ctx, items[k].sys);
+        if (items[k].status) it.status = items[k].status;
+        it.i_idx = items[k].i_idx;
+        dev.push_back(it);
+        which.push_back(k);
+    }
+    std::vector<SelResult> res;
+    NB_TRY(run_select(ctx, dev, res));
+    for (size_t q = 0; q < which.size(); ++q) {
+        nb_batch_item &b = items[which[q]];
+        if (!b.startup) {
+            b.t_next = res[q].t_next;
+            b.m = res[q].m;
+        }
+        b.error = status_code(res[q].status);
+    }
+    return NB_OK;
+}
+
+nb_status nb_predict_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    std::vector<Item> dev;
+    std::vector<int64_t> blocks;
+    for (int32_t k = 0; k < n_items; ++k) {
+        NB_TRY(check_item(ctx, items[k], true));
+        if (items[k].startup || items[k].sys.n == 0) continue;
+        dev.push_back(batch_item(ctx, items[k]));
+        blocks.push_back((items[k].sys.n + nbk::WG - 1) / nbk::WG);
+    }
+    Table t;
+    NB_TRY(make_table(ctx, dev, blocks, &t));
+    hipError_t e = nbk::launch_predict(t, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict launch");
+}
+
+nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
+                                nb_precision precision)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    if (precision != NB_FP64 && precision != NB_MIXED)
+        return fail(ctx, NB_EINVAL, "unknown precision");
+    std::vector<ForceJob> jobs;
+    for (int32_t k = 0; k < n_items; ++k) {
+        NB_TRY(check_item(ctx, items[k], true));
+        if (items[k].sys.n == 0) continue;
+        if (precision == NB_MIXED && !items[k].sys.vxp32)
+            return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
+        ForceJob job;
+        job.it = batch_item(ctx, items[k]);
+        job.plan = make_plan(items[k].sys.n, job.it.m, precision);
+        jobs.push_back(job);
+    }
+    return run_force(ctx, jobs, precision);
+}
+
+nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items, double eta,
+                           double eta_s, double dt_max, double dt_min)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
+    if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
+    std::vector<Item> cor, ini;
+    std::vector<int64_t> cblocks, iblocks;
+    for (int32_t k = 0; k < n_items; ++k) {
+        NB_TRY(check_item(ctx, items[k], true));
+        if (items[k].sys.n == 0) continue;
+        Item it = batch_item(ctx, items[k]);
+        if (items[k].startup) {
+            ini.push_back(it);
+            iblocks.push_back((items[k].sys.n + nbk::WG - 1) / nbk::WG);
+        } else if (it.m > 0) {
+            cor.push_back(it);
+            cblocks.push_back((it.m + nbk::WG - 1) / nbk::WG);
+        }
+    }
+    Table t;
+    NB_TRY(make_table(ctx, cor, cblocks, &t));
+    hipError_t e = nbk::launch_correct(t, eta, dt_max, dt_min, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "correct launch");
+    NB_TRY(make_table(ctx, ini, iblocks, &t));
+    e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
 }
 
 }  // extern "C"

@@ -9,8 +9,11 @@
 //    sums are combined at the end with cross-lane shuffles inside the wave;
 //  - j-bodies are staged cooperatively through LDS in structure-of-arrays tiles
 //    (coalesced global loads, broadcast LDS reads when S = 1);
-//  - the j-range is split into chunks across blockIdx.y (the paper's Bfactor);
-//    each chunk writes FP64 partials that a second kernel sums in fixed order.
+//  - the j-range is split into B chunks (the paper's Bfactor); each chunk writes
+//    FP64 partials that a second kernel sums in fixed order;
+//  - a launch serves a table of systems (items); each workgroup finds its item
+//    by binary search over the table's workgroup offsets, so systems of
+//    different N and active-block size share one launch.
 // Precision (Sec. 2 item 4): the FP64 kernel does all pair arithmetic in FP64;
 // the mixed kernel forms r_j - r_i in FP64, rounds it to FP32, does the rest in
 // FP32 with the hardware reciprocal square root, accumulates short runs of
@@ -18,8 +21,6 @@
 #include "nb_internal.h"
 
 namespace nbk {
-
-constexpr int TILE = 512;  // j-bodies per LDS tile
 
 // FP64 reciprocal square root: hardware estimate refined by two Newton steps
 // y <- y (3 - s y^2) / 2 written as y + y (1/2 - (s/2) y^2).
@@ -45,18 +46,26 @@ __device__ __forceinline__ double group_sum(double v)
 }
 
 template <int IL, int S, int F>
-__global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
+__global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, const int64_t *starts,
+                                                         int n_items)
 {
     __shared__ double sx[TILE], sy[TILE], sz[TILE];
     __shared__ float svx[TILE], svy[TILE], svz[TILE], sm[TILE];
 
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t local = (int64_t)blockIdx.x - starts[it_k];
+    const int64_t iblk = local / p.b, bidx = local % p.b;
     const int tid = threadIdx.x;
     const int g = tid / S, s = tid % S;
     constexpr int IWG = (WG / S) * IL;
-    const int64_t kbase = (int64_t)blockIdx.x * IWG + (int64_t)g * IL;
-    const int64_t jb = p.j0 + (int64_t)blockIdx.y * p.chunk;
+    const int64_t kbase = iblk * IWG + (int64_t)g * IL;
+    const int64_t jb = p.j0 + bidx * p.chunk;
     const int64_t je = min(jb + p.chunk, p.j1);
     const float eps2 = (float)p.eps2;
+    const int64_t n = p.s.n;
+    const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp;
+    const float *vx32 = p.s.vxp32, *vy32 = p.s.vyp32, *vz32 = p.s.vzp32, *m32 = p.s.m32;
 
     double xi[IL], yi[IL], zi[IL];
     float vxi[IL], vyi[IL], vzi[IL];
@@ -67,13 +76,13 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
         int64_t i = 0;
         if (k < p.m) {
             i = p.i_idx ? (int64_t)p.i_idx[k] : k;
-            if (i < 0 || i >= p.n) {
+            if (i < 0 || i >= n) {
                 atomicOr(p.status, (int)NBK_EINDEX);
                 i = 0;
             }
         }
-        xi[u] = p.xp[i]; yi[u] = p.yp[i]; zi[u] = p.zp[i];
-        vxi[u] = p.vx32[i]; vyi[u] = p.vy32[i]; vzi[u] = p.vz32[i];
+        xi[u] = xp[i]; yi[u] = yp[i]; zi[u] = zp[i];
+        vxi[u] = vx32[i]; vyi[u] = vy32[i]; vzi[u] = vz32[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) { A[u][c] = 0.0; J[u][c] = 0.0; }
     }
@@ -83,9 +92,9 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
         for (int q = tid; q < TILE; q += WG) {
             const int64_t j = jt + q;
             if (j < je) {
-                sx[q] = p.xp[j]; sy[q] = p.yp[j]; sz[q] = p.zp[j];
-                svx[q] = p.vx32[j]; svy[q] = p.vy32[j]; svz[q] = p.vz32[j];
-                sm[q] = p.m32[j];
+                sx[q] = xp[j]; sy[q] = yp[j]; sz[q] = zp[j];
+                svx[q] = vx32[j]; svy[q] = vy32[j]; svz[q] = vz32[j];
+                sm[q] = m32[j];
             } else {  // padding: zero mass contributes exactly zero
                 sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0;
                 svx[q] = 0.f; svy[q] = 0.f; svz[q] = 0.f; sm[q] = 0.f;
@@ -99,7 +108,7 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
             for (int u = 0; u < IL; ++u)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; }
-#pragma unroll 4
+#pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
                 const int q = kk + f * S + s;
                 const double xj = sx[q], yj = sy[q], zj = sz[q];
@@ -145,8 +154,9 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
         }
         const int64_t k = kbase + u;
         if (s == 0 && k < p.m) {
-            double *oa = p.out_acc + (int64_t)blockIdx.y * p.stride_b;
-            double *oj = p.out_jerk + (int64_t)blockIdx.y * p.stride_b;
+            const int64_t six_m = 6 * (int64_t)p.m;
+            double *oa = p.b > 1 ? p.part + bidx * six_m : p.acc;
+            double *oj = p.b > 1 ? p.part + bidx * six_m + 3 * (int64_t)p.m : p.jerk;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 oa[c * (int64_t)p.m + k] = A[u][c];
@@ -157,18 +167,26 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(ForceArgs p)
 }
 
 template <int IL, int S, int F>
-__global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
+__global__ __launch_bounds__(WG) void force_fp64_kernel(const Item *items, const int64_t *starts,
+                                                        int n_items)
 {
     __shared__ double sx[TILE], sy[TILE], sz[TILE];
     __shared__ double svx[TILE], svy[TILE], svz[TILE], sm[TILE];
 
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t local = (int64_t)blockIdx.x - starts[it_k];
+    const int64_t iblk = local / p.b, bidx = local % p.b;
     const int tid = threadIdx.x;
     const int g = tid / S, s = tid % S;
     constexpr int IWG = (WG / S) * IL;
-    const int64_t kbase = (int64_t)blockIdx.x * IWG + (int64_t)g * IL;
-    const int64_t jb = p.j0 + (int64_t)blockIdx.y * p.chunk;
+    const int64_t kbase = iblk * IWG + (int64_t)g * IL;
+    const int64_t jb = p.j0 + bidx * p.chunk;
     const int64_t je = min(jb + p.chunk, p.j1);
     const double eps2 = p.eps2;
+    const int64_t n = p.s.n;
+    const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp;
+    const double *vx64 = p.s.vxp, *vy64 = p.s.vyp, *vz64 = p.s.vzp, *m64 = p.s.m;
 
     double xi[IL], yi[IL], zi[IL], vxi[IL], vyi[IL], vzi[IL];
     double A[IL][3], J[IL][3];
@@ -178,13 +196,13 @@ __global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
         int64_t i = 0;
         if (k < p.m) {
             i = p.i_idx ? (int64_t)p.i_idx[k] : k;
-            if (i < 0 || i >= p.n) {
+            if (i < 0 || i >= n) {
                 atomicOr(p.status, (int)NBK_EINDEX);
                 i = 0;
             }
         }
-        xi[u] = p.xp[i]; yi[u] = p.yp[i]; zi[u] = p.zp[i];
-        vxi[u] = p.vx64[i]; vyi[u] = p.vy64[i]; vzi[u] = p.vz64[i];
+        xi[u] = xp[i]; yi[u] = yp[i]; zi[u] = zp[i];
+        vxi[u] = vx64[i]; vyi[u] = vy64[i]; vzi[u] = vz64[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) { A[u][c] = 0.0; J[u][c] = 0.0; }
     }
@@ -194,9 +212,9 @@ __global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
         for (int q = tid; q < TILE; q += WG) {
             const int64_t j = jt + q;
             if (j < je) {
-                sx[q] = p.xp[j]; sy[q] = p.yp[j]; sz[q] = p.zp[j];
-                svx[q] = p.vx64[j]; svy[q] = p.vy64[j]; svz[q] = p.vz64[j];
-                sm[q] = p.m64[j];
+                sx[q] = xp[j]; sy[q] = yp[j]; sz[q] = zp[j];
+                svx[q] = vx64[j]; svy[q] = vy64[j]; svz[q] = vz64[j];
+                sm[q] = m64[j];
             } else {
                 sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0;
                 svx[q] = 0.0; svy[q] = 0.0; svz[q] = 0.0; sm[q] = 0.0;
@@ -251,8 +269,9 @@ __global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
         }
         const int64_t k = kbase + u;
         if (s == 0 && k < p.m) {
-            double *oa = p.out_acc + (int64_t)blockIdx.y * p.stride_b;
-            double *oj = p.out_jerk + (int64_t)blockIdx.y * p.stride_b;
+            const int64_t six_m = 6 * (int64_t)p.m;
+            double *oa = p.b > 1 ? p.part + bidx * six_m : p.acc;
+            double *oj = p.b > 1 ? p.part + bidx * six_m + 3 * (int64_t)p.m : p.jerk;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 oa[c * (int64_t)p.m + k] = A[u][c];
@@ -265,65 +284,71 @@ __global__ __launch_bounds__(WG) void force_fp64_kernel(ForceArgs p)
 // Fold interval: FP32 terms summed per lane before a fold into FP64 (mixed),
 // bounded so that a tile holds a whole number of folds.
 template <int S>
-constexpr int fold_mixed() { return (TILE / S) < 32 ? (TILE / S) : 32; }
+constexpr int fold_mixed() { return (TILE / S) < NBK_FOLD ? (TILE / S) : NBK_FOLD; }
 template <int S>
 constexpr int fold_fp64() { return TILE / S; }
 
 template <int IL, int S>
-static hipError_t launch_one(int precision, dim3 grid, const ForceArgs &a, hipStream_t st)
+static hipError_t launch_one(int precision, const Table &t, hipStream_t st)
 {
+    const dim3 grid((unsigned)t.blocks);
     if (precision == NB_MIXED)
-        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>()>), grid, dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>()>), grid, dim3(WG), 0, st,
+                           t.items, t.starts, t.n);
     else
-        hipLaunchKernelGGL((force_fp64_kernel<IL, S, fold_fp64<S>()>), grid, dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((force_fp64_kernel<IL, S, fold_fp64<S>()>), grid, dim3(WG), 0, st,
+                           t.items, t.starts, t.n);
     return hipGetLastError();
 }
 
 template <int IL>
-static hipError_t launch_il(int precision, int s, dim3 grid, const ForceArgs &a, hipStream_t st)
+static hipError_t launch_il(int precision, int s, const Table &t, hipStream_t st)
 {
     switch (s) {
-    case 1: return launch_one<IL, 1>(precision, grid, a, st);
-    case 4: return launch_one<IL, 4>(precision, grid, a, st);
-    case 16: return launch_one<IL, 16>(precision, grid, a, st);
-    case 64: return launch_one<IL, 64>(precision, grid, a, st);
+    case 1: return launch_one<IL, 1>(precision, t, st);
+    case 4: return launch_one<IL, 4>(precision, t, st);
+    case 16: return launch_one<IL, 16>(precision, t, st);
+    case 64: return launch_one<IL, 64>(precision, t, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_force(int precision, int il, int s, dim3 grid, const ForceArgs &a,
-                        hipStream_t st)
+hipError_t launch_force(int precision, int il, int s, const Table &t, hipStream_t st)
 {
+    if (t.blocks <= 0) return hipSuccess;
     switch (il) {
-    case 1: return launch_il<1>(precision, s, grid, a, st);
-    case 2: return launch_il<2>(precision, s, grid, a, st);
-    case 4: return launch_il<4>(precision, s, grid, a, st);
+    case 1: return launch_il<1>(precision, s, t, st);
+    case 2: return launch_il<2>(precision, s, t, st);
+    case 4: return launch_il<4>(precision, s, t, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-__global__ __launch_bounds__(WG) void reduce_partials_kernel(const double *part, int32_t m, int nb,
-                                                             double *acc, double *jerk)
+// One thread per output value of every item with j_chunks > 1: the B partials
+// are summed in ascending chunk order.
+__global__ __launch_bounds__(WG) void reduce_partials_kernel(const Item *items,
+                                                             const int64_t *starts, int n_items)
 {
-    const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;   // over 6*m
-    const int64_t six_m = 6 * (int64_t)m;
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t idx = ((int64_t)blockIdx.x - starts[it_k]) * WG + threadIdx.x;   // < 6m
+    const int64_t six_m = 6 * (int64_t)p.m;
     if (idx >= six_m)
         return;
     double v = 0.0;
-    for (int b = 0; b < nb; ++b)
-        v += part[(int64_t)b * six_m + idx];
-    if (idx < 3 * (int64_t)m)
-        acc[idx] = v;
+    for (int b = 0; b < p.b; ++b)
+        v += p.part[(int64_t)b * six_m + idx];
+    if (idx < 3 * (int64_t)p.m)
+        p.acc[idx] = v;
     else
-        jerk[idx - 3 * (int64_t)m] = v;
+        p.jerk[idx - 3 * (int64_t)p.m] = v;
 }
 
-hipError_t launch_reduce_partials(const double *part, int32_t m, int nb, double *acc,
-                                  double *jerk, hipStream_t st)
+hipError_t launch_reduce(const Table &t, hipStream_t st)
 {
-    const int64_t total = 6 * (int64_t)m;
-    const unsigned blocks = (unsigned)((total + WG - 1) / WG);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks), dim3(WG), 0, st, part, m, nb, acc, jerk);
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items,
+                       t.starts, t.n);
     return hipGetLastError();
 }
 

@@ -1,4 +1,10 @@
 // Internal declarations shared by the HIP translation units of libnbody.so.
+//
+// Every kernel of the block-step path works from a table of Items: one Item per
+// system taking part in the launch, plus an array `starts` of n_items + 1
+// workgroup offsets (item k owns workgroups [starts[k], starts[k+1])).  A
+// single-system call is a table of one item, so the arithmetic a system sees
+// does not depend on what else is in the launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,74 +14,116 @@
 
 #include "../../include/nbody.h"
 
-// Bits of the device status word latched by kernels.
+// Bits of a status word latched by kernels.
 enum : int {
     NBK_ERANGE = 1,   // a new step fell below dt_min
     NBK_ENAN = 2,     // non-finite acceleration, jerk or step
     NBK_EINDEX = 4,   // active index out of range
 };
 
-// Small fixed-size device area of a context (allocated once at creation).
+// Small fixed-size device area of a context.
 struct nb_small {
-    int status;
-    int32_t m;
-    double t_next;
+    int status;          // the context's status word
+    int pad;
     double energy[2];
-    double blockval[1024];   // per-block minima of t + dt (selection pass 1)
-    int32_t blockcnt[1024];  // per-block active counts (selection pass 2)
 };
 
 struct nb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     nb_small *small = nullptr;        // device
-    nb_small *small_host = nullptr;   // pinned host mirror (only the leading words are used)
-    void *scratch = nullptr;          // device, grows on demand
+    nb_small *small_host = nullptr;   // pinned host mirror
+    void *scratch = nullptr;          // device: force partials, energy rows (grows)
     size_t scratch_bytes = 0;
+    void *selbuf = nullptr;           // device: selection per-workgroup temporaries (grows)
+    size_t selbuf_bytes = 0;
+    void *res = nullptr;              // device: per-item selection results (grows)
+    void *res_host = nullptr;         // pinned mirror of res
+    size_t res_bytes = 0;
+    char *stage_host = nullptr;       // pinned ring for item tables
+    char *stage_dev = nullptr;        // device ring mirrored by stage_host
+    size_t stage_bytes = 0, stage_off = 0;
     std::string err;
 };
 
 namespace nbk {
 
-constexpr int WG = 256;          // threads per workgroup (4 waves of 64)
-constexpr int SEL_BLOCKS = 1024; // upper bound on selection workgroups
+#ifndef NBK_TILE
+#define NBK_TILE 512
+#endif
+#ifndef NBK_UNROLL
+#define NBK_UNROLL 2
+#endif
+#ifndef NBK_FOLD
+#define NBK_FOLD 32
+#endif
 
-struct ForceArgs {
-    const double *xp, *yp, *zp;           // predicted positions (FP64)
-    const double *vx64, *vy64, *vz64;     // predicted velocities (FP64 path)
-    const double *m64;                    // masses (FP64 path)
-    const float *vx32, *vy32, *vz32;      // FP32 copies (mixed path)
-    const float *m32;
-    const int32_t *i_idx;                 // active list, or null for i = k
-    int32_t m;                            // active block size
-    int64_t n;                            // bodies in the system (index bound)
-    int64_t j0, j1;                       // j-range
-    int64_t chunk;                        // j per workgroup chunk (multiple of the tile)
-    double eps2;
-    double *out_acc, *out_jerk;           // rows c*m + k, plus b*stride_b
-    int64_t stride_b;
-    int *status;
+constexpr int WG = 256;          // threads per workgroup (4 waves of 64)
+constexpr int TILE = NBK_TILE;   // j-bodies per LDS tile
+
+// One system's part of a launch.  Plain data, uploaded to the device.
+struct Item {
+    nb_system s;                 // the system's arrays
+    const int32_t *i_idx;        // active list, or null for i = k
+    double *acc, *jerk;          // force outputs / corrector inputs, rows c*m + k
+    double *part;                // force partials of this item (j_chunks > 1)
+    int *status;                 // error word
+    double eps2;                 // softening squared
+    double t_next;               // block time
+    int64_t j0, j1;              // force j-range
+    int64_t chunk;               // j per chunk (multiple of TILE)
+    int32_t m;                   // active block size
+    int32_t b;                   // j-chunks (Bfactor)
+    int64_t sel_slice;           // selection: bodies per workgroup
+    int64_t sel_off;             // selection: first slot of this item's temporaries
+    int32_t sel_blocks;          // selection: workgroups
+    int32_t pad;
 };
 
-// Launch one force kernel instance; returns hipSuccess or the launch error.
-hipError_t launch_force(int precision, int il, int s, dim3 grid, const ForceArgs &a,
-                        hipStream_t st);
-// out[c*m+k] = sum_b part[b*6m + c*m + k] in ascending b, for c < 6.
-hipError_t launch_reduce_partials(const double *part, int32_t m, int nb, double *acc,
-                                  double *jerk, hipStream_t st);
-// Energy: per-body m_i * sum_{j != i} m_j / sqrt(r^2 + eps^2) into rows[n], then
+// Per-item selection results written by the selection kernels.
+struct SelResult {
+    double t_next;
+    int32_t m;
+    int32_t status;
+};
+
+struct Table {
+    const Item *items;           // device
+    const int64_t *starts;       // device, n + 1 entries
+    int n;
+    int64_t blocks;              // starts[n]
+};
+
+// Item owning workgroup `blk`: the largest k with starts[k] <= blk.
+__device__ __forceinline__ int find_item(const int64_t *starts, int n, int64_t blk)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Force kernels for one plan shape (IL i-bodies per lane, S lanes per i-body).
+hipError_t launch_force(int precision, int il, int s, const Table &t, hipStream_t st);
+// acc/jerk[c*m + k] = sum_b part[b*6m + c*m + k] (ascending b), one thread per value.
+hipError_t launch_reduce(const Table &t, hipStream_t st);
+// Energy of one system: rows[i] = m_i sum_{j != i} m_j / sqrt(r^2 + eps^2), then
 // compensated totals (kinetic, potential) into out[2].
 hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *out,
                          hipStream_t st);
 
-// Step kernels.
-hipError_t launch_select(const nb_system &s, nb_small *small, int32_t *i_idx, hipStream_t st);
-hipError_t launch_predict(const nb_system &s, double t_next, hipStream_t st);
-hipError_t launch_correct(const nb_system &s, const int32_t *i_idx, int32_t m,
-                          const double *acc, const double *jerk, double t_next, double eta,
-                          double dt_max, double dt_min, int *status, hipStream_t st);
-hipError_t launch_init_steps(const nb_system &s, const double *acc, const double *jerk,
-                             double eta_s, double dt_max, double dt_min, int *status,
+// Selection: three passes over per-item workgroup slices, then per-item results.
+hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
+                         hipStream_t st);
+// Copy each item's status word into res[k].status, then clear the words.
+hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipStream_t st);
+hipError_t launch_predict(const Table &t, hipStream_t st);
+hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_min,
+                          hipStream_t st);
+hipError_t launch_init_steps(const Table &t, double eta_s, double dt_max, double dt_min,
                              hipStream_t st);
 
 }  // namespace nbk

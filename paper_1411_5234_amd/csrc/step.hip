@@ -1,35 +1,23 @@
 // Block-time-step kernels (Sec. 2 items 1-2 of the paper): active-block
 // selection, Hermite-4 predictor for all bodies, corrector plus new
 // power-of-two step for the active block, and the startup step.  All FP64.
-// These are memory- or latency-bound one-pass kernels.
+// These are memory- or latency-bound one-pass kernels.  Every kernel serves a
+// table of systems (items): a workgroup finds its item by binary search over
+// the table's workgroup offsets and then works inside that one system.
 #include "nb_internal.h"
 
 namespace nbk {
 
 // ---- selection ---------------------------------------------------------------
-// Pass 1: per-workgroup minimum of t + dt over a contiguous slice.
-// Pass 2: every workgroup reduces the per-workgroup minima to t_next (identical
-//         arithmetic in every workgroup) and counts its bodies due at t_next.
-// Pass 3: every workgroup adds the counts of the workgroups before it and writes
+// Per item, the bodies are cut into sel_blocks contiguous slices of sel_slice.
+// Pass 1: each workgroup takes the minimum of t + dt over its slice.
+// Pass 2: each workgroup reduces its item's slice minima to t_next (the same
+//         arithmetic in every workgroup of the item) and counts its bodies due
+//         at t_next; the item's first workgroup stores t_next.
+// Pass 3: each workgroup adds the counts of the item's earlier slices and writes
 //         its due bodies' indices in ascending order (ordered compaction with a
-//         wave ballot and an LDS prefix over the four waves).
-
-struct SelShape {
-    int blocks;
-    int64_t slice;  // bodies per workgroup
-};
-
-static SelShape sel_shape(int64_t n)
-{
-    int64_t blocks = (n + 4095) / 4096;
-    if (blocks < 1) blocks = 1;
-    if (blocks > SEL_BLOCKS) blocks = SEL_BLOCKS;
-    int64_t slice = (n + blocks - 1) / blocks;
-    slice = (slice + WG - 1) / WG * WG;
-    blocks = (n + slice - 1) / slice;
-    if (blocks < 1) blocks = 1;
-    return {(int)blocks, slice};
-}
+//         wave ballot and an LDS prefix over the four waves); the item's last
+//         workgroup stores m.
 
 __device__ double wg_min(double v, double *lds)
 {
@@ -57,129 +45,157 @@ __device__ int wg_sum_int(int v, int *lds)
     return t;
 }
 
-__global__ __launch_bounds__(WG) void select_min_kernel(const double *t, const double *dt,
-                                                        int64_t n, int64_t slice, nb_small *sm)
+__global__ __launch_bounds__(WG) void select_min_kernel(const Item *items, const int64_t *starts,
+                                                        int n_items, double *blockval)
 {
     __shared__ double lds[WG / 64];
-    const int64_t b0 = (int64_t)blockIdx.x * slice;
-    const int64_t b1 = min(b0 + slice, n);
+    const int k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[k];
+    const int64_t lb = (int64_t)blockIdx.x - starts[k];
+    const int64_t b0 = lb * p.sel_slice;
+    const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
     double v = INFINITY;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += WG)
-        v = fmin(v, t[i] + dt[i]);
+        v = fmin(v, p.s.t[i] + p.s.dt[i]);
     v = wg_min(v, lds);
     if (threadIdx.x == 0)
-        sm->blockval[blockIdx.x] = v;
+        blockval[p.sel_off + lb] = v;
 }
 
-__device__ double global_tnext(const nb_small *sm, int nblocks, double *lds)
-{
-    double v = INFINITY;
-    for (int k = threadIdx.x; k < nblocks; k += WG)
-        v = fmin(v, sm->blockval[k]);
-    return wg_min(v, lds);
-}
-
-__global__ __launch_bounds__(WG) void select_count_kernel(const double *t, const double *dt,
-                                                          int64_t n, int64_t slice, int nblocks,
-                                                          nb_small *sm)
+__global__ __launch_bounds__(WG) void select_count_kernel(const Item *items, const int64_t *starts,
+                                                          int n_items, const double *blockval,
+                                                          int32_t *blockcnt, SelResult *res)
 {
     __shared__ double lds[WG / 64];
     __shared__ int ldi[WG / 64];
-    const double tn = global_tnext(sm, nblocks, lds);
-    const int64_t b0 = (int64_t)blockIdx.x * slice;
-    const int64_t b1 = min(b0 + slice, n);
+    const int k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[k];
+    const int64_t lb = (int64_t)blockIdx.x - starts[k];
+    double v = INFINITY;
+    for (int q = threadIdx.x; q < p.sel_blocks; q += WG)
+        v = fmin(v, blockval[p.sel_off + q]);
+    const double tn = wg_min(v, lds);
+    const int64_t b0 = lb * p.sel_slice;
+    const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
     int c = 0;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += WG)
-        c += (t[i] + dt[i] == tn) ? 1 : 0;
+        c += (p.s.t[i] + p.s.dt[i] == tn) ? 1 : 0;
     c = wg_sum_int(c, ldi);
     if (threadIdx.x == 0) {
-        sm->blockcnt[blockIdx.x] = c;
-        if (blockIdx.x == 0)
-            sm->t_next = tn;
+        blockcnt[p.sel_off + lb] = c;
+        if (lb == 0)
+            res[k].t_next = tn;
     }
 }
 
-__global__ __launch_bounds__(WG) void select_scatter_kernel(const double *t, const double *dt,
-                                                            int64_t n, int64_t slice, int nblocks,
-                                                            nb_small *sm, int32_t *i_idx)
+__global__ __launch_bounds__(WG) void select_scatter_kernel(const Item *items,
+                                                            const int64_t *starts, int n_items,
+                                                            const int32_t *blockcnt,
+                                                            SelResult *res)
 {
     __shared__ int ldi[WG / 64];
     __shared__ int wave_off[WG / 64];
-    const double tn = sm->t_next;
+    const int k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[k];
+    const int64_t lb = (int64_t)blockIdx.x - starts[k];
+    const double tn = res[k].t_next;
     int before = 0;
-    for (int k = threadIdx.x; k < (int)blockIdx.x; k += WG)
-        before += sm->blockcnt[k];
+    for (int q = threadIdx.x; q < (int)lb; q += WG)
+        before += blockcnt[p.sel_off + q];
     int base = wg_sum_int(before, ldi);
-    const int64_t b0 = (int64_t)blockIdx.x * slice;
-    const int64_t b1 = min(b0 + slice, n);
+    const int64_t b0 = lb * p.sel_slice;
+    const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    int32_t *out = (int32_t *)p.i_idx;
     for (int64_t r = b0; r < b1; r += WG) {
         const int64_t i = r + threadIdx.x;
-        const bool due = (i < b1) && (t[i] + dt[i] == tn);
+        const bool due = (i < b1) && (p.s.t[i] + p.s.dt[i] == tn);
         const unsigned long long mask = __ballot(due);
         const int in_wave = __popcll(mask & ((1ull << l) - 1ull));
         __syncthreads();
         if (l == 0) wave_off[w] = __popcll(mask);
         __syncthreads();
         int off = base;
-        for (int k = 0; k < w; ++k) off += wave_off[k];
+        for (int q = 0; q < w; ++q) off += wave_off[q];
         if (due)
-            i_idx[off + in_wave] = (int32_t)i;
+            out[off + in_wave] = (int32_t)i;
         int round = 0;
-        for (int k = 0; k < WG / 64; ++k) round += wave_off[k];
+        for (int q = 0; q < WG / 64; ++q) round += wave_off[q];
         base += round;
     }
-    if (blockIdx.x == nblocks - 1 && threadIdx.x == 0)
-        sm->m = base;
+    if (lb == p.sel_blocks - 1 && threadIdx.x == 0)
+        res[k].m = base;
 }
 
-hipError_t launch_select(const nb_system &s, nb_small *small, int32_t *i_idx, hipStream_t st)
+hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
+                         hipStream_t st)
 {
-    const SelShape sh = sel_shape(s.n);
-    hipLaunchKernelGGL(select_min_kernel, dim3(sh.blocks), dim3(WG), 0, st, s.t, s.dt, s.n,
-                       sh.slice, small);
+    if (t.blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)t.blocks);
+    hipLaunchKernelGGL(select_min_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n, blockval);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(select_count_kernel, dim3(sh.blocks), dim3(WG), 0, st, s.t, s.dt, s.n,
-                       sh.slice, sh.blocks, small);
+    hipLaunchKernelGGL(select_count_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n,
+                       (const double *)blockval, blockcnt, res);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(select_scatter_kernel, dim3(sh.blocks), dim3(WG), 0, st, s.t, s.dt, s.n,
-                       sh.slice, sh.blocks, small, i_idx);
+    hipLaunchKernelGGL(select_scatter_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n,
+                       (const int32_t *)blockcnt, res);
+    return hipGetLastError();
+}
+
+// One workgroup: read every item's status word, then clear the words (several
+// items may share one word, so all reads finish before any clear).
+__global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, int n, SelResult *res)
+{
+    for (int k = threadIdx.x; k < n; k += WG)
+        res[k].status = *items[k].status;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += WG)
+        *items[k].status = 0;
+}
+
+hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(collect_status_kernel, dim3(1), dim3(WG), 0, st, items, n, res);
     return hipGetLastError();
 }
 
 // ---- predictor -----------------------------------------------------------------
 
-__global__ __launch_bounds__(WG) void predict_kernel(nb_system s, double t_next)
+__global__ __launch_bounds__(WG) void predict_kernel(const Item *items, const int64_t *starts,
+                                                     int n_items)
 {
-    const int64_t stride = (int64_t)gridDim.x * WG;
-    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < s.n; i += stride) {
-        const double d = t_next - s.t[i];
-        const double d2 = d * d * 0.5, d3 = d * d * d * (1.0 / 6.0);
-        const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-        const double ax = s.ax[i], ay = s.ay[i], az = s.az[i];
-        const double jx = s.jx[i], jy = s.jy[i], jz = s.jz[i];
-        s.xp[i] = s.x[i] + vx * d + ax * d2 + jx * d3;
-        s.yp[i] = s.y[i] + vy * d + ay * d2 + jy * d3;
-        s.zp[i] = s.z[i] + vz * d + az * d2 + jz * d3;
-        const double px = vx + ax * d + jx * d2;
-        const double py = vy + ay * d + jy * d2;
-        const double pz = vz + az * d + jz * d2;
-        s.vxp[i] = px; s.vyp[i] = py; s.vzp[i] = pz;
-        if (s.vxp32) {
-            s.vxp32[i] = (float)px; s.vyp32[i] = (float)py; s.vzp32[i] = (float)pz;
-            s.m32[i] = (float)s.m[i];
-        }
+    const int k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[k];
+    const int64_t i = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
+    const nb_system &s = p.s;
+    if (i >= s.n)
+        return;
+    const double d = p.t_next - s.t[i];
+    const double d2 = d * d * 0.5, d3 = d * d * d * (1.0 / 6.0);
+    const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+    const double ax = s.ax[i], ay = s.ay[i], az = s.az[i];
+    const double jx = s.jx[i], jy = s.jy[i], jz = s.jz[i];
+    s.xp[i] = s.x[i] + vx * d + ax * d2 + jx * d3;
+    s.yp[i] = s.y[i] + vy * d + ay * d2 + jy * d3;
+    s.zp[i] = s.z[i] + vz * d + az * d2 + jz * d3;
+    const double px = vx + ax * d + jx * d2;
+    const double py = vy + ay * d + jy * d2;
+    const double pz = vz + az * d + jz * d2;
+    s.vxp[i] = px; s.vyp[i] = py; s.vzp[i] = pz;
+    if (s.vxp32) {
+        s.vxp32[i] = (float)px; s.vyp32[i] = (float)py; s.vzp32[i] = (float)pz;
+        s.m32[i] = (float)s.m[i];
     }
 }
 
-hipError_t launch_predict(const nb_system &s, double t_next, hipStream_t st)
+hipError_t launch_predict(const Table &t, hipStream_t st)
 {
-    int64_t blocks = (s.n + WG - 1) / WG;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)blocks), dim3(WG), 0, st, s, t_next);
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(predict_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
+                       t.n);
     return hipGetLastError();
 }
 
@@ -190,32 +206,36 @@ __device__ __forceinline__ double norm3(double a, double b, double c)
     return sqrt(a * a + b * b + c * c);
 }
 
-__global__ __launch_bounds__(WG) void correct_kernel(nb_system s, const int32_t *i_idx, int32_t m,
-                                                     const double *acc, const double *jerk,
-                                                     double t_next, double eta, double dt_max,
-                                                     double dt_min, int *status)
+__global__ __launch_bounds__(WG) void correct_kernel(const Item *items, const int64_t *starts,
+                                                     int n_items, double eta, double dt_max,
+                                                     double dt_min)
 {
-    const int64_t k = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t k = ((int64_t)blockIdx.x - starts[it_k]) * WG + threadIdx.x;
+    const int32_t m = p.m;
     if (k >= m)
         return;
-    const int64_t i = i_idx ? (int64_t)i_idx[k] : k;
+    const nb_system &s = p.s;
+    const int64_t i = p.i_idx ? (int64_t)p.i_idx[k] : k;
     if (i < 0 || i >= s.n) {
-        atomicOr(status, (int)NBK_EINDEX);
+        atomicOr(p.status, (int)NBK_EINDEX);
         return;
     }
+    const double t_next = p.t_next;
     const double h = t_next - s.t[i];
     const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
-    double* xs[3] = {s.x, s.y, s.z};
-    double* vs[3] = {s.vx, s.vy, s.vz};
-    double* as[3] = {s.ax, s.ay, s.az};
-    double* js[3] = {s.jx, s.jy, s.jz};
-    const double* xps[3] = {s.xp, s.yp, s.zp};
-    const double* vps[3] = {s.vxp, s.vyp, s.vzp};
+    double *xs[3] = {s.x, s.y, s.z};
+    double *vs[3] = {s.vx, s.vy, s.vz};
+    double *as[3] = {s.ax, s.ay, s.az};
+    double *js[3] = {s.jx, s.jy, s.jz};
+    const double *xps[3] = {s.xp, s.yp, s.zp};
+    const double *vps[3] = {s.vxp, s.vyp, s.vzp};
     double a1v[3], j1v[3], a2e[3], a3v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double a0 = as[c][i], j0 = js[c][i];
-        const double a1 = acc[c * (int64_t)m + k], j1 = jerk[c * (int64_t)m + k];
+        const double a1 = p.acc[c * (int64_t)m + k], j1 = p.jerk[c * (int64_t)m + k];
         const double da = a0 - a1;
         const double a2 = (-6.0 * da - h * (4.0 * j0 + 2.0 * j1)) / h2;
         const double a3 = (12.0 * da + 6.0 * h * (j0 + j1)) / h3;
@@ -250,31 +270,33 @@ __global__ __launch_bounds__(WG) void correct_kernel(nb_system s, const int32_t 
     s.t[i] = t_next;
     s.dt[i] = step;
     if (err)
-        atomicOr(status, err);
+        atomicOr(p.status, err);
 }
 
-hipError_t launch_correct(const nb_system &s, const int32_t *i_idx, int32_t m,
-                          const double *acc, const double *jerk, double t_next, double eta,
-                          double dt_max, double dt_min, int *status, hipStream_t st)
+hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_min,
+                          hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((m + WG - 1) / WG);
-    hipLaunchKernelGGL(correct_kernel, dim3(blocks), dim3(WG), 0, st, s, i_idx, m, acc, jerk,
-                       t_next, eta, dt_max, dt_min, status);
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(correct_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
+                       t.n, eta, dt_max, dt_min);
     return hipGetLastError();
 }
 
 // ---- startup ---------------------------------------------------------------------
 
-__global__ __launch_bounds__(WG) void init_steps_kernel(nb_system s, const double *acc,
-                                                        const double *jerk, double eta_s,
-                                                        double dt_max, double dt_min, int *status)
+__global__ __launch_bounds__(WG) void init_steps_kernel(const Item *items, const int64_t *starts,
+                                                        int n_items, double eta_s, double dt_max,
+                                                        double dt_min)
 {
-    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (i >= s.n)
-        return;
+    const int k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[k];
+    const int64_t i = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
+    const nb_system &s = p.s;
     const int64_t n = s.n;
-    const double ax = acc[i], ay = acc[n + i], az = acc[2 * n + i];
-    const double jx = jerk[i], jy = jerk[n + i], jz = jerk[2 * n + i];
+    if (i >= n)
+        return;
+    const double ax = p.acc[i], ay = p.acc[n + i], az = p.acc[2 * n + i];
+    const double jx = p.jerk[i], jy = p.jerk[n + i], jz = p.jerk[2 * n + i];
     s.ax[i] = ax; s.ay[i] = ay; s.az[i] = az;
     s.jx[i] = jx; s.jy[i] = jy; s.jz[i] = jz;
     const double an = norm3(ax, ay, az), jn = norm3(jx, jy, jz);
@@ -292,16 +314,15 @@ __global__ __launch_bounds__(WG) void init_steps_kernel(nb_system s, const doubl
     s.t[i] = 0.0;
     s.dt[i] = step;
     if (err)
-        atomicOr(status, err);
+        atomicOr(p.status, err);
 }
 
-hipError_t launch_init_steps(const nb_system &s, const double *acc, const double *jerk,
-                             double eta_s, double dt_max, double dt_min, int *status,
+hipError_t launch_init_steps(const Table &t, double eta_s, double dt_max, double dt_min,
                              hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((s.n + WG - 1) / WG);
-    hipLaunchKernelGGL(init_steps_kernel, dim3(blocks), dim3(WG), 0, st, s, acc, jerk, eta_s,
-                       dt_max, dt_min, status);
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_steps_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items,
+                       t.starts, t.n, eta_s, dt_max, dt_min);
     return hipGetLastError();
 }
 

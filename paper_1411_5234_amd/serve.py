@@ -1,0 +1,238 @@
+"""Continuous-batching server for ensembles of N-body simulations.
+
+Each request is an initial condition to integrate to t_end with the Hermite-4
+block-step scheme.  The server keeps every admitted system's state resident in
+HBM and advances ALL resident systems together: one iteration is one block step
+of every resident system, done with one ragged batched launch per phase through
+the C ABI (nb_select_active_batch, nb_predict_batch, nb_force_active_batch,
+nb_correct_batch).  Requests that arrive while others run are admitted between
+iterations as slots and device memory free up; a finished or failed system is
+retired at once and its memory is released.  A failing system (non-finite
+values, a step below dt_min) is reported alone; the others go on.
+
+Every system is computed with the same kernels, launch plan and arithmetic
+whether it runs alone or in a mix (the single-system calls are batches of one),
+so its result is bitwise the same in both cases.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NbBatchItem, NbError, PRECISIONS
+from .nbody import Context, System
+
+
+@dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float               # seconds after the stream start
+    admitted: float
+    finished: float
+    steps: int = 0
+    interactions: int = 0
+    energy0: float = float("nan")
+    energy1: float = float("nan")
+    error: str | None = None
+    final: dict | None = None    # final state (when keep_state is set)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+    @property
+    def energy_error(self) -> float:
+        return abs(self.energy1 - self.energy0) / abs(self.energy0)
+
+
+class _Slot:
+    """One resident system: device state, work buffers and its batch item."""
+
+    def __init__(self, req, device, precision, now):
+        snap = req.snapshot()
+        self.req = req
+        self.n = snap.n
+        self.sys = System.from_arrays(snap.x, snap.v, snap.m, device=device,
+                                      fp32_copies=(precision == "mixed"))
+        n1 = max(self.n, 1)
+        self.i_idx = torch.zeros(n1, dtype=torch.int32, device=device)
+        self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=device)
+        self.jerk = torch.zeros(3 * n1, dtype=torch.float64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.item = NbBatchItem()
+        self.item.sys = self.sys._struct
+        self.item.i_idx = self.i_idx.data_ptr()
+        self.item.acc = self.acc.data_ptr()
+        self.item.jerk = self.jerk.data_ptr()
+        self.item.status = self.status.data_ptr()
+        self.item.eps = float(req.eps)
+        self.item.startup = 1
+        self.result = Result(req.rid, self.n, req.arrival, now, float("nan"))
+
+
+def footprint_bytes(n: int, precision: str = "mixed") -> int:
+    """Device bytes one resident system of n bodies holds (state + work buffers)."""
+    per_body = 8 * 21 + (16 if precision == "mixed" else 0) + 4 + 48
+    return per_body * max(n, 1) + 4 + 1024
+
+
+class Server:
+    """Advance many systems together with ragged batched launches.
+
+    precision: "mixed" or "fp64"; memory_budget: device bytes for resident systems
+    (default 90% of free memory); max_slots: most systems resident at once.
+    """
+
+    def __init__(self, ctx: Context | None = None, precision: str = "mixed",
+                 memory_budget: int | None = None, max_slots: int = 256, eta: float = 0.02,
+                 eta_s: float = 0.01, dt_max: float = 2.0 ** -3, dt_min: float = 2.0 ** -40,
+                 keep_state: bool = False, energy: bool = True):
+        if precision not in PRECISIONS:
+            raise ValueError(precision)
+        self.ctx = ctx if ctx is not None else Context(0)
+        self.L = _lib.load()
+        self.precision = precision
+        self.prec_code = PRECISIONS[precision]
+        self.device = torch.device("cuda", self.ctx.device)
+        if memory_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.ctx.device)
+            memory_budget = int(0.9 * free)
+        self.budget = int(memory_budget)
+        self.max_slots = int(max_slots)
+        self.eta, self.eta_s, self.dt_max, self.dt_min = eta, eta_s, dt_max, dt_min
+        self.keep_state = keep_state
+        self.energy = energy
+        self.queue: deque = deque()
+        self.slots: list[_Slot] = []
+        self.used = 0
+        self.results: list[Result] = []
+        self.iterations = 0
+        self.t0 = None
+
+    # ---- admission -----------------------------------------------------------
+    def submit(self, req):
+        if req.t_end / self.dt_max != math.floor(req.t_end / self.dt_max):
+            raise ValueError("t_end must be a multiple of dt_max")
+        if footprint_bytes(req.n, self.precision) > self.budget:
+            raise ValueError("request of n=%d does not fit the memory budget" % req.n)
+        self.queue.append(req)
+
+    def _now(self):
+        return time.perf_counter() - self.t0
+
+    def _admit(self):
+        while self.queue and len(self.slots) < self.max_slots:
+            req = self.queue[0]
+            need = footprint_bytes(req.n, self.precision)
+            if self.used + need > self.budget:
+                break
+            self.queue.popleft()
+            slot = _Slot(req, self.device, self.precision, self._now())
+            if self.energy:
+                slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
+            slot.bytes = need
+            self.used += need
+            self.slots.append(slot)
+
+    def _retire(self, slot: _Slot, error: str | None):
+        r = slot.result
+        r.error = error
+        if error is None:
+            if self.energy:
+                r.energy1 = self.ctx.energy(slot.sys, slot.req.eps)[2]
+            if self.keep_state:
+                r.final = slot.sys.state_numpy()
+        r.finished = self._now()
+        self.results.append(r)
+        self.used -= slot.bytes
+        self.slots.remove(slot)
+
+    # ---- one iteration: one block step of every resident system ---------------
+    def _check(self, rc):
+        if rc != 0:
+            raise NbError(rc, self.L.nb_last_error(self.ctx.h).decode())
+
+    def step(self):
+        """Select every resident system's next block; retire finished or failed
+        systems; then predict, force and correct all the others in one launch
+        per phase."""
+        slots = list(self.slots)
+        if not slots:
+            return
+        items = (NbBatchItem * len(slots))(*[s.item for s in slots])
+        self._check(self.L.nb_select_active_batch(self.ctx.h, items, len(slots)))
+        active = []
+        for s, it in zip(slots, items):
+            if it.error != 0:
+                self._retire(s, _lib.STATUS.get(it.error, str(it.error)))
+            elif not it.startup and it.t_next > s.req.t_end:
+                self._retire(s, None)
+            else:
+                s.item.t_next, s.item.m = it.t_next, it.m
+                active.append(s)
+        if not active:
+            return
+        run = (NbBatchItem * len(active))(*[s.item for s in active])
+        k = len(active)
+        self._check(self.L.nb_predict_batch(self.ctx.h, run, k))
+        self._check(self.L.nb_force_active_batch(self.ctx.h, run, k, self.prec_code))
+        self._check(self.L.nb_correct_batch(self.ctx.h, run, k, self.eta, self.eta_s,
+                                            self.dt_max, self.dt_min))
+        for s in active:
+            if s.item.startup:
+                s.result.interactions += s.n * s.n
+                s.item.startup = 0
+            else:
+                s.result.steps += 1
+                s.result.interactions += s.item.m * s.n
+        self.iterations += 1
+
+    # ---- driving a request stream ------------------------------------------------
+    def run(self, requests, realtime: bool = True, on_iteration=None):
+        """Serve `requests` (with .arrival in seconds) until every one is finished.
+
+        realtime: requests become visible at their arrival times on the wall clock;
+        otherwise all are visible at once (a closed batch).  Returns the results.
+        """
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        self.t0 = time.perf_counter()
+        while pending or self.queue or self.slots:
+            now = self._now()
+            while pending and (not realtime or pending[0].arrival <= now):
+                self.submit(pending.popleft())
+            self._admit()
+            if not self.slots:
+                if pending and realtime:
+                    time.sleep(max(0.0, min(pending[0].arrival - self._now(), 0.01)))
+                    continue
+                if self.queue:
+                    raise RuntimeError("a queued request can never be admitted")
+                continue
+            self.step()
+            if on_iteration is not None:
+                on_iteration(self)
+        self.ctx.sync()
+        return self.results
+
+
+def summarize(results, wall: float) -> dict:
+    ok = [r for r in results if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([float("nan")])
+    inter = sum(r.interactions for r in ok)
+    out = {"requests": len(results), "completed": len(ok), "failed": len(results) - len(ok),
+           "wall_s": wall, "solves_per_s": len(ok) / wall if wall > 0 else float("nan"),
+           "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+           "interactions": int(inter), "interactions_per_s": inter / wall if wall > 0 else float("nan")}
+    errs = [r.energy_error for r in ok if not math.isnan(r.energy1)]
+    if errs:
+        out["energy_error_median"] = float(np.median(errs))
+        out["energy_error_max"] = float(np.max(errs))
+    return out

@@ -53,8 +53,30 @@ def test_force_plan_is_pure_and_valid():
                 # every lane still walks a useful number of j-bodies
                 assert nj // (s * b) >= min(128, nj // (s * b) if s * b > 1 else nj)
                 seen[(prec, nj, m)] = p
-    # the whole system active at N = 2^20: no j-split needed
-    assert seen[("mixed", 1 << 20, 1 << 20)][2] == 1
+    # the whole system active at N = 2^20: broadcast LDS reads (S = 1), two
+    # i-bodies per lane, and only a small j-split
+    il, s, b = seen[("mixed", 1 << 20, 1 << 20)]
+    assert (il, s) == (2, 1) and b <= 4
     # a small block in a large system is split across j (the paper's Bfactor)
     il, s, b = seen[("mixed", 65536, 64)]
     assert s * b > 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of nb_system / nb_batch_item have the C sizes and offsets."""
+    import ctypes
+    import subprocess
+    from paper_1411_5234_amd import _lib
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "nbody.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(nb_system), '
+        'sizeof(nb_batch_item), offsetof(nb_batch_item, status), offsetof(nb_batch_item, eps), '
+        'offsetof(nb_batch_item, m), offsetof(nb_batch_item, error)); return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    B = _lib.NbBatchItem
+    want = [ctypes.sizeof(_lib.NbSystem), ctypes.sizeof(B), B.status.offset, B.eps.offset,
+            B.m.offset, B.error.offset]
+    assert got == want

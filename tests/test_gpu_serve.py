@@ -1,0 +1,118 @@
+"""Continuous-batching server on the GPU.
+
+A request's result must be bitwise the same alone and in a mix that is admitted
+and retired while it runs; the served result must equal the single-system
+block-step integrator's (which is checked against the oracle in
+test_gpu_integrate); admission must respect the memory budget; a failing request
+must fail alone.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1411_5234_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("x", "v", "a", "j", "t", "dt")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1411_5234_amd.nbody import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _req(rid, n, seed, arrival=0.0, t_end=0.25, eps=1e-3, kind="plummer"):
+    return inputs.Request(rid, arrival, n, seed, eps, t_end, kind)
+
+
+def _serve(ctx, reqs, precision="mixed", **kw):
+    from paper_1411_5234_amd.serve import Server
+    srv = Server(ctx, precision=precision, keep_state=True, **kw)
+    res = srv.run(reqs, realtime=False)
+    return {r.rid: r for r in res}, srv
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_same_result_alone_and_in_a_mix(ctx, precision):
+    target = _req(0, 700, 11)
+    alone, _ = _serve(ctx, [target], precision)
+    mix = [_req(1, 300, 12), _req(2, 1500, 13), target, _req(3, 256, 14, t_end=0.125),
+           _req(4, 900, 15), _req(5, 2048, 16, t_end=0.5), _req(6, 333, 17)]
+    # three slots: systems are admitted while others are mid-run and retired
+    mixed, srv = _serve(ctx, mix, precision, max_slots=3)
+    assert all(r.error is None for r in mixed.values())
+    a, b = alone[0].final, mixed[0].final
+    for f in FIELDS:
+        assert a[f].tobytes() == b[f].tobytes(), f
+    assert alone[0].steps == mixed[0].steps
+    assert np.all(b["t"] == 0.25)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_equals_single_system_integrator(ctx, precision):
+    from paper_1411_5234_amd.nbody import Integrator, Params, System
+    req = _req(0, 512, 21, t_end=0.25)
+    served, _ = _serve(ctx, [req, _req(1, 1024, 22)], precision)
+    snap = req.snapshot()
+    sys_ = System.from_arrays(snap.x, snap.v, snap.m, fp32_copies=(precision == "mixed"))
+    it = Integrator(ctx, sys_, Params(eps=req.eps, precision=precision))
+    it.startup()
+    steps, inter = it.run(req.t_end)
+    st = sys_.state_numpy()
+    for f in FIELDS:
+        assert st[f].tobytes() == served[0].final[f].tobytes(), f
+    assert served[0].steps == steps and served[0].interactions == inter
+
+
+def test_admission_respects_memory_budget(ctx):
+    from paper_1411_5234_amd.serve import Server, footprint_bytes
+    reqs = [_req(k, 600 + 50 * k, 30 + k, t_end=0.125) for k in range(8)]
+    budget = footprint_bytes(700, "mixed") * 2 + 10
+    seen = []
+    srv = Server(ctx, precision="mixed", memory_budget=budget)
+    res = srv.run(reqs, realtime=False,
+                  on_iteration=lambda s: seen.append((len(s.slots), s.used)))
+    assert len(res) == 8 and all(r.error is None for r in res)
+    assert max(k for k, _ in seen) <= 2
+    assert max(u for _, u in seen) <= budget
+    with pytest.raises(ValueError):
+        srv.submit(_req(99, 10 ** 6, 1))
+
+
+class _NaNRequest(inputs.Request):
+    def snapshot(self):
+        s = inputs.plummer(self.n, self.seed)
+        s.x[3, 1] = float("nan")
+        return s
+
+
+def test_a_failing_request_fails_alone(ctx):
+    bad = _NaNRequest(1, 0.0, 400, 41, 1e-3, 0.25)
+    good = _req(0, 500, 42)
+    alone, _ = _serve(ctx, [good])
+    both, _ = _serve(ctx, [good, bad, _req(2, 300, 43)])
+    assert both[1].error is not None
+    assert both[0].error is None and both[2].error is None
+    for f in FIELDS:
+        assert alone[0].final[f].tobytes() == both[0].final[f].tobytes(), f
+
+
+def test_poisson_stream_latency_and_throughput(ctx):
+    from paper_1411_5234_amd.serve import Server, summarize
+    import time
+    reqs = inputs.request_stream(24, 4, 256, 2048, rate=200.0, eps=1e-3, t_end=0.25,
+                                 ic_seed_base=4000)
+    srv = Server(ctx, precision="mixed", max_slots=16)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    s = summarize(res, time.perf_counter() - t0)
+    print(s, flush=True)
+    assert s["completed"] == 24 and s["failed"] == 0
+    assert 0 < s["latency_p50_s"] <= s["latency_p99_s"]
+    assert s["energy_error_max"] < 1e-4
+    assert all(r.admitted >= r.arrival - 1e-9 for r in res)

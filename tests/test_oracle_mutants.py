@@ -19,11 +19,11 @@ import test_oracle_hermite as th
 SRC = os.path.join(os.path.dirname(real_oracle.__file__), "nbody_oracle.c")
 
 MUTANTS = [
-    ("jerk drops the radial term", "mu * (w[d] - alpha * r[d])", "mu * (w[d])",
+    ("jerk drops the radial term", "cs_add(&jk[d], mu * (w[d] - alpha * r[d]))", "cs_add(&jk[d], mu * (w[d]))",
      lambda o: tf.test_jerk_is_time_derivative_of_acc(o, 3)),
     ("jerk coefficient 2 instead of 3", "3.0 * rw * rinv2", "2.0 * rw * rinv2",
      lambda o: tf.test_jerk_is_time_derivative_of_acc(o, 3)),
-    ("pair vector reversed", "r[d] = x[3 * j + d] - x[3 * i + d];", "r[d] = x[3 * i + d] - x[3 * j + d];",
+    ("pair vector reversed", " r[d] = x[3 * j + d] - x[3 * i + d];", " r[d] = x[3 * i + d] - x[3 * j + d];",
      lambda o: tf.test_acc_is_minus_gradient_of_potential(o, 0)),
     ("mass of i instead of j", "m[j] * rinv * rinv2", "m[i] * rinv * rinv2",
      lambda o: tf.test_acc_is_minus_gradient_of_potential(o, 0)),
