@@ -32,6 +32,21 @@ FLOPS_PER_INTERACTION = 41
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 vector (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_FP64_TFLOPS = 78.6
 
+# HBM bytes per force launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
+# plain-copy calibration: x2.0 fetch, x1.0 write), for the kernel sources whose hash
+# is the key.  Reported only while the sources are unchanged; null otherwise.
+TRAFFIC = {("41aa275a3b8e7192", "mixed", 1 << 20): 2.718e9 + 1.481e8}
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_1411_5234_amd", "csrc")
+    for f in ("nb_internal.h", "force.hip", "api.hip"):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -45,11 +60,12 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
     ap.add_argument("--no-energy", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve", "copy"], default="step",
                     help="step: the headline (default); sweep: active-block sizes 2^6..2^16 at "
                          "N=65536 (Salpeter), FP64 vs mixed, planned j-split vs none; integrate: "
                          "block-step integration of the N=2^20 Plummer sphere to t_end with energy "
-                         "drift; serve: Poisson request stream through the continuous-batching server")
+                         "drift; serve: Poisson request stream through the continuous-batching server; "
+                         "copy: a plain 1 GiB device copy (calibrates the HBM traffic counters)")
     ap.add_argument("--t-end", type=float, default=0.125)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
@@ -71,6 +87,8 @@ def main():
         return mode_integrate(args)
     if args.mode == "serve":
         return mode_serve(args)
+    if args.mode == "copy":
+        return mode_copy(args)
 
     import numpy as np
     import torch
@@ -184,7 +202,8 @@ def main():
                    "shared_step": h},
         "fp32_peak_frac": value * FLOPS_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / peak, "traffic": None,
+                     "frac": achieved_tflops / peak,
+                     "traffic": TRAFFIC.get((_kernel_source_hash(), args.precision, n)),
                      "kernel": "force_%s_kernel" % args.precision,
                      "kernel_ms_avg": float(np.mean(force_ms)),
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
@@ -210,6 +229,22 @@ def _timed_force(ctx, system, idx, m, eps, precision, acc, jerk, plan=None, reps
         ctx.sync()
         best = min(best, e0.elapsed_time(e1) / 1e3)
     return best
+
+
+def mode_copy(args):
+    """Plain device-to-device copy of 1 GiB, three times: the calibration kernel for
+    the FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes 2^30 bytes)."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": 1 << 30, "bytes_written_per_copy": 1 << 30,
+                      "GB_per_s": 2 * (1 << 30) / dt / 1e9}), flush=True)
 
 
 def mode_sweep(args):
@@ -318,19 +353,29 @@ def mode_serve(args):
                                      ic_seed_base=spec["base"])
 
     ctx = Context(0)
+    last = [time.perf_counter()]
+
+    def progress(srv):
+        now = time.perf_counter()
+        if now - last[0] > 10:
+            last[0] = now
+            print("  iteration %d: %d resident, %d queued, %d done" % (
+                srv.iterations, len(srv.slots), len(srv.queue), len(srv.results)),
+                file=sys.stderr, flush=True)
+
     out = {"metric": "ensemble solves/s and p50/p99 latency", "mode": "serve",
            "config": {"workload": args.stream, "requests": args.requests, "slots": args.slots,
                       "precision": args.precision, **{k: v for k, v in spec.items() if k != "base"}}}
     srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
     t0 = time.perf_counter()
-    res = srv.run(stream(0.0, args.requests), realtime=False)
+    res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
     closed = summarize(res, time.perf_counter() - t0)
     out["closed_batch"] = closed
     print("closed batch: %s" % closed, file=sys.stderr, flush=True)
     rate = 0.8 * closed["solves_per_s"]
     srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
     t0 = time.perf_counter()
-    res = srv.run(stream(rate, args.requests), realtime=True)
+    res = srv.run(stream(rate, args.requests), realtime=True, on_iteration=progress)
     poisson = summarize(res, time.perf_counter() - t0)
     poisson["arrival_rate_per_s"] = rate
     out["poisson"] = poisson
@@ -339,7 +384,7 @@ def mode_serve(args):
     if k > 0:
         srv = Server(ctx, precision="fp64", max_slots=1, energy=True)
         t0 = time.perf_counter()
-        res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
+        res = srv.run(stream(0.0, args.requests)[:k], realtime=False, on_iteration=progress)
         base = summarize(res, time.perf_counter() - t0)
         base["requests_served"] = k
         out["one_at_a_time_fp64"] = base

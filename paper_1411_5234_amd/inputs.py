@@ -238,11 +238,15 @@ class Request:
 def request_stream(count: int, seed: int, n_lo: int, n_hi: int, rate: float,
                    eps: float, t_end: float, kind: str = "plummer",
                    ic_seed_base: int = 0) -> list[Request]:
-    """Poisson stream: exponential gaps at `rate` per second, N log-uniform in [n_lo, n_hi]."""
-    rng = _rng(seed)
-    gaps = rng.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
+    """Poisson stream: exponential gaps at `rate` per second, N log-uniform in [n_lo, n_hi].
+
+    Sizes and arrival gaps come from independent streams of the seed, so the same seed
+    gives the same requests at every rate (rate <= 0: all arrive at t = 0)."""
+    size_rng, gap_rng = (np.random.Generator(np.random.PCG64(s))
+                         for s in np.random.SeedSequence(int(seed)).spawn(2))
+    ns = np.rint(np.exp(size_rng.uniform(math.log(n_lo), math.log(n_hi), count))).astype(np.int64)
+    gaps = gap_rng.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
     arr = np.cumsum(gaps) - (gaps[0] if count else 0.0)
-    ns = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), count))).astype(np.int64)
     ns = np.clip(ns, n_lo, n_hi)
     return [Request(k, float(arr[k]), int(ns[k]), ic_seed_base + k, eps, t_end, kind)
             for k in range(count)]

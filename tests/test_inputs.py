@@ -88,3 +88,6 @@ def test_request_stream_shape():
     assert np.median(ns) == pytest.approx(math.sqrt(256 * 32768), rel=0.1)
     again = inputs.request_stream(4096, 4, 256, 32768, rate=100.0, eps=1e-3, t_end=1.0)
     assert [r.n for r in again] == list(ns)
+    # the same requests at any arrival rate (closed batch vs Poisson replay)
+    closed = inputs.request_stream(4096, 4, 256, 32768, rate=0.0, eps=1e-3, t_end=1.0)
+    assert [r.n for r in closed] == list(ns) and all(r.arrival == 0.0 for r in closed)
