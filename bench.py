@@ -33,16 +33,17 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 vector (256 CU x 2.4 GHz x 256 
 PEAK_FP64_TFLOPS = 78.6
 
 # HBM bytes per force launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
-# plain-copy calibration: x2.0 fetch, x1.0 write), for the kernel sources whose hash
-# is the key.  Reported only while the sources are unchanged; null otherwise.
-TRAFFIC = {("41aa275a3b8e7192", "mixed", 1 << 20): 2.718e9 + 1.481e8}
+# plain-copy calibration: x2.0 fetch, x1.0 write), keyed by the hash of the force
+# kernel's sources, the precision, N and the launch plan.  Reported only for that
+# exact kernel and launch; null otherwise.
+TRAFFIC = {("b5e0dcf384027a92", "mixed", 1 << 20, (2, 1, 4)): 2.770e9 + 2.013e8}
 
 
 def _kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(ROOT, "paper_1411_5234_amd", "csrc")
-    for f in ("nb_internal.h", "force.hip", "api.hip"):
+    for f in ("nb_internal.h", "force.hip"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -93,7 +94,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd import _lib, inputs
     from paper_1411_5234_amd.nbody import Context, Integrator, Params, System
 
     n = args.n
@@ -203,7 +204,8 @@ def main():
         "fp32_peak_frac": value * FLOPS_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak,
-                     "traffic": TRAFFIC.get((_kernel_source_hash(), args.precision, n)),
+                     "traffic": TRAFFIC.get((_kernel_source_hash(), args.precision, n,
+                                             _lib.force_plan(n, n, args.precision))),
                      "kernel": "force_%s_kernel" % args.precision,
                      "kernel_ms_avg": float(np.mean(force_ms)),
                      "flops_per_interaction": FLOPS_PER_INTERACTION,

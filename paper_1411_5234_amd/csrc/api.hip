@@ -205,19 +205,20 @@ struct Plan {
 // is split into B chunks (the paper's Bfactor).  The plan
 //  - uses S > 1 only as far as needed to fill a workgroup's lanes when the
 //    active block is small (S = 1 keeps the LDS reads broadcasts);
-//  - splits j into B chunks while the grid has fewer than about 2^20 lanes --
-//    four times the lanes the force kernels keep resident on 256 CUs, so the
+//  - splits j into B chunks while the grid has fewer than about 2^21 lanes --
+//    eight times the lanes the force kernels keep resident on 256 CUs, so the
 //    last round of workgroups is a small part of the run -- keeping at least
 //    2048 j-bodies per chunk, so the FP64 partial sums (48 B per body and
 //    chunk) stay a few per cent of the pair work;
-//  - then raises S while lanes are still short and every lane keeps at least
-//    128 j-bodies.
+//  - then raises S while the grid has fewer than about 2^20 lanes and every
+//    lane keeps at least 128 j-bodies (S > 1 turns LDS broadcasts into per-lane
+//    reads, so it is used less eagerly than the j-split).
 // Large mixed-precision blocks hold two i-bodies per lane (half the LDS reads
 // per interaction).  Pure function of (nj, m, precision): a system's results
 // never depend on what else runs.
 Plan make_plan(int64_t nj, int32_t m, int precision)
 {
-    const int64_t target_lanes = (int64_t)1 << 20;
+    const int64_t target_lanes = (int64_t)1 << 21;
     const int64_t min_j_lane = 128, min_j_chunk = 2048;
     Plan p{(precision == NB_MIXED && m >= (1 << 16)) ? 2 : 1, 1, 1};
     if (m <= 0 || nj <= 0) return p;
@@ -229,7 +230,7 @@ Plan make_plan(int64_t nj, int32_t m, int precision)
            nj / (p.s * b * 2) >= min_j_lane && b < 1024)
         b *= 2;
     p.b = (int)b;
-    while (p.s < 64 && groups * p.s * b < target_lanes && nj / (p.s * 4 * b) >= min_j_lane)
+    while (p.s < 64 && groups * p.s * b < target_lanes / 2 && nj / (p.s * 4 * b) >= min_j_lane)
         p.s *= 4;
     return p;
 }

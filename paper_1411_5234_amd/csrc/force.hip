@@ -45,8 +45,73 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// One j-body of a mixed-precision tile, read from LDS.
+struct JMixed {
+    double x, y, z;
+    float vx, vy, vz, m;
+};
+
+// Acceleration and jerk terms of one j-body on IL i-bodies, FP32 after the FP64
+// position difference, added to the FP32 run accumulators.
+template <int IL>
+__device__ __forceinline__ void pair_mixed(const JMixed &j, const double (&xi)[IL],
+                                           const double (&yi)[IL], const double (&zi)[IL],
+                                           const float (&vxi)[IL], const float (&vyi)[IL],
+                                           const float (&vzi)[IL], float eps2,
+                                           float (&a32)[IL][3], float (&j32)[IL][3])
+{
+#pragma unroll
+    for (int u = 0; u < IL; ++u) {
+        const float dx = (float)(j.x - xi[u]);
+        const float dy = (float)(j.y - yi[u]);
+        const float dz = (float)(j.z - zi[u]);
+        const float dvx = j.vx - vxi[u], dvy = j.vy - vyi[u], dvz = j.vz - vzi[u];
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+        const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float rinv2 = rinv * rinv;
+        const float mr3 = j.m * rinv * rinv2;
+        const float al = -3.0f * rv * rinv2;
+        a32[u][0] = fmaf(mr3, dx, a32[u][0]);
+        a32[u][1] = fmaf(mr3, dy, a32[u][1]);
+        a32[u][2] = fmaf(mr3, dz, a32[u][2]);
+        j32[u][0] = fmaf(mr3, fmaf(al, dx, dvx), j32[u][0]);
+        j32[u][1] = fmaf(mr3, fmaf(al, dy, dvy), j32[u][1]);
+        j32[u][2] = fmaf(mr3, fmaf(al, dz, dvz), j32[u][2]);
+    }
+}
+
+#ifndef NBK_KAHAN
+#define NBK_KAHAN 0
+#endif
+#ifndef NBK_MIXED_WAVES
+#define NBK_MIXED_WAVES 1
+#endif
+#ifndef NBK_PREFETCH
+#define NBK_PREFETCH 1
+#endif
+
+// Running total of the FP32 run sums: FP64, or (NBK_KAHAN) an FP32 Kahan pair.
+struct Total {
+#if NBK_KAHAN
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float v)
+    {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+#else
+    double s = 0.0;
+    __device__ __forceinline__ void add(float v) { s += (double)v; }
+    __device__ __forceinline__ double value() const { return s; }
+#endif
+};
+
 template <int IL, int S, int F>
-__global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, const int64_t *starts,
+__global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const Item *items, const int64_t *starts,
                                                          int n_items)
 {
     __shared__ double sx[TILE], sy[TILE], sz[TILE];
@@ -69,7 +134,7 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, cons
 
     double xi[IL], yi[IL], zi[IL];
     float vxi[IL], vyi[IL], vzi[IL];
-    double A[IL][3], J[IL][3];
+    Total A[IL][3], J[IL][3];
 #pragma unroll
     for (int u = 0; u < IL; ++u) {
         const int64_t k = kbase + u;
@@ -83,8 +148,6 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, cons
         }
         xi[u] = xp[i]; yi[u] = yp[i]; zi[u] = zp[i];
         vxi[u] = vx32[i]; vyi[u] = vy32[i]; vzi[u] = vz32[i];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { A[u][c] = 0.0; J[u][c] = 0.0; }
     }
 
     for (int64_t jt = jb; jt < je; jt += TILE) {
@@ -108,48 +171,44 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, cons
             for (int u = 0; u < IL; ++u)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; }
+#if NBK_PREFETCH
+            JMixed cur{sx[kk + s], sy[kk + s], sz[kk + s], svx[kk + s], svy[kk + s], svz[kk + s],
+                       sm[kk + s]};
+#pragma unroll NBK_UNROLL
+            for (int f = 0; f < F; ++f) {
+                const int qn = kk + (f + 1 < F ? f + 1 : f) * S + s;
+                const JMixed nxt{sx[qn], sy[qn], sz[qn], svx[qn], svy[qn], svz[qn], sm[qn]};
+                pair_mixed<IL>(cur, xi, yi, zi, vxi, vyi, vzi, eps2, a32, j32);
+                cur = nxt;
+            }
+#else
 #pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
                 const int q = kk + f * S + s;
-                const double xj = sx[q], yj = sy[q], zj = sz[q];
-                const float vxj = svx[q], vyj = svy[q], vzj = svz[q], mj = sm[q];
-#pragma unroll
-                for (int u = 0; u < IL; ++u) {
-                    const float dx = (float)(xj - xi[u]);
-                    const float dy = (float)(yj - yi[u]);
-                    const float dz = (float)(zj - zi[u]);
-                    const float dvx = vxj - vxi[u], dvy = vyj - vyi[u], dvz = vzj - vzi[u];
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-                    const float rinv = __builtin_amdgcn_rsqf(r2);
-                    const float rinv2 = rinv * rinv;
-                    const float mr3 = mj * rinv * rinv2;
-                    const float al = -3.0f * rv * rinv2;
-                    a32[u][0] = fmaf(mr3, dx, a32[u][0]);
-                    a32[u][1] = fmaf(mr3, dy, a32[u][1]);
-                    a32[u][2] = fmaf(mr3, dz, a32[u][2]);
-                    j32[u][0] = fmaf(mr3, fmaf(al, dx, dvx), j32[u][0]);
-                    j32[u][1] = fmaf(mr3, fmaf(al, dy, dvy), j32[u][1]);
-                    j32[u][2] = fmaf(mr3, fmaf(al, dz, dvz), j32[u][2]);
-                }
+                const JMixed cur{sx[q], sy[q], sz[q], svx[q], svy[q], svz[q], sm[q]};
+                pair_mixed<IL>(cur, xi, yi, zi, vxi, vyi, vzi, eps2, a32, j32);
             }
+#endif
 #pragma unroll
             for (int u = 0; u < IL; ++u)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    A[u][c] += (double)a32[u][c];
-                    J[u][c] += (double)j32[u][c];
+                    A[u][c].add(a32[u][c]);
+                    J[u][c].add(j32[u][c]);
                 }
         }
     }
 
 #pragma unroll
     for (int u = 0; u < IL; ++u) {
+        double At[3], Jt[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            At[c] = A[u][c].value();
+            Jt[c] = J[u][c].value();
             if constexpr (S > 1) {
-                A[u][c] = group_sum<S>(A[u][c]);
-                J[u][c] = group_sum<S>(J[u][c]);
+                At[c] = group_sum<S>(At[c]);
+                Jt[c] = group_sum<S>(Jt[c]);
             }
         }
         const int64_t k = kbase + u;
@@ -159,8 +218,8 @@ __global__ __launch_bounds__(WG) void force_mixed_kernel(const Item *items, cons
             double *oj = p.b > 1 ? p.part + bidx * six_m + 3 * (int64_t)p.m : p.jerk;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                oa[c * (int64_t)p.m + k] = A[u][c];
-                oj[c * (int64_t)p.m + k] = J[u][c];
+                oa[c * (int64_t)p.m + k] = At[c];
+                oj[c * (int64_t)p.m + k] = Jt[c];
             }
         }
     }
