@@ -396,6 +396,20 @@ def mode_serve(args):
         t0 = time.perf_counter()
         res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
         out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
+    if args.stream == "c5":
+        # the same requests in FP64 and in mixed precision: energy error per request
+        per = {}
+        for prec in ("fp64", "mixed"):
+            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True)
+            res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
+            per[prec] = {r.rid: r for r in res}
+        rows = []
+        for rid in sorted(per["fp64"]):
+            a, b = per["fp64"][rid], per["mixed"].get(rid)
+            if a.error is None and b is not None and b.error is None:
+                rows.append({"rid": rid, "n": a.n, "energy_error_fp64": a.energy_error,
+                             "energy_error_mixed": b.energy_error})
+        out["energy_error_per_request"] = rows
     ctx.close()
     out["value"] = poisson["solves_per_s"]
     out["unit"] = "solves/s"

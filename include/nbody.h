@@ -177,11 +177,12 @@ typedef struct {
     int32_t *status;     /* device word for this item's kernel errors, or NULL       */
     double eps;          /* Plummer softening, > 0                                   */
     double t_next;       /* block time: set by nb_select_active_batch                */
+    double t_end;        /* nb_step_batch: the item is done once t_next > t_end       */
     int32_t m;           /* active block size: set by nb_select_active_batch         */
     int32_t startup;     /* 1: the t = 0 step (all bodies active, no selection)      */
     int32_t error;       /* host: nb_status of this item's latched errors, set by
                             nb_select_active_batch (the item's word is then cleared) */
-    int32_t reserved;
+    int32_t done;        /* host: set to 1 by nb_step_batch when t_next > t_end      */
 } nb_batch_item;
 
 /* a1 for every item (Sec. 2 item 2).  Startup items get m = n, t_next = 0 and no
@@ -197,6 +198,16 @@ nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t
  * nb_init_steps for startup items. */
 nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
                            double eta, double eta_s, double dt_max, double dt_min);
+
+/* One iteration of an ensemble loop in one call: a1 for every item (waits for
+ * the stream), then, for every item without an error whose next block time is
+ * not past its t_end, a2 + a3 + a4 + a5 as in the four calls above (startup
+ * items: force + startup steps, after which their startup flag is cleared).
+ * Items past t_end get done = 1 and no work; items with an error get no work.
+ * Host fields t_next, m, error, done and startup are updated in place. */
+nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
+                        nb_precision precision, double eta, double eta_s, double dt_max,
+                        double dt_min);
 
 /* Library version string. */
 const char *nb_version(void);

@@ -27,7 +27,7 @@ STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
            "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
-           "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch"]
+           "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch"]
 
 
 class NbSystem(C.Structure):
@@ -37,8 +37,8 @@ class NbSystem(C.Structure):
 class NbBatchItem(C.Structure):
     _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("acc", C.c_void_p),
                 ("jerk", C.c_void_p), ("status", C.c_void_p), ("eps", C.c_double),
-                ("t_next", C.c_double), ("m", C.c_int32), ("startup", C.c_int32),
-                ("error", C.c_int32), ("reserved", C.c_int32)]
+                ("t_next", C.c_double), ("t_end", C.c_double), ("m", C.c_int32),
+                ("startup", C.c_int32), ("error", C.c_int32), ("done", C.c_int32)]
 
 
 class NbError(RuntimeError):
@@ -81,6 +81,7 @@ def load() -> C.CDLL:
         "nb_predict_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32]),
         "nb_force_active_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, C.c_int]),
         "nb_correct_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, f64, f64, f64, f64]),
+        "nb_step_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, C.c_int, f64, f64, f64, f64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

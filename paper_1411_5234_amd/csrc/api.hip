@@ -14,7 +14,7 @@
 
 #include "nb_internal.h"
 
-#define NB_VERSION "0.2.0"
+#define NB_VERSION "0.3.0"
 
 using nbk::Item;
 using nbk::SelResult;
@@ -429,6 +429,87 @@ Item batch_item(nb_ctx *ctx, const nb_batch_item &b)
     return it;
 }
 
+// a1 for every item (see nb_select_active_batch).
+nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items)
+{
+    std::vector<Item> dev;
+    std::vector<int32_t> which;
+    for (int32_t k = 0; k < n_items; ++k) {
+        NB_TRY(check_item(ctx, items[k], false));
+        items[k].error = NB_OK;
+        if (items[k].sys.n == 0) {
+            items[k].m = 0;
+            items[k].t_next = INFINITY;
+            continue;
+        }
+        if (items[k].startup) {
+            items[k].m = (int32_t)items[k].sys.n;
+            items[k].t_next = 0.0;
+        }
+        // a startup item runs the selection too (its result is ignored), so that
+        // every item's status word is collected by the same launch
+        Item it = base_item(ctx, items[k].sys);
+        if (items[k].status) it.status = items[k].status;
+        it.i_idx = items[k].i_idx;
+        dev.push_back(it);
+        which.push_back(k);
+    }
+    std::vector<SelResult> res;
+    NB_TRY(run_select(ctx, dev, res));
+    for (size_t q = 0; q < which.size(); ++q) {
+        nb_batch_item &b = items[which[q]];
+        if (!b.startup) {
+            b.t_next = res[q].t_next;
+            b.m = res[q].m;
+        }
+        b.error = status_code(res[q].status);
+    }
+    return NB_OK;
+}
+
+// a2 .. a5 for the items flagged in `run` (see the batch entry points).
+nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
+                        const std::vector<char> &run, nb_precision precision, double eta,
+                        double eta_s, double dt_max, double dt_min)
+{
+    std::vector<Item> pred, cor, ini;
+    std::vector<int64_t> pblocks, cblocks, iblocks;
+    std::vector<ForceJob> jobs;
+    for (int32_t k = 0; k < n_items; ++k) {
+        if (!run[k] || items[k].sys.n == 0) continue;
+        if (precision == NB_MIXED && !items[k].sys.vxp32)
+            return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
+        const Item it = batch_item(ctx, items[k]);
+        const int64_t nb = (items[k].sys.n + nbk::WG - 1) / nbk::WG;
+        if (items[k].startup) {
+            ini.push_back(it);
+            iblocks.push_back(nb);
+        } else {
+            pred.push_back(it);
+            pblocks.push_back(nb);
+            if (it.m > 0) {
+                cor.push_back(it);
+                cblocks.push_back((it.m + nbk::WG - 1) / nbk::WG);
+            }
+        }
+        ForceJob job;
+        job.it = it;
+        job.plan = make_plan(items[k].sys.n, it.m, precision);
+        jobs.push_back(job);
+    }
+    Table t;
+    NB_TRY(make_table(ctx, pred, pblocks, &t));
+    hipError_t e = nbk::launch_predict(t, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
+    NB_TRY(run_force(ctx, jobs, precision));
+    NB_TRY(make_table(ctx, cor, cblocks, &t));
+    e = nbk::launch_correct(t, eta, dt_max, dt_min, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "correct launch");
+    NB_TRY(make_table(ctx, ini, iblocks, &t));
+    e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
+}
+
 nb_status check_step_params(nb_ctx *ctx, double eta, double dt_max, double dt_min)
 {
     if (!(eta > 0.0) || !(dt_max > 0.0) || !(dt_min > 0.0) || dt_min > dt_max)
@@ -632,39 +713,7 @@ nb_status nb_select_active_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_it
 {
     if (!ctx) return NB_EINVAL;
     if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
-    std::vector<Item> dev;
-    std::vector<int32_t> which;
-    for (int32_t k = 0; k < n_items; ++k) {
-        NB_TRY(check_item(ctx, items[k], false));
-        items[k].error = NB_OK;
-        if (items[k].sys.n == 0) {
-            items[k].m = 0;
-            items[k].t_next = INFINITY;
-            continue;
-        }
-        if (items[k].startup) {
-            items[k].m = (int32_t)items[k].sys.n;
-            items[k].t_next = 0.0;
-        }
-        // a startup item runs the selection too (its result is ignored), so that
-        // every item's status word is collected by the same launch
-        Item it = base_item(ctx, items[k].sys);
-        if (items[k].status) it.status = items[k].status;
-        it.i_idx = items[k].i_idx;
-        dev.push_back(it);
-        which.push_back(k);
-    }
-    std::vector<SelResult> res;
-    NB_TRY(run_select(ctx, dev, res));
-    for (size_t q = 0; q < which.size(); ++q) {
-        nb_batch_item &b = items[which[q]];
-        if (!b.startup) {
-            b.t_next = res[q].t_next;
-            b.m = res[q].m;
-        }
-        b.error = status_code(res[q].status);
-    }
-    return NB_OK;
+    return select_items(ctx, items, n_items);
 }
 
 nb_status nb_predict_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items)
@@ -734,6 +783,35 @@ nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_it
     NB_TRY(make_table(ctx, ini, iblocks, &t));
     e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
+}
+
+nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
+                        nb_precision precision, double eta, double eta_s, double dt_max,
+                        double dt_min)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    if (precision != NB_FP64 && precision != NB_MIXED)
+        return fail(ctx, NB_EINVAL, "unknown precision");
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
+    if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
+    NB_TRY(select_items(ctx, items, n_items));
+    std::vector<char> run(n_items, 0);
+    for (int32_t k = 0; k < n_items; ++k) {
+        nb_batch_item &b = items[k];
+        b.done = 0;
+        if (b.error != NB_OK || b.sys.n == 0) continue;
+        if (!b.startup && b.t_next > b.t_end) {
+            b.done = 1;
+            continue;
+        }
+        NB_TRY(check_item(ctx, b, true));
+        run[k] = 1;
+    }
+    NB_TRY(advance_items(ctx, items, n_items, run, precision, eta, eta_s, dt_max, dt_min));
+    for (int32_t k = 0; k < n_items; ++k)
+        if (run[k]) items[k].startup = 0;
+    return NB_OK;
 }
 
 }  // extern "C"

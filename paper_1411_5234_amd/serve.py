@@ -3,9 +3,8 @@
 Each request is an initial condition to integrate to t_end with the Hermite-4
 block-step scheme.  The server keeps every admitted system's state resident in
 HBM and advances ALL resident systems together: one iteration is one block step
-of every resident system, done with one ragged batched launch per phase through
-the C ABI (nb_select_active_batch, nb_predict_batch, nb_force_active_batch,
-nb_correct_batch).  Requests that arrive while others run are admitted between
+of every resident system, done by one native call (nb_step_batch: selection,
+then one ragged batched launch per phase for predict, force and correct).  Requests that arrive while others run are admitted between
 iterations as slots and device memory free up; a finished or failed system is
 retired at once and its memory is released.  A failing system (non-finite
 values, a step below dt_min) is reported alone; the others go on.
@@ -74,6 +73,7 @@ class _Slot:
         self.item.jerk = self.jerk.data_ptr()
         self.item.status = self.status.data_ptr()
         self.item.eps = float(req.eps)
+        self.item.t_end = float(req.t_end)
         self.item.startup = 1
         self.result = Result(req.rid, self.n, req.arrival, now, float("nan"))
 
@@ -82,6 +82,46 @@ def footprint_bytes(n: int, precision: str = "mixed") -> int:
     """Device bytes one resident system of n bodies holds (state + work buffers)."""
     per_body = 8 * 21 + (16 if precision == "mixed" else 0) + 4 + 48
     return per_body * max(n, 1) + 4 + 1024
+
+
+class Admission:
+    """Admission policy and slot/memory accounting of the server (no device work).
+
+    Requests wait in FIFO order; the head is admitted while a slot is free and its
+    footprint fits the budget next to the resident systems.  A request that could
+    never fit is refused at submit.  Admission is in arrival order: a large request
+    at the head is not overtaken by smaller ones behind it.
+    """
+
+    def __init__(self, budget: int, max_slots: int, footprint):
+        if max_slots < 1:
+            raise ValueError("max_slots must be >= 1")
+        self.budget = int(budget)
+        self.max_slots = int(max_slots)
+        self.footprint = footprint
+        self.queue: deque = deque()
+        self.resident: dict = {}          # key -> bytes
+        self.used = 0
+
+    def submit(self, req):
+        if self.footprint(req) > self.budget:
+            raise ValueError("request of n=%d does not fit the memory budget" % req.n)
+        self.queue.append(req)
+
+    def admit_next(self):
+        """Pop and return the next admissible request (or None); reserve its bytes."""
+        if not self.queue or len(self.resident) >= self.max_slots:
+            return None
+        need = self.footprint(self.queue[0])
+        if self.used + need > self.budget:
+            return None
+        req = self.queue.popleft()
+        self.resident[id(req)] = need
+        self.used += need
+        return req
+
+    def release(self, req):
+        self.used -= self.resident.pop(id(req))
 
 
 class Server:
@@ -105,41 +145,45 @@ class Server:
         if memory_budget is None:
             free, _ = torch.cuda.mem_get_info(self.ctx.device)
             memory_budget = int(0.9 * free)
-        self.budget = int(memory_budget)
-        self.max_slots = int(max_slots)
+        self.adm = Admission(memory_budget, max_slots,
+                             lambda r: footprint_bytes(r.n, self.precision))
         self.eta, self.eta_s, self.dt_max, self.dt_min = eta, eta_s, dt_max, dt_min
         self.keep_state = keep_state
         self.energy = energy
-        self.queue: deque = deque()
         self.slots: list[_Slot] = []
-        self.used = 0
         self.results: list[Result] = []
         self.iterations = 0
         self.t0 = None
 
     # ---- admission -----------------------------------------------------------
+    @property
+    def budget(self):
+        return self.adm.budget
+
+    @property
+    def used(self):
+        return self.adm.used
+
+    @property
+    def queue(self):
+        return self.adm.queue
+
     def submit(self, req):
         if req.t_end / self.dt_max != math.floor(req.t_end / self.dt_max):
             raise ValueError("t_end must be a multiple of dt_max")
-        if footprint_bytes(req.n, self.precision) > self.budget:
-            raise ValueError("request of n=%d does not fit the memory budget" % req.n)
-        self.queue.append(req)
+        self.adm.submit(req)
 
     def _now(self):
         return time.perf_counter() - self.t0
 
     def _admit(self):
-        while self.queue and len(self.slots) < self.max_slots:
-            req = self.queue[0]
-            need = footprint_bytes(req.n, self.precision)
-            if self.used + need > self.budget:
-                break
-            self.queue.popleft()
+        while True:
+            req = self.adm.admit_next()
+            if req is None:
+                return
             slot = _Slot(req, self.device, self.precision, self._now())
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
-            slot.bytes = need
-            self.used += need
             self.slots.append(slot)
 
     def _retire(self, slot: _Slot, error: str | None):
@@ -152,7 +196,7 @@ class Server:
                 r.final = slot.sys.state_numpy()
         r.finished = self._now()
         self.results.append(r)
-        self.used -= slot.bytes
+        self.adm.release(slot.req)
         self.slots.remove(slot)
 
     # ---- one iteration: one block step of every resident system ---------------
@@ -161,38 +205,28 @@ class Server:
             raise NbError(rc, self.L.nb_last_error(self.ctx.h).decode())
 
     def step(self):
-        """Select every resident system's next block; retire finished or failed
-        systems; then predict, force and correct all the others in one launch
-        per phase."""
+        """One iteration: every resident system advances one block step in one
+        native call (select, then predict, force and correct for every system not
+        yet past its t_end, one launch per phase); finished or failed systems are
+        retired."""
         slots = list(self.slots)
         if not slots:
             return
         items = (NbBatchItem * len(slots))(*[s.item for s in slots])
-        self._check(self.L.nb_select_active_batch(self.ctx.h, items, len(slots)))
-        active = []
+        self._check(self.L.nb_step_batch(self.ctx.h, items, len(slots), self.prec_code, self.eta,
+                                         self.eta_s, self.dt_max, self.dt_min))
         for s, it in zip(slots, items):
             if it.error != 0:
                 self._retire(s, _lib.STATUS.get(it.error, str(it.error)))
-            elif not it.startup and it.t_next > s.req.t_end:
+            elif it.done:
                 self._retire(s, None)
             else:
-                s.item.t_next, s.item.m = it.t_next, it.m
-                active.append(s)
-        if not active:
-            return
-        run = (NbBatchItem * len(active))(*[s.item for s in active])
-        k = len(active)
-        self._check(self.L.nb_predict_batch(self.ctx.h, run, k))
-        self._check(self.L.nb_force_active_batch(self.ctx.h, run, k, self.prec_code))
-        self._check(self.L.nb_correct_batch(self.ctx.h, run, k, self.eta, self.eta_s,
-                                            self.dt_max, self.dt_min))
-        for s in active:
-            if s.item.startup:
-                s.result.interactions += s.n * s.n
-                s.item.startup = 0
-            else:
-                s.result.steps += 1
-                s.result.interactions += s.item.m * s.n
+                if s.item.startup:
+                    s.result.interactions += s.n * s.n
+                else:
+                    s.result.steps += 1
+                    s.result.interactions += it.m * s.n
+                s.item.t_next, s.item.m, s.item.startup = it.t_next, it.m, it.startup
         self.iterations += 1
 
     # ---- driving a request stream ------------------------------------------------

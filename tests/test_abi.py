@@ -72,11 +72,11 @@ def test_struct_layouts_match_the_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "nbody.h"\n'
         'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(nb_system), '
         'sizeof(nb_batch_item), offsetof(nb_batch_item, status), offsetof(nb_batch_item, eps), '
-        'offsetof(nb_batch_item, m), offsetof(nb_batch_item, error)); return 0; }\n')
+        'offsetof(nb_batch_item, m), offsetof(nb_batch_item, done)); return 0; }\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     B = _lib.NbBatchItem
     want = [ctypes.sizeof(_lib.NbSystem), ctypes.sizeof(B), B.status.offset, B.eps.offset,
-            B.m.offset, B.error.offset]
+            B.m.offset, B.done.offset]
     assert got == want

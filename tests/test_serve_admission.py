@@ -1,0 +1,103 @@
+"""Admission policy and slot/memory accounting of the server, on the CPU.
+
+A test-only stub stands in for the device: each admitted request needs a fixed
+number of iterations.  The policy must keep the slot and memory limits at every
+iteration, admit in arrival order as soon as capacity frees up (continuous
+batching), and refuse requests that could never fit.
+"""
+from dataclasses import dataclass
+
+import pytest
+
+from paper_1411_5234_amd.serve import Admission, footprint_bytes
+
+
+@dataclass
+class Req:
+    rid: int
+    n: int
+    work: int          # iterations the stub needs for this request
+
+
+def fp(r):
+    return 100 * r.n
+
+
+def run_stub(adm, reqs, arrivals):
+    """Drive the policy: at iteration t the requests with arrival <= t are
+    submitted; every resident request does one unit of work per iteration."""
+    pending = sorted(zip(arrivals, reqs), key=lambda x: x[0])
+    left = {}
+    done, log = [], []
+    t = 0
+    while pending or adm.queue or left:
+        while pending and pending[0][0] <= t:
+            adm.submit(pending.pop(0)[1])
+        while True:
+            r = adm.admit_next()
+            if r is None:
+                break
+            left[r.rid] = (r, r.work)
+        log.append((t, len(left), adm.used, [q.rid for q in adm.queue]))
+        assert len(left) <= adm.max_slots and adm.used <= adm.budget
+        for rid in list(left):
+            r, w = left[rid]
+            if w == 1:
+                del left[rid]
+                adm.release(r)
+                done.append((rid, t))
+            else:
+                left[rid] = (r, w - 1)
+        t += 1
+        assert t < 10000
+    return done, log
+
+
+def test_slots_limit_and_fifo_order():
+    adm = Admission(budget=10 ** 9, max_slots=3, footprint=fp)
+    reqs = [Req(k, 10, work=5) for k in range(7)]
+    done, log = run_stub(adm, reqs, [0] * 7)
+    assert sorted(r for r, _ in done) == list(range(7))
+    assert max(k for _, k, _, _ in log) == 3
+    # continuous batching: the fourth request starts the iteration after a slot frees
+    assert [t for r, t in done] == [4, 4, 4, 9, 9, 9, 14]
+
+
+def test_memory_budget_and_head_of_line():
+    # budget fits one big (n=50) or five small (n=10) requests
+    adm = Admission(budget=5000, max_slots=100, footprint=fp)
+    reqs = [Req(0, 10, 3), Req(1, 50, 3), Req(2, 10, 1), Req(3, 10, 1)]
+    done, log = run_stub(adm, reqs, [0, 0, 0, 0])
+    assert all(u <= 5000 for _, _, u, _ in log)
+    order = [r for r, _ in done]
+    # the big request at the head of the queue is not overtaken by the small ones
+    assert order.index(1) < order.index(2) and order.index(1) < order.index(3)
+    assert adm.used == 0 and not adm.resident
+
+
+def test_arrivals_while_running_are_admitted():
+    adm = Admission(budget=10 ** 9, max_slots=2, footprint=fp)
+    reqs = [Req(0, 10, 10), Req(1, 10, 2), Req(2, 10, 2), Req(3, 10, 2)]
+    done, log = run_stub(adm, reqs, [0, 0, 3, 3])
+    finished = dict(done)
+    assert finished[1] == 1          # request 1 shares the device with request 0
+    assert finished[2] == 4 and finished[3] == 6   # 2 starts at t=3 beside 0; 3 waits for a slot
+    assert finished[0] == 9
+
+
+def test_refuses_what_never_fits():
+    adm = Admission(budget=1000, max_slots=4, footprint=fp)
+    with pytest.raises(ValueError):
+        adm.submit(Req(0, 11, 1))
+    adm.submit(Req(1, 10, 1))
+    assert adm.admit_next().rid == 1
+    with pytest.raises(ValueError):
+        Admission(budget=1000, max_slots=0, footprint=fp)
+
+
+def test_footprint_covers_the_device_arrays():
+    from paper_1411_5234_amd._lib import FIELDS32, FIELDS64
+    n = 1000
+    # state rows + FP32 copies + i_idx + acc/jerk (3n doubles each)
+    need = 8 * len(FIELDS64) * n + 4 * len(FIELDS32) * n + 4 * n + 2 * 8 * 3 * n
+    assert footprint_bytes(n, "mixed") >= need
