@@ -63,6 +63,16 @@ def lib():
         L.orc_correct.argtypes = [C.c_int64, C.c_int64, _ip, C.c_double, _dp, _dp, _dp, _dp,
                                   _dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                   C.c_double, C.c_void_p]
+        L.orc_force6.restype = C.c_int
+        L.orc_force6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
+                                 C.c_int64, C.c_double, _dp, _dp, _dp]
+        L.orc_predict6.restype = None
+        L.orc_predict6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
+                                   _dp, _dp, _dp]
+        L.orc_correct6.restype = C.c_int
+        L.orc_correct6.argtypes = [C.c_int64, C.c_int64, _ip, C.c_double, _dp, _dp, _dp,
+                                   _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
+                                   C.c_double, C.c_double, C.c_void_p]
         _lib = L
     return _lib
 
@@ -236,6 +246,129 @@ def integrate(x, v, m, t_end, p: Params, log=None):
         if tmin > t_end:
             break
         rec = block_step(st, p)
+        steps += 1
+        inter += rec.ilist.size * n
+        if log is not None:
+            log.append((rec.t_next, rec.ilist))
+        if np.all(st.t == t_end):
+            break
+    return st, steps, inter
+
+
+# ---------------------------------------------------------------------------
+# 6th-order Hermite (the order of the paper's HiGPUs code, Sec. 2 item 1)
+# ---------------------------------------------------------------------------
+
+def force6(x, v, a, m, eps, ilist=None, j0=0, j1=None):
+    """Acceleration, jerk and snap of bodies `ilist` from j in [j0, j1).
+
+    `a` holds the (predicted) accelerations of all bodies: the snap of a pair
+    needs the relative acceleration of the two bodies.
+    """
+    x, v, a, m = _c(x), _c(v), _c(a), _c(m)
+    n = m.shape[0]
+    if ilist is None:
+        ilist = np.arange(n, dtype=np.int64)
+    ilist = _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    acc = np.zeros((ilist.size, 3))
+    jerk = np.zeros((ilist.size, 3))
+    snap = np.zeros((ilist.size, 3))
+    _check(lib().orc_force6(n, x, v, a, m, ilist.size, ilist, int(j0), j1, float(eps),
+                            acc, jerk, snap))
+    return acc, jerk, snap
+
+
+def predict6(x, v, a, jk, sn, cr, t, t_next):
+    """Taylor prediction of position (to crackle), velocity and acceleration."""
+    x, v, a, jk, sn, cr, t = (_c(q) for q in (x, v, a, jk, sn, cr, t))
+    xp, vp, ap = np.empty_like(x), np.empty_like(v), np.empty_like(a)
+    lib().orc_predict6(t.shape[0], x, v, a, jk, sn, cr, t, float(t_next), xp, vp, ap)
+    return xp, vp, ap
+
+
+@dataclass
+class State6(State):
+    """Hermite-6 state: the Hermite-4 fields plus snap s and crackle c (n, 3)."""
+
+    s: np.ndarray = None
+    c: np.ndarray = None
+
+    def copy(self):
+        return State6(*(None if f is None else f.copy() for f in
+                        (self.x, self.v, self.m, self.a, self.j, self.t, self.dt,
+                         self.s, self.c)))
+
+
+def correct6(st: State6, ilist, t_next, acc, jerk, snap, eta, dt_max, dt_min, want_dta=False):
+    """Hermite-6 correction of the active bodies plus the new power-of-two step (in place)."""
+    ilist = _c(ilist, np.int64)
+    acc, jerk, snap = _c(acc), _c(jerk), _c(snap)
+    dta = np.empty(ilist.size) if want_dta else None
+    ptr = dta.ctypes.data_as(C.c_void_p) if want_dta else None
+    rc = lib().orc_correct6(st.n, ilist.size, ilist, float(t_next), acc, jerk, snap,
+                            st.x, st.v, st.a, st.j, st.s, st.c, st.t, st.dt, float(eta),
+                            float(dt_max), float(dt_min), ptr)
+    _check(rc)
+    return dta
+
+
+@dataclass
+class Params6(Params):
+    """Step parameters of the 6th-order scheme.
+
+    The generalized criterion gives dt = eta / omega on a circular orbit, where
+    Aarseth's 4th-order one gives sqrt(eta) / omega; eta = 0.14 matches the
+    4th-order eta = 0.02 there.
+    """
+
+    eta: float = 0.14
+
+
+def startup6(x, v, m, p: Params6) -> State6:
+    """t = 0: every body active.  A first pass gives the accelerations that the
+    snap needs; the second gives acceleration, jerk and snap.  The crackle
+    starts at zero; the first correction replaces it.  Startup steps as in the
+    4th-order scheme."""
+    x, v, m = _c(x).copy(), _c(v).copy(), _c(m).copy()
+    a0, _ = force(x, v, m, p.eps)
+    a, jk, sn = force6(x, v, a0, m, p.eps)
+    n = m.shape[0]
+    st = State6(x, v, m, a, jk, np.zeros(n), None, sn, np.zeros((n, 3)))
+    st.dt = init_dt(st.a, st.j, p.eta_s, p.dt_max, p.dt_min)
+    return st
+
+
+@dataclass
+class StepRecord6(StepRecord):
+    ap: np.ndarray = None
+    snap: np.ndarray = None
+
+
+def block_step6(st: State6, p: Params6, keep=False) -> StepRecord6:
+    """One Hermite-6 block step: select, predict all, force + snap, correct."""
+    t_next, ilist = select(st.t, st.dt)
+    xp, vp, ap = predict6(st.x, st.v, st.a, st.j, st.s, st.c, st.t, t_next)
+    acc, jerk, snap = force6(xp, vp, ap, st.m, p.eps, ilist)
+    rec = StepRecord6(t_next, ilist)
+    if keep:
+        rec.xp, rec.vp, rec.ap, rec.acc, rec.jerk, rec.snap = xp, vp, ap, acc, jerk, snap
+    correct6(st, ilist, t_next, acc, jerk, snap, p.eta, p.dt_max, p.dt_min)
+    return rec
+
+
+def integrate6(x, v, m, t_end, p: Params6, log=None):
+    """Block-step Hermite-6 integration from t = 0 to t_end (a multiple of dt_max).
+
+    Returns (state, n_steps, interactions); the startup counts two passes.
+    """
+    st = startup6(x, v, m, p)
+    n = st.n
+    steps, inter = 0, 2 * n * n
+    while True:
+        if float(np.min(st.t + st.dt)) > t_end:
+            break
+        rec = block_step6(st, p)
         steps += 1
         inter += rec.ilist.size * n
         if log is not None:

@@ -324,3 +324,215 @@ int orc_correct(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
     }
     return status;
 }
+
+/* =========================================================================
+ * 6th-order Hermite (the integrator of the paper's HiGPUs, Sec. 2 item 1).
+ * ========================================================================= */
+
+/* ---- acceleration, jerk and snap ---------------------------------------------
+ * For each listed body i and each j in [j0, j1) with j != i, with the
+ * (predicted) relative position r, velocity w and acceleration b of j:
+ *   s = r.r + eps^2,  A = m_j r / s^(3/2)                 (Eq. 1-2)
+ *   alpha = (r.w)/s,  J = m_j w / s^(3/2) - 3 alpha A      (dA/dt)
+ *   beta = (w.w + r.b)/s + alpha^2,
+ *   S = m_j b / s^(3/2) - 6 alpha J - 3 beta A            (d^2A/dt^2)
+ * summed with compensated sums in order j = j0 .. j1-1.
+ */
+int orc_force6(int64_t n, const double *x, const double *v, const double *ac,
+               const double *m, int64_t ni, const int64_t *ilist, int64_t j0, int64_t j1,
+               double eps, double *acc, double *jerk, double *snap)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        csum sa[3] = {{0, 0}, {0, 0}, {0, 0}};
+        csum sj[3] = {{0, 0}, {0, 0}, {0, 0}};
+        csum ss[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double rij[3], vij[3], aij[3];
+            for (int d = 0; d < 3; d++) {
+                rij[d] = x[3 * j + d] - x[3 * i + d];
+                vij[d] = v[3 * j + d] - v[3 * i + d];
+                aij[d] = ac[3 * j + d] - ac[3 * i + d];
+            }
+            const double s = rij[0] * rij[0] + rij[1] * rij[1] + rij[2] * rij[2] + eps2;
+            const double rinv = 1.0 / sqrt(s);
+            const double inv_s = rinv * rinv;
+            const double mu = m[j] * rinv * inv_s;
+            const double alpha = (rij[0] * vij[0] + rij[1] * vij[1] + rij[2] * vij[2]) * inv_s;
+            const double beta = (vij[0] * vij[0] + vij[1] * vij[1] + vij[2] * vij[2]
+                                 + rij[0] * aij[0] + rij[1] * aij[1] + rij[2] * aij[2]) * inv_s
+                                + alpha * alpha;
+            for (int d = 0; d < 3; d++) {
+                const double Ad = mu * rij[d];
+                const double Jd = mu * vij[d] - 3.0 * alpha * Ad;
+                const double Sd = mu * aij[d] - 6.0 * alpha * Jd - 3.0 * beta * Ad;
+                cs_add(&sa[d], Ad);
+                cs_add(&sj[d], Jd);
+                cs_add(&ss[d], Sd);
+            }
+        }
+        for (int d = 0; d < 3; d++) {
+            acc[3 * k + d] = cs_val(&sa[d]);
+            jerk[3 * k + d] = cs_val(&sj[d]);
+            snap[3 * k + d] = cs_val(&ss[d]);
+        }
+    }
+    return 0;
+}
+
+/* ---- 6th-order predictor --------------------------------------------------------
+ * d = t_next - t_i:
+ *   xp = x + v d + a d^2/2 + j d^3/6 + s d^4/24 + c d^5/120
+ *   vp = v + a d + j d^2/2 + s d^3/6 + c d^4/24
+ *   ap = a + j d + s d^2/2 + c d^3/6
+ * (s = snap, c = crackle: the second and third derivatives of the acceleration).
+ */
+void orc_predict6(int64_t n, const double *x, const double *v, const double *a,
+                  const double *jk, const double *sn, const double *cr, const double *t,
+                  double t_next, double *xp, double *vp, double *ap)
+{
+    for (int64_t i = 0; i < n; i++) {
+        const double tau = t_next - t[i];
+        for (int c = 0; c < 3; c++) {
+            const int64_t q = 3 * i + c;
+            xp[q] = x[q] + v[q] * tau + a[q] * tau * tau / 2.0 + jk[q] * tau * tau * tau / 6.0
+                    + sn[q] * tau * tau * tau * tau / 24.0 + cr[q] * tau * tau * tau * tau * tau / 120.0;
+            vp[q] = v[q] + a[q] * tau + jk[q] * tau * tau / 2.0 + sn[q] * tau * tau * tau / 6.0
+                    + cr[q] * tau * tau * tau * tau / 24.0;
+            ap[q] = a[q] + jk[q] * tau + sn[q] * tau * tau / 2.0 + cr[q] * tau * tau * tau / 6.0;
+        }
+    }
+}
+
+/* Solve the 3x3 system M u = r by Gaussian elimination with partial pivoting. */
+static void solve3(double M[3][3], double r[3], double u[3])
+{
+    for (int col = 0; col < 3; col++) {
+        int piv = col;
+        for (int row = col + 1; row < 3; row++)
+            if (fabs(M[row][col]) > fabs(M[piv][col]))
+                piv = row;
+        for (int q = 0; q < 3; q++) {
+            const double tmp = M[col][q];
+            M[col][q] = M[piv][q];
+            M[piv][q] = tmp;
+        }
+        const double tr = r[col];
+        r[col] = r[piv];
+        r[piv] = tr;
+        for (int row = col + 1; row < 3; row++) {
+            const double f = M[row][col] / M[col][col];
+            for (int q = col; q < 3; q++)
+                M[row][q] -= f * M[col][q];
+            r[row] -= f * r[col];
+        }
+    }
+    for (int row = 2; row >= 0; row--) {
+        double acc = r[row];
+        for (int q = row + 1; q < 3; q++)
+            acc -= M[row][q] * u[q];
+        u[row] = acc / M[row][row];
+    }
+}
+
+/* Derivatives 3, 4 and 5 at tau = h of the degree-5 polynomial a(tau) with
+ * a(0) = a0, a'(0) = j0, a''(0) = s0, a(h) = a1, a'(h) = j1, a''(h) = s1
+ * (the Hermite interpolant of the step).  Coefficients k0..k5 of
+ * sum k_n tau^n: k0, k1, k2 from the conditions at 0; k3, k4, k5 from the three
+ * conditions at h, solved as a linear system in u_n = k_n h^n. */
+static void hermite5_derivs(double h, double a0, double j0, double s0, double a1,
+                            double j1, double s1, double *d3, double *d4, double *d5)
+{
+    const double k0 = a0, k1 = j0, k2 = s0 / 2.0;
+    double M[3][3] = {{1.0, 1.0, 1.0}, {3.0, 4.0, 5.0}, {6.0, 12.0, 20.0}};
+    double r[3] = {a1 - (k0 + k1 * h + k2 * h * h),
+                   (j1 - (k1 + 2.0 * k2 * h)) * h,
+                   (s1 - 2.0 * k2) * h * h};
+    double u[3];
+    solve3(M, r, u);
+    const double k3 = u[0] / (h * h * h), k4 = u[1] / (h * h * h * h),
+                 k5 = u[2] / (h * h * h * h * h);
+    *d3 = 6.0 * k3 + 24.0 * k4 * h + 60.0 * k5 * h * h;
+    *d4 = 24.0 * k4 + 120.0 * k5 * h;
+    *d5 = 120.0 * k5;
+}
+
+/* ---- 6th-order corrector and new step -------------------------------------------
+ * Active body i, h = t_next - t_i, (a0, j0, s0) stored at t_i and (a1, j1, s1)
+ * new at t_next; the two-point Hermite quadratures (exact for a quartic
+ * acceleration):
+ *   v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
+ *   x1 = x0 + h/2 (v0 + v1) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1)
+ * The crackle c1 and the 4th and 5th derivatives at t_next come from the
+ * degree-5 Hermite interpolant of the step; c1 is stored for the predictor.
+ * New step (generalized Aarseth criterion for order 6):
+ *   dtA = eta ((sqrt(|a1||s1|) + |j1|) / (sqrt(|c1||a5|) + |a4|))^(1/3)
+ * kept a power of two by the same rule as the 4th-order scheme.
+ * dta_out (may be NULL) receives the unquantised dtA.
+ */
+int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
+                 const double *acc_new, const double *jerk_new, const double *snap_new,
+                 double *x, double *v, double *a, double *jk, double *sn, double *cr,
+                 double *t, double *dt, double eta, double dt_max, double dt_min,
+                 double *dta_out)
+{
+    int status = 0;
+    for (int64_t k = 0; k < mcount; k++) {
+        const int64_t i = ilist[k];
+        if (i < 0 || i >= n)
+            return -1;
+        const double h = t_next - t[i];
+        double d3v[3], d4v[3], d5v[3];
+        for (int c = 0; c < 3; c++) {
+            const int64_t q = 3 * i + c;
+            const double a0 = a[q], j0 = jk[q], s0 = sn[q];
+            const double a1 = acc_new[3 * k + c], j1 = jerk_new[3 * k + c],
+                         s1 = snap_new[3 * k + c];
+            const double v0 = v[q], x0 = x[q];
+            const double v1 = v0 + h / 2.0 * (a0 + a1) - h * h / 10.0 * (j1 - j0)
+                              + h * h * h / 120.0 * (s0 + s1);
+            const double x1 = x0 + h / 2.0 * (v0 + v1) - h * h / 10.0 * (a1 - a0)
+                              + h * h * h / 120.0 * (j0 + j1);
+            hermite5_derivs(h, a0, j0, s0, a1, j1, s1, &d3v[c], &d4v[c], &d5v[c]);
+            x[q] = x1;
+            v[q] = v1;
+            a[q] = a1;
+            jk[q] = j1;
+            sn[q] = s1;
+            cr[q] = d3v[c];
+        }
+        const double an = norm3(acc_new + 3 * k), jn = norm3(jerk_new + 3 * k),
+                     sN = norm3(snap_new + 3 * k);
+        const double cn = norm3(d3v), pn = norm3(d4v), qn = norm3(d5v);
+        const double num = sqrt(an * sN) + jn, den = sqrt(cn * qn) + pn;
+        double dta = den > 0.0 ? eta * cbrt(num / den) : INFINITY;
+        if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
+            return -5;
+        if (dta_out)
+            dta_out[k] = dta;
+        double step = h;
+        if (step > dta) {
+            while (step > dta)
+                step /= 2.0;
+        } else {
+            const double h2 = 2.0 * h;
+            if (dta >= h2 && fmod(t_next, h2) == 0.0 && h2 <= dt_max)
+                step = h2;
+        }
+        if (step < dt_min)
+            status = -4;
+        t[i] = t_next;
+        dt[i] = step;
+    }
+    return status;
+}

@@ -15,6 +15,7 @@ import test_oracle_blocksteps as tb
 import test_oracle_energy as te
 import test_oracle_force as tf
 import test_oracle_hermite as th
+import test_oracle_hermite6 as t6
 
 SRC = os.path.join(os.path.dirname(real_oracle.__file__), "nbody_oracle.c")
 
@@ -56,6 +57,36 @@ MUTANTS = [
      lambda o: tb.test_select_against_brute_scan(o)),
     ("startup step not a power of two", "        dt[i] = step;\n    }\n    return 0;", "        dt[i] = want;\n    }\n    return 0;",
      lambda o: th.test_aarseth_step_on_circular_orbit(o)),
+    # 6th-order scheme
+    ("snap drops the 3 beta A term", "- 3.0 * beta * Ad", "",
+     lambda o: t6.test_snap_is_second_time_derivative_of_acc(o, 5)),
+    ("snap coefficient 3 instead of 6", "6.0 * alpha * Jd", "3.0 * alpha * Jd",
+     lambda o: t6.test_snap_is_second_time_derivative_of_acc(o, 5)),
+    ("snap uses relative velocity for relative acceleration", "mu * aij[d]", "mu * vij[d]",
+     lambda o: t6.test_snap_is_second_time_derivative_of_acc(o, 5)),
+    ("beta without alpha^2", "+ alpha * alpha;", ";",
+     lambda o: t6.test_snap_is_second_time_derivative_of_acc(o, 5)),
+    ("predictor crackle c d^5/24", "cr[q] * tau * tau * tau * tau * tau / 120.0",
+     "cr[q] * tau * tau * tau * tau * tau / 24.0",
+     lambda o: t6.test_predictor6_is_exact_for_quintic_motion(o)),
+    ("predicted acceleration drops snap", "ap[q] = a[q] + jk[q] * tau + sn[q] * tau * tau / 2.0",
+     "ap[q] = a[q] + jk[q] * tau",
+     lambda o: t6.test_predictor6_is_exact_for_quintic_motion(o)),
+    ("corrector6 snap weight h^3/60", "h * h * h / 120.0 * (s0 + s1)", "h * h * h / 60.0 * (s0 + s1)",
+     lambda o: t6.test_corrector6_is_exact_for_quartic_acceleration(o, 0.5)),
+    ("corrector6 jerk difference reversed", "- h * h / 10.0 * (j1 - j0)", "- h * h / 10.0 * (j0 - j1)",
+     lambda o: t6.test_corrector6_is_exact_for_quartic_acceleration(o, 2.0 ** -4)),
+    ("corrector6 position uses a jerk difference", "h * h * h / 120.0 * (j0 + j1)",
+     "h * h * h / 120.0 * (j1 - j0)",
+     lambda o: t6.test_corrector6_is_exact_for_quartic_acceleration(o, 0.5)),
+    ("interpolant condition row", "{3.0, 4.0, 5.0}", "{3.0, 4.0, 6.0}",
+     lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
+    ("crackle coefficient 30 instead of 60", "60.0 * k5 * h * h", "30.0 * k5 * h * h",
+     lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
+    ("criterion square root instead of cube root", "eta * cbrt(num / den)", "eta * sqrt(num / den)",
+     lambda o: t6.test_generalized_step_on_circular_orbits(o, 0.5)),
+    ("criterion A4 without the square root", "sqrt(cn * qn) + pn", "cn * qn + pn",
+     lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
 ]
 
 
