@@ -66,6 +66,9 @@ def lib():
         L.orc_force6.restype = C.c_int
         L.orc_force6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
                                  C.c_int64, C.c_double, _dp, _dp, _dp]
+        L.orc_force6_scale.restype = C.c_int
+        L.orc_force6_scale.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
+                                       C.c_int64, C.c_double, _dp]
         L.orc_predict6.restype = None
         L.orc_predict6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
                                    _dp, _dp, _dp]
@@ -277,6 +280,19 @@ def force6(x, v, a, m, eps, ilist=None, j0=0, j1=None):
     _check(lib().orc_force6(n, x, v, a, m, ilist.size, ilist, int(j0), j1, float(eps),
                             acc, jerk, snap))
     return acc, jerk, snap
+
+
+def force6_scale(x, v, a, m, eps, ilist=None, j0=0, j1=None):
+    """Per body: sum_j |snap_ij| (magnitude scale of the snap sum)."""
+    x, v, a, m = _c(x), _c(v), _c(a), _c(m)
+    n = m.shape[0]
+    if ilist is None:
+        ilist = np.arange(n, dtype=np.int64)
+    ilist = _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    ss = np.zeros(ilist.size)
+    _check(lib().orc_force6_scale(n, x, v, a, m, ilist.size, ilist, int(j0), j1, float(eps), ss))
+    return ss
 
 
 def predict6(x, v, a, jk, sn, cr, t, t_next):

@@ -390,6 +390,52 @@ int orc_force6(int64_t n, const double *x, const double *v, const double *ac,
     return 0;
 }
 
+/* ---- magnitude scale of the snap sum --------------------------------------------
+ * Per listed body: sum over the same j as orc_force6 of |S_ij|, the length of
+ * each pair's snap term (the size of the numbers a finite-precision sum of the
+ * snap adds up, for error bounds relative to that sum's own scale).
+ */
+int orc_force6_scale(int64_t n, const double *x, const double *v, const double *ac,
+                     const double *m, int64_t ni, const int64_t *ilist, int64_t j0, int64_t j1,
+                     double eps, double *ss)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        csum tot = {0, 0};
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double px[3], pv[3], pa[3], term[3];
+            for (int d = 0; d < 3; d++) {
+                px[d] = x[3 * j + d] - x[3 * i + d];
+                pv[d] = v[3 * j + d] - v[3 * i + d];
+                pa[d] = ac[3 * j + d] - ac[3 * i + d];
+            }
+            const double ss2 = px[0] * px[0] + px[1] * px[1] + px[2] * px[2] + eps2;
+            const double q2 = 1.0 / ss2;
+            const double mq3 = m[j] * q2 / sqrt(ss2);
+            const double al = (px[0] * pv[0] + px[1] * pv[1] + px[2] * pv[2]) * q2;
+            const double bt = (pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]
+                               + px[0] * pa[0] + px[1] * pa[1] + px[2] * pa[2]) * q2 + al * al;
+            for (int d = 0; d < 3; d++) {
+                const double jt = pv[d] - 3.0 * al * px[d];
+                term[d] = mq3 * (pa[d] - 6.0 * al * jt - 3.0 * bt * px[d]);
+            }
+            cs_add(&tot, sqrt(term[0] * term[0] + term[1] * term[1] + term[2] * term[2]));
+        }
+        ss[k] = cs_val(&tot);
+    }
+    return 0;
+}
+
 /* ---- 6th-order predictor --------------------------------------------------------
  * d = t_next - t_i:
  *   xp = x + v d + a d^2/2 + j d^3/6 + s d^4/24 + c d^5/120

@@ -81,6 +81,28 @@ def test_snap_third_law_and_j_linearity(orc):
     np.testing.assert_allclose(lo + hi, sn, rtol=0, atol=1e-12 * np.abs(sn).max())
 
 
+def test_snap_scale_pins(orc):
+    from paper_1411_5234_amd import inputs
+    # one pair: the scale is the length of the only term
+    rng = np.random.default_rng(41)
+    x, v, b = rng.normal(size=(2, 3)), rng.normal(size=(2, 3)), rng.normal(size=(2, 3))
+    m = np.array([0.7, 1.3])
+    _, _, sn = orc.force6(x, v, b, m, 0.1)
+    ss = orc.force6_scale(x, v, b, m, 0.1)
+    np.testing.assert_allclose(ss, np.linalg.norm(sn, axis=1), rtol=1e-14)
+    # many bodies: at least the length of the sum, additive over j-ranges, linear in m_j
+    s = inputs.plummer(200, 42)
+    a, _ = orc.force(s.x, s.v, s.m, 1e-2)
+    _, _, sn = orc.force6(s.x, s.v, a, s.m, 1e-2)
+    ss = orc.force6_scale(s.x, s.v, a, s.m, 1e-2)
+    assert np.all(ss >= np.linalg.norm(sn, axis=1) * (1 - 1e-14))
+    part = (orc.force6_scale(s.x, s.v, a, s.m, 1e-2, j0=0, j1=77)
+            + orc.force6_scale(s.x, s.v, a, s.m, 1e-2, j0=77, j1=200))
+    np.testing.assert_allclose(part, ss, rtol=1e-13)
+    np.testing.assert_allclose(orc.force6_scale(s.x, s.v, a, 3.0 * s.m, 1e-2), 3.0 * ss,
+                               rtol=1e-13)
+
+
 # ---- predictor and corrector on polynomial motion ------------------------------------
 
 def test_predictor6_is_exact_for_quintic_motion(orc):
