@@ -491,13 +491,13 @@ static void solve3(double M[3][3], double r[3], double u[3])
     }
 }
 
-/* Derivatives 3, 4 and 5 at tau = h of the degree-5 polynomial a(tau) with
+/* Crackle (third derivative) at tau = h of the degree-5 polynomial a(tau) with
  * a(0) = a0, a'(0) = j0, a''(0) = s0, a(h) = a1, a'(h) = j1, a''(h) = s1
  * (the Hermite interpolant of the step).  Coefficients k0..k5 of
  * sum k_n tau^n: k0, k1, k2 from the conditions at 0; k3, k4, k5 from the three
  * conditions at h, solved as a linear system in u_n = k_n h^n. */
-static void hermite5_derivs(double h, double a0, double j0, double s0, double a1,
-                            double j1, double s1, double *d3, double *d4, double *d5)
+static double hermite5_crackle(double h, double a0, double j0, double s0, double a1,
+                               double j1, double s1)
 {
     const double k0 = a0, k1 = j0, k2 = s0 / 2.0;
     double M[3][3] = {{1.0, 1.0, 1.0}, {3.0, 4.0, 5.0}, {6.0, 12.0, 20.0}};
@@ -508,9 +508,7 @@ static void hermite5_derivs(double h, double a0, double j0, double s0, double a1
     solve3(M, r, u);
     const double k3 = u[0] / (h * h * h), k4 = u[1] / (h * h * h * h),
                  k5 = u[2] / (h * h * h * h * h);
-    *d3 = 6.0 * k3 + 24.0 * k4 * h + 60.0 * k5 * h * h;
-    *d4 = 24.0 * k4 + 120.0 * k5 * h;
-    *d5 = 120.0 * k5;
+    return 6.0 * k3 + 24.0 * k4 * h + 60.0 * k5 * h * h;
 }
 
 /* ---- 6th-order corrector and new step -------------------------------------------
@@ -519,11 +517,14 @@ static void hermite5_derivs(double h, double a0, double j0, double s0, double a1
  * acceleration):
  *   v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
  *   x1 = x0 + h/2 (v0 + v1) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1)
- * The crackle c1 and the 4th and 5th derivatives at t_next come from the
- * degree-5 Hermite interpolant of the step; c1 is stored for the predictor.
- * New step (generalized Aarseth criterion for order 6):
- *   dtA = eta ((sqrt(|a1||s1|) + |j1|) / (sqrt(|c1||a5|) + |a4|))^(1/3)
- * kept a power of two by the same rule as the 4th-order scheme.
+ * The crackle c1 at t_next comes from the degree-5 Hermite interpolant of the
+ * step and is stored for the predictor.  New step: the generalized Aarseth
+ * criterion in its lowest form, from the new acceleration, jerk and snap and the
+ * interpolated crackle,
+ *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||c1|) + |s1|),
+ * kept a power of two by the same rule as the 4th-order scheme.  (The forms that
+ * use the interpolant's 4th and 5th derivatives amplify the error of the forces
+ * by h^-4 and h^-5.)
  * dta_out (may be NULL) receives the unquantised dtA.
  */
 int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
@@ -538,7 +539,7 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
         if (i < 0 || i >= n)
             return -1;
         const double h = t_next - t[i];
-        double d3v[3], d4v[3], d5v[3];
+        double d3v[3];
         for (int c = 0; c < 3; c++) {
             const int64_t q = 3 * i + c;
             const double a0 = a[q], j0 = jk[q], s0 = sn[q];
@@ -549,7 +550,7 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
                               + h * h * h / 120.0 * (s0 + s1);
             const double x1 = x0 + h / 2.0 * (v0 + v1) - h * h / 10.0 * (a1 - a0)
                               + h * h * h / 120.0 * (j0 + j1);
-            hermite5_derivs(h, a0, j0, s0, a1, j1, s1, &d3v[c], &d4v[c], &d5v[c]);
+            d3v[c] = hermite5_crackle(h, a0, j0, s0, a1, j1, s1);
             x[q] = x1;
             v[q] = v1;
             a[q] = a1;
@@ -559,9 +560,9 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
         }
         const double an = norm3(acc_new + 3 * k), jn = norm3(jerk_new + 3 * k),
                      sN = norm3(snap_new + 3 * k);
-        const double cn = norm3(d3v), pn = norm3(d4v), qn = norm3(d5v);
-        const double num = sqrt(an * sN) + jn, den = sqrt(cn * qn) + pn;
-        double dta = den > 0.0 ? eta * cbrt(num / den) : INFINITY;
+        const double cn = norm3(d3v);
+        const double num = sqrt(an * sN) + jn, den = sqrt(jn * cn) + sN;
+        double dta = den > 0.0 ? eta * (num / den) : INFINITY;
         if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
             return -5;
         if (dta_out)

@@ -83,9 +83,11 @@ MUTANTS = [
      lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
     ("crackle coefficient 30 instead of 60", "60.0 * k5 * h * h", "30.0 * k5 * h * h",
      lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
-    ("criterion square root instead of cube root", "eta * cbrt(num / den)", "eta * sqrt(num / den)",
+    ("criterion ratio under a square root", "eta * (num / den)", "eta * sqrt(num / den)",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 0.5)),
-    ("criterion A4 without the square root", "sqrt(cn * qn) + pn", "cn * qn + pn",
+    ("criterion denominator without the square root", "sqrt(jn * cn) + sN", "jn * cn + sN",
+     lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
+    ("criterion numerator without |j|", "num = sqrt(an * sN) + jn,", "num = sqrt(an * sN),",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
 ]
 
