@@ -29,6 +29,10 @@ if ROOT not in sys.path:
 
 METRIC = "pair-interactions/s & % FP32 peak at N=1M; ensemble solves/s, p99 latency"
 FLOPS_PER_INTERACTION = 41
+# 6th order (acc + jerk + snap): 9 differences, s (6), r.w, w.w, r.b (15), rsqrt, r^-2 and
+# m s^-3/2 (4), alpha (1), beta (4), -3 alpha, -6 alpha, -3 beta (3), acc (6), u (6),
+# jerk (6), snap term (12) and snap (6), with FMA = 2
+FLOPS_PER_INTERACTION6 = 78
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 vector (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_FP64_TFLOPS = 78.6
 
@@ -39,11 +43,11 @@ PEAK_FP64_TFLOPS = 78.6
 TRAFFIC = {("b5e0dcf384027a92", "mixed", 1 << 20, (2, 1, 4)): 2.770e9 + 2.013e8}
 
 
-def _kernel_source_hash():
+def _kernel_source_hash(order=4):
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(ROOT, "paper_1411_5234_amd", "csrc")
-    for f in ("nb_internal.h", "force.hip"):
+    for f in ("nb_internal.h", "pair.h", "force.hip" if order == 4 else "force6.hip"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -56,7 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--eps", type=float, default=1e-4)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "ds", "fp64"], default="mixed")
+    ap.add_argument("--order", type=int, choices=[4, 6], default=4,
+                    help="Hermite order of the step mode (6: acc + jerk + snap, 6th-order corrector)")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
@@ -91,26 +97,42 @@ def main():
     if args.mode == "copy":
         return mode_copy(args)
 
+    return mode_step(args)
+
+
+def mode_step(args):
+    """The headline: shared-step block steps with the whole system active."""
     import numpy as np
     import torch
 
     from paper_1411_5234_amd import _lib, inputs
-    from paper_1411_5234_amd.nbody import Context, Integrator, Params, System
+    from paper_1411_5234_amd.nbody import (Context, Integrator, Integrator6, Params, Params6,
+                                           System)
 
+    h6 = args.order == 6
+    flops = FLOPS_PER_INTERACTION6 if h6 else FLOPS_PER_INTERACTION
     n = args.n
     snap = inputs.plummer(n, args.seed)
     system = System.from_arrays(snap.x, snap.v, snap.m, device="cuda")
     ctx = Context(0)
     stream = ctx.stream
-    p = Params(eps=args.eps, precision=args.precision)
-    it = Integrator(ctx, system, p)
+    if h6:
+        p = Params6(eps=args.eps, precision=args.precision)
+        it = Integrator6(ctx, system, p)
+    else:
+        p = Params(eps=args.eps, precision=args.precision)
+        it = Integrator(ctx, system, p)
     it.startup()
     ctx.sync()
     dt0 = system.row("dt")
     h = float(dt0.min().item())
     # shared step: every body gets h (the smallest startup step), dt_max = h
     p.dt_max = h
-    ctx.init_steps(system, it.acc.view(-1)[: 3 * n], it.jerk.view(-1)[: 3 * n], p.eta_s, h, p.dt_min)
+    a3, j3 = it.acc.view(-1)[: 3 * n], it.jerk.view(-1)[: 3 * n]
+    if h6:
+        ctx.init_steps6(system, it.h6, a3, j3, it.snap.view(-1)[: 3 * n], p.eta_s, h, p.dt_min)
+    else:
+        ctx.init_steps(system, a3, j3, p.eta_s, h, p.dt_min)
     ctx.sync()
 
     E0 = None
@@ -118,21 +140,34 @@ def main():
         E0 = ctx.energy(system, args.eps)[2]
 
     ev = []
-    force_ms = []
     inter = 0
+
+    def force(m, prec, plan=None):
+        acc = it.acc.view(-1)[: 3 * m]
+        jerk = it.jerk.view(-1)[: 3 * m]
+        if h6:
+            sn = it.snap.view(-1)[: 3 * m]
+            ctx.force6_active(system, it.h6, it.i_idx, m, 0, n, p.eps, prec, acc, jerk, sn, plan)
+            return acc, jerk, sn
+        ctx.force_active(system, it.i_idx, m, 0, n, p.eps, prec, acc, jerk, plan)
+        return acc, jerk
 
     def one_step(timed):
         nonlocal inter
         t_next, m = ctx.select_active(system, it.i_idx)
-        ctx.predict(system, t_next)
-        acc = it.acc.view(-1)[: 3 * m]
-        jerk = it.jerk.view(-1)[: 3 * m]
+        if h6:
+            ctx.predict6(system, it.h6, t_next)
+        else:
+            ctx.predict(system, t_next)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        ctx.force_active(system, it.i_idx, m, 0, n, p.eps, p.precision, acc, jerk)
+        out = force(m, p.precision)
         e1.record(stream)
-        ctx.correct(system, it.i_idx, m, acc, jerk, t_next, p.eta, p.dt_max, p.dt_min)
+        if h6:
+            ctx.correct6(system, it.h6, it.i_idx, m, *out, t_next, p.eta, p.dt_max, p.dt_min)
+        else:
+            ctx.correct(system, it.i_idx, m, *out, t_next, p.eta, p.dt_max, p.dt_min)
         if timed:
             ev.append((e0, e1))
             inter += m * n
@@ -153,10 +188,35 @@ def main():
     value = inter / wall
     favg_s = float(np.mean(force_ms)) / 1e3
     per_launch = float(np.mean(ms)) * n
-    achieved_tflops = FLOPS_PER_INTERACTION * per_launch / favg_s / 1e12
-    peak = PEAK_FP32_TFLOPS if args.precision == "mixed" else PEAK_FP64_TFLOPS
+    achieved_tflops = flops * per_launch / favg_s / 1e12
+    peak = PEAK_FP32_TFLOPS if args.precision != "fp64" else PEAK_FP64_TFLOPS
 
     extra = {}
+    if ms[-1] == n:
+        # the other precisions on the same predicted state and launch shape: one
+        # warm-up and two HIP-event-timed force launches each
+        alt = {}
+        for prec in ("fp64", "ds", "mixed"):
+            if prec == args.precision:
+                continue
+            force(n, prec)
+            ctx.sync()
+            best = float("inf")
+            for _ in range(2):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                force(n, prec)
+                e1.record(stream)
+                ctx.sync()
+                best = min(best, e0.elapsed_time(e1) / 1e3)
+            alt[prec] = {"kernel_ms": best * 1e3, "interactions_per_s": n * n / best,
+                         "tflops": flops * n * n / best / 1e12,
+                         "plan": list(_lib.force_plan(n, n, prec))}
+        extra["other_precisions_same_state"] = alt
+        # leave the results of the benchmarked precision in place for the CPU check
+        force(n, args.precision)
+        ctx.sync()
     if E0 is not None:
         E1 = ctx.energy(system, args.eps)[2]
         extra["energy_drift_over_timed_steps"] = abs(E1 - E0) / abs(E0)
@@ -169,12 +229,17 @@ def main():
         il = np.arange(k, dtype=np.int64)
         # the oracle evaluates the sample from the same predicted j-set the last GPU step used
         tc = time.perf_counter()
-        oa, oj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, il)
+        if h6:
+            ap = it.h6.state_numpy()["ap"]
+            oa, oj, _ = oracle.force6(st["xp"], st["vp"], ap, st["m"], args.eps, il)
+        else:
+            oa, oj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, il)
         tcpu = time.perf_counter() - tc
         cpu = {"value": k * n / tcpu, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "acc+jerk of the first %d bodies against all %d predicted bodies (FP64, "
-                         "compensated sums), %.1f s" % (k, n, tcpu)}
+               "sample": "%s of the first %d bodies against all %d predicted bodies (FP64, "
+                         "compensated sums), %.1f s" % ("acc+jerk+snap" if h6 else "acc+jerk",
+                                                         k, n, tcpu)}
         if ms[-1] == n:   # the last block was the whole system, in index order
             ga = it.acc.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
             gj = it.jerk.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
@@ -185,6 +250,8 @@ def main():
                 "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
                 "jerk_rel_max": float(ej.max()), "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
 
+    kname = "force%s_%s_kernel" % ("6" if h6 else "",
+                                   "fp64" if args.precision == "fp64" else "mixed")
     out = {
         "metric": METRIC,
         "value": value,
@@ -196,19 +263,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if args.precision == "mixed" else "f64",
+        "dtype": {"mixed": "f64+f32", "ds": "f32x2+f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "plummer_n%d_eps%g_%s_shared_step_full_block" % (n, args.eps, args.precision),
-                   "n": n, "eps": args.eps, "precision": args.precision, "active_block": "m=N",
-                   "shared_step": h},
-        "fp32_peak_frac": value * FLOPS_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12),
+        "config": {"workload": "plummer_n%d_eps%g_%s_hermite%d_shared_step_full_block"
+                               % (n, args.eps, args.precision, args.order),
+                   "n": n, "eps": args.eps, "precision": args.precision, "order": args.order,
+                   "active_block": "m=N", "shared_step": h},
+        "fp32_peak_frac": value * flops / (PEAK_FP32_TFLOPS * 1e12),
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved_tflops / peak,
-                     "traffic": TRAFFIC.get((_kernel_source_hash(), args.precision, n,
+                     "traffic": TRAFFIC.get((_kernel_source_hash(args.order), args.precision, n,
                                              _lib.force_plan(n, n, args.precision))),
-                     "kernel": "force_%s_kernel" % args.precision,
+                     "kernel": kname,
                      "kernel_ms_avg": float(np.mean(force_ms)),
-                     "flops_per_interaction": FLOPS_PER_INTERACTION,
+                     "flops_per_interaction": flops,
                      "interactions_per_launch": per_launch},
         "cpu_baseline": cpu,
     }

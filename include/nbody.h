@@ -1,8 +1,8 @@
 /*
  * nbody.h -- C ABI of libnbody.so, the MI355X (gfx950) hot path of a direct
- * N-body code with a 4th-order Hermite integrator and power-of-two block time
- * steps (Spera 2014, "Using GPUs to solve the classical N-body problem",
- * GPUHEP2014: Eq. 1-2 and Sec. 2 items 1-5).
+ * N-body code with 4th- and 6th-order Hermite integrators and power-of-two
+ * block time steps (Spera 2014, "Using GPUs to solve the classical N-body
+ * problem", GPUHEP2014: Eq. 1-2 and Sec. 2 items 1-5).
  *
  * General conventions
  *  - Units: G = 1.  Every floating-point state array is FP64.
@@ -47,7 +47,10 @@ typedef enum {
 
 typedef enum {
     NB_FP64 = 0,      /* all pair arithmetic in FP64                            */
-    NB_MIXED = 1      /* FP64 pair differences, FP32 pair arithmetic, FP64 sums */
+    NB_MIXED = 1,     /* FP64 pair differences, FP32 pair arithmetic, FP64 sums */
+    NB_DS = 2         /* double-single pair differences (each FP64 position as
+                         FP32 hi + lo, difference (hi_j - hi_i) + (lo_j - lo_i)),
+                         then as NB_MIXED: the DS alternative of Sec. 2 item 4 */
 } nb_precision;
 
 /* One system of n bodies.  Every pointer is a device array of length n.
@@ -106,7 +109,9 @@ nb_status nb_predict(nb_ctx *ctx, const nb_system *sys, double t_next);
  * overwritten.  NB_FP64 does all pair arithmetic in FP64; NB_MIXED forms r in
  * FP64, rounds it to FP32, does the rest of the pair arithmetic in FP32 (with
  * the hardware reciprocal square root) and accumulates in FP64 (the precision
- * split of Sec. 2 item 4).  The j-range is split across workgroups when m is
+ * split of Sec. 2 item 4); NB_DS forms r from double-single (FP32 hi + lo)
+ * positions in FP32 and continues as NB_MIXED.  NB_MIXED and NB_DS need the
+ * FP32 velocity and mass copies.  The j-range is split across workgroups when m is
  * small (Sec. 2 item 3) and the partial sums are combined in a fixed order,
  * so results are bitwise reproducible.  m == 0 is a no-op.
  * Returns NB_EINVAL for eps <= 0, j0 < 0, j1 > n, j0 > j1, m < 0 or m > n. */
@@ -208,6 +213,83 @@ nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_it
 nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
                         nb_precision precision, double eta, double eta_s, double dt_max,
                         double dt_min);
+
+/* ---- 6th-order Hermite ----------------------------------------------------------
+ * The scheme of the paper's HiGPUs code (Sec. 2 item 1: Hermite integrators of
+ * order 4, 6 and 8 need one force evaluation per step).  The pair sum adds the
+ * snap (second time derivative of the acceleration), which needs the predicted
+ * accelerations of the j-bodies; the predictor reaches the crackle (third
+ * derivative); the corrector is the two-point Hermite quadrature exact for a
+ * quartic acceleration, and the crackle at the step's end comes from the
+ * degree-5 interpolant of (a, j, s) at both ends.
+ * These calls take an nb_system (whose a and j are the state's acceleration and
+ * jerk, and whose xp, vp, vp32, m32 are the predicted j-set as for the 4th
+ * order) plus the extra arrays below, all device arrays of length n owned by
+ * the caller.  Snap and crackle must hold finite values before the first
+ * nb_predict6 (zeros are fine: the startup sets them).                         */
+typedef struct {
+    double *sx, *sy, *sz;          /* snap at t_i                                  */
+    double *cx, *cy, *cz;          /* crackle at t_i                               */
+    double *axp, *ayp, *azp;       /* predicted acceleration at the block time     */
+    float *axp32, *ayp32, *azp32;  /* FP32 copies for NB_MIXED / NB_DS (or NULL)   */
+} nb_hermite6;
+
+/* Predictor to the crackle for every body, with d = t_next - t_i:
+ *   xp = x + v d + a d^2/2 + j d^3/6 + s d^4/24 + c d^5/120,
+ *   vp = v + a d + j d^2/2 + s d^3/6 + c d^4/24,
+ *   ap = a + j d + s d^2/2 + c d^3/6                       (FP64),
+ * and, when the FP32 pointers are non-NULL, vp32, ap32 and m32 as FP32 copies. */
+nb_status nb_predict6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                      double t_next);
+
+/* Acceleration, jerk and snap of the active block from the predicted j-set.
+ * As nb_force_active, plus, with b = ap_j - ap_i, alpha = (r.w)/s and
+ * beta = (|w|^2 + r.b)/s + alpha^2:
+ *   jerk_k += m_j s^(-3/2) (w - 3 alpha r),
+ *   snap_k += m_j s^(-3/2) (b - 6 alpha (w - 3 alpha r) - 3 beta r),
+ * the second time derivative of the pair acceleration along the predicted
+ * motion.  acc, jerk and snap are device arrays of 3*m doubles (SoA, stride m)
+ * and are overwritten.  Precisions as nb_force_active; NB_MIXED and NB_DS need
+ * the FP32 copies of sys and h6.  Bitwise reproducible; m == 0 is a no-op.
+ * Returns NB_EINVAL for eps <= 0, j0 < 0, j1 > n, j0 > j1, m < 0 or m > n. */
+nb_status nb_force6_active(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                           const int32_t *i_idx, int32_t m, int64_t j0, int64_t j1,
+                           double eps, nb_precision precision, double *acc, double *jerk,
+                           double *snap);
+
+/* Same as nb_force6_active with an explicit plan (as nb_force_active_plan). */
+nb_status nb_force6_active_plan(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                                const int32_t *i_idx, int32_t m, int64_t j0, int64_t j1,
+                                double eps, nb_precision precision, int32_t i_per_lane,
+                                int32_t lanes_per_i, int32_t j_chunks, double *acc,
+                                double *jerk, double *snap);
+
+/* Startup of the 6th-order scheme (t = 0, every body active): copy acc, jerk
+ * and snap (3*n SoA each, from nb_force6_active over all bodies with the
+ * accelerations of a first nb_force_active pass as predicted accelerations)
+ * into the state, set the crackle to 0, t = 0 and dt as nb_init_steps.
+ * Errors latched as nb_init_steps. */
+nb_status nb_init_steps6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                         const double *acc, const double *jerk, const double *snap,
+                         double eta_s, double dt_max, double dt_min);
+
+/* 6th-order corrector and new step for the active block.  With h = t_next - t_i,
+ * (a0, j0, s0) stored and (a1, j1, s1) new (3*m SoA, order of i_idx):
+ *   v = v + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1),
+ *   x = x + h/2 (v_old + v) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1),
+ *   crackle = -3 (20 (a0 - a1) + h^2 (s0 - 3 s1) + h (8 j0 + 12 j1)) / h^3
+ * (the third derivative at t_next of the degree-5 interpolant of (a, j, s) at
+ * both ends), a, j, s = a1, j1, s1, t = t_next, and the new step from the
+ * generalized Aarseth criterion in its lowest form
+ *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||crackle|) + |s1|),
+ * kept a power of two by the rule of nb_correct.  (The higher forms of the
+ * criterion need the interpolant's 4th and 5th derivatives, which amplify the
+ * error of FP32 pair arithmetic by h^-4 and h^-5 and then drive the steps to
+ * dt_min.)  Errors latched as nb_correct. */
+nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                      const int32_t *i_idx, int32_t m, const double *acc, const double *jerk,
+                      const double *snap, double t_next, double eta, double dt_max,
+                      double dt_min);
 
 /* Library version string. */
 const char *nb_version(void);

@@ -15,10 +15,14 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnbody.so
 FIELDS64 = ["x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "jx", "jy", "jz",
             "m", "t", "dt", "xp", "yp", "zp", "vxp", "vyp", "vzp"]
 FIELDS32 = ["vxp32", "vyp32", "vzp32", "m32"]
+# nb_hermite6: snap, crackle, predicted acceleration (FP64), FP32 copies
+H6_FIELDS64 = ["sx", "sy", "sz", "cx", "cy", "cz", "axp", "ayp", "azp"]
+H6_FIELDS32 = ["axp32", "ayp32", "azp32"]
 
 NB_FP64 = 0
 NB_MIXED = 1
-PRECISIONS = {"fp64": NB_FP64, "mixed": NB_MIXED}
+NB_DS = 2
+PRECISIONS = {"fp64": NB_FP64, "mixed": NB_MIXED, "ds": NB_DS}
 
 STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
           -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX"}
@@ -27,11 +31,17 @@ STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
            "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
-           "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch"]
+           "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
+           "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
+           "nb_correct6"]
 
 
 class NbSystem(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in FIELDS64 + FIELDS32]
+
+
+class NbHermite6(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in H6_FIELDS64 + H6_FIELDS32]
 
 
 class NbBatchItem(C.Structure):
@@ -62,6 +72,7 @@ def load() -> C.CDLL:
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     ps = C.POINTER(NbSystem)
+    ph = C.POINTER(NbHermite6)
     sig = {
         "nb_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, vp]),
         "nb_ctx_destroy": (C.c_int, [vp]),
@@ -82,6 +93,12 @@ def load() -> C.CDLL:
         "nb_force_active_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, C.c_int]),
         "nb_correct_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, f64, f64, f64, f64]),
         "nb_step_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), i32, C.c_int, f64, f64, f64, f64]),
+        "nb_predict6": (C.c_int, [vp, ps, ph, f64]),
+        "nb_force6_active": (C.c_int, [vp, ps, ph, vp, i32, i64, i64, f64, C.c_int, vp, vp, vp]),
+        "nb_force6_active_plan": (C.c_int, [vp, ps, ph, vp, i32, i64, i64, f64, C.c_int, i32, i32,
+                                            i32, vp, vp, vp]),
+        "nb_init_steps6": (C.c_int, [vp, ps, ph, vp, vp, vp, f64, f64, f64]),
+        "nb_correct6": (C.c_int, [vp, ps, ph, vp, i32, vp, vp, vp, f64, f64, f64, f64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["api.hip", "force.hip", "step.hip"]
+SOURCES = ["api.hip", "force.hip", "force6.hip", "step.hip", "step6.hip"]
 ARCH = "gfx950"
 
 

@@ -9,12 +9,13 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <utility>
 #include <vector>
 
 #include "nb_internal.h"
 
-#define NB_VERSION "0.3.0"
+#define NB_VERSION "0.4.0"
 
 using nbk::Item;
 using nbk::SelResult;
@@ -67,6 +68,21 @@ nb_status check_system(nb_ctx *ctx, const nb_system *s, bool need_pred)
     const bool any32 = s->vxp32 || s->vyp32 || s->vzp32 || s->m32;
     const bool all32 = s->vxp32 && s->vyp32 && s->vzp32 && s->m32;
     if (any32 && !all32) return fail(ctx, NB_EINVAL, "FP32 copies must be all set or all NULL");
+    return NB_OK;
+}
+
+nb_status check_h6(nb_ctx *ctx, const nb_system *s, const nb_hermite6 *h)
+{
+    if (!h) return fail(ctx, NB_EINVAL, "6th-order arrays are NULL");
+    if (s->n == 0) return NB_OK;
+    const double *need[] = {h->sx, h->sy, h->sz, h->cx, h->cy, h->cz, h->axp, h->ayp, h->azp};
+    for (const double *p : need)
+        if (!p) return fail(ctx, NB_EINVAL, "a 6th-order array is NULL");
+    const bool any32 = h->axp32 || h->ayp32 || h->azp32;
+    const bool all32 = h->axp32 && h->ayp32 && h->azp32;
+    if (any32 && !all32) return fail(ctx, NB_EINVAL, "FP32 copies must be all set or all NULL");
+    if (all32 && !s->vxp32)
+        return fail(ctx, NB_EINVAL, "FP32 predicted accelerations need the system's FP32 copies");
     return NB_OK;
 }
 
@@ -220,7 +236,7 @@ Plan make_plan(int64_t nj, int32_t m, int precision)
 {
     const int64_t target_lanes = (int64_t)1 << 21;
     const int64_t min_j_lane = 128, min_j_chunk = 2048;
-    Plan p{(precision == NB_MIXED && m >= (1 << 16)) ? 2 : 1, 1, 1};
+    Plan p{(precision != NB_FP64 && m >= (1 << 16)) ? 2 : 1, 1, 1};
     if (m <= 0 || nj <= 0) return p;
     const int64_t groups = (m + p.il - 1) / p.il;   // lane groups holding distinct i-bodies
     while (p.s < 64 && groups * p.s < nbk::WG && nj / (p.s * 4) >= min_j_lane)
@@ -260,7 +276,7 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
         if (chunk < nbk::TILE) chunk = nbk::TILE;
         it.chunk = chunk;
         it.b = j.plan.b;
-        if (it.b > 1) part_doubles += 6 * (size_t)it.m * (size_t)it.b;
+        if (it.b > 1) part_doubles += nbk::force_outputs(it) * (size_t)it.m * (size_t)it.b;
     }
     if (part_doubles) {
         size_t have = ctx->scratch_bytes;
@@ -271,14 +287,16 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
     for (ForceJob &j : jobs) {
         if (j.it.b > 1) {
             j.it.part = (double *)ctx->scratch + off;
-            off += 6 * (size_t)j.it.m * (size_t)j.it.b;
+            off += nbk::force_outputs(j.it) * (size_t)j.it.m * (size_t)j.it.b;
         }
     }
-    std::map<std::pair<int, int>, std::vector<size_t>> shapes;
+    std::map<std::tuple<int, int, bool>, std::vector<size_t>> shapes;
     for (size_t k = 0; k < jobs.size(); ++k)
-        if (jobs[k].it.m > 0) shapes[{jobs[k].plan.il, jobs[k].plan.s}].push_back(k);
+        if (jobs[k].it.m > 0)
+            shapes[{jobs[k].plan.il, jobs[k].plan.s, jobs[k].it.snap != nullptr}].push_back(k);
     for (auto &kv : shapes) {
-        const int il = kv.first.first, s = kv.first.second;
+        const int il = std::get<0>(kv.first), s = std::get<1>(kv.first);
+        const bool h6 = std::get<2>(kv.first);
         const int iwg = (nbk::WG / s) * il;
         std::vector<Item> items;
         std::vector<int64_t> blocks;
@@ -288,7 +306,8 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
         }
         Table t;
         NB_TRY(make_table(ctx, items, blocks, &t));
-        hipError_t e = nbk::launch_force(prec, il, s, t, ctx->stream);
+        hipError_t e = h6 ? nbk::launch_force6(prec, il, s, t, ctx->stream)
+                          : nbk::launch_force(prec, il, s, t, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
     }
     std::vector<Item> red;
@@ -296,7 +315,8 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
     for (ForceJob &j : jobs) {
         if (j.it.b > 1 && j.it.m > 0) {
             red.push_back(j.it);
-            rblocks.push_back((6 * (int64_t)j.it.m + nbk::WG - 1) / nbk::WG);
+            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + nbk::WG - 1) /
+                              nbk::WG);
         }
     }
     if (!red.empty()) {
@@ -313,12 +333,13 @@ nb_status check_force_args(nb_ctx *ctx, const nb_system *sys, int32_t m, int64_t
 {
     NB_TRY(check_system(ctx, sys, true));
     if (!(eps > 0.0) || !isfinite(eps)) return fail(ctx, NB_EINVAL, "eps must be > 0 and finite");
-    if (prec != NB_FP64 && prec != NB_MIXED) return fail(ctx, NB_EINVAL, "unknown precision");
+    if (prec != NB_FP64 && prec != NB_MIXED && prec != NB_DS)
+        return fail(ctx, NB_EINVAL, "unknown precision");
     if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
     if (j0 < 0 || j1 > sys->n || j0 > j1) return fail(ctx, NB_EINVAL, "bad j-range");
     if (m > 0 && (!acc || !jerk)) return fail(ctx, NB_EINVAL, "acc/jerk is NULL");
-    if (m > 0 && prec == NB_MIXED && !sys->vxp32)
-        return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
+    if (m > 0 && prec != NB_FP64 && !sys->vxp32)
+        return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 copies");
     return NB_OK;
 }
 
@@ -338,6 +359,33 @@ nb_status force_one(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int
     job.it.eps2 = eps * eps;
     job.it.acc = acc;
     job.it.jerk = jerk;
+    job.plan = plan;
+    std::vector<ForceJob> jobs{job};
+    return run_force(ctx, jobs, prec);
+}
+
+nb_status force6_one(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                     const int32_t *i_idx, int32_t m, int64_t j0, int64_t j1, double eps,
+                     nb_precision prec, Plan plan, double *acc, double *jerk, double *snap)
+{
+    NB_TRY(check_force_args(ctx, sys, m, j0, j1, eps, prec, acc, jerk));
+    NB_TRY(check_h6(ctx, sys, h6));
+    if (m > 0 && !snap) return fail(ctx, NB_EINVAL, "snap is NULL");
+    if (m > 0 && prec != NB_FP64 && !h6->axp32)
+        return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 accelerations");
+    if (!valid_plan(plan)) return fail(ctx, NB_EINVAL, "invalid plan");
+    if (m == 0) return NB_OK;
+    ForceJob job;
+    job.it = base_item(ctx, *sys);
+    job.it.h6 = *h6;
+    job.it.i_idx = i_idx;
+    job.it.m = m;
+    job.it.j0 = j0;
+    job.it.j1 = j1;
+    job.it.eps2 = eps * eps;
+    job.it.acc = acc;
+    job.it.jerk = jerk;
+    job.it.snap = snap;
     job.plan = plan;
     std::vector<ForceJob> jobs{job};
     return run_force(ctx, jobs, prec);
@@ -477,8 +525,8 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
     std::vector<ForceJob> jobs;
     for (int32_t k = 0; k < n_items; ++k) {
         if (!run[k] || items[k].sys.n == 0) continue;
-        if (precision == NB_MIXED && !items[k].sys.vxp32)
-            return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
+        if (precision != NB_FP64 && !items[k].sys.vxp32)
+            return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 copies");
         const Item it = batch_item(ctx, items[k]);
         const int64_t nb = (items[k].sys.n + nbk::WG - 1) / nbk::WG;
         if (items[k].startup) {
@@ -739,14 +787,14 @@ nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t
 {
     if (!ctx) return NB_EINVAL;
     if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
-    if (precision != NB_FP64 && precision != NB_MIXED)
+    if (precision != NB_FP64 && precision != NB_MIXED && precision != NB_DS)
         return fail(ctx, NB_EINVAL, "unknown precision");
     std::vector<ForceJob> jobs;
     for (int32_t k = 0; k < n_items; ++k) {
         NB_TRY(check_item(ctx, items[k], true));
         if (items[k].sys.n == 0) continue;
-        if (precision == NB_MIXED && !items[k].sys.vxp32)
-            return fail(ctx, NB_EINVAL, "mixed precision needs the FP32 copies");
+        if (precision != NB_FP64 && !items[k].sys.vxp32)
+            return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 copies");
         ForceJob job;
         job.it = batch_item(ctx, items[k]);
         job.plan = make_plan(items[k].sys.n, job.it.m, precision);
@@ -791,7 +839,7 @@ nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
 {
     if (!ctx) return NB_EINVAL;
     if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
-    if (precision != NB_FP64 && precision != NB_MIXED)
+    if (precision != NB_FP64 && precision != NB_MIXED && precision != NB_DS)
         return fail(ctx, NB_EINVAL, "unknown precision");
     NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
     if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
@@ -812,6 +860,90 @@ nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
     for (int32_t k = 0; k < n_items; ++k)
         if (run[k]) items[k].startup = 0;
     return NB_OK;
+}
+
+// ---- 6th order ---------------------------------------------------------------------
+
+nb_status nb_predict6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, double t_next)
+{
+    NB_TRY(check_system(ctx, sys, true));
+    NB_TRY(check_h6(ctx, sys, h6));
+    if (!isfinite(t_next)) return fail(ctx, NB_EINVAL, "t_next must be finite");
+    if (sys->n == 0) return NB_OK;
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].h6 = *h6;
+    items[0].t_next = t_next;
+    std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_predict6(t, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict6 launch");
+}
+
+nb_status nb_force6_active(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                           const int32_t *i_idx, int32_t m, int64_t j0, int64_t j1, double eps,
+                           nb_precision precision, double *acc, double *jerk, double *snap)
+{
+    return force6_one(ctx, sys, h6, i_idx, m, j0, j1, eps, precision,
+                      make_plan(j1 - j0, m, precision), acc, jerk, snap);
+}
+
+nb_status nb_force6_active_plan(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                                const int32_t *i_idx, int32_t m, int64_t j0, int64_t j1,
+                                double eps, nb_precision precision, int32_t i_per_lane,
+                                int32_t lanes_per_i, int32_t j_chunks, double *acc,
+                                double *jerk, double *snap)
+{
+    return force6_one(ctx, sys, h6, i_idx, m, j0, j1, eps, precision,
+                      Plan{i_per_lane, lanes_per_i, j_chunks}, acc, jerk, snap);
+}
+
+nb_status nb_init_steps6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                         const double *acc, const double *jerk, const double *snap,
+                         double eta_s, double dt_max, double dt_min)
+{
+    NB_TRY(check_system(ctx, sys, false));
+    NB_TRY(check_h6(ctx, sys, h6));
+    NB_TRY(check_step_params(ctx, eta_s, dt_max, dt_min));
+    if (sys->n == 0) return NB_OK;
+    if (!acc || !jerk || !snap) return fail(ctx, NB_EINVAL, "acc/jerk/snap is NULL");
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].h6 = *h6;
+    items[0].acc = (double *)acc;
+    items[0].jerk = (double *)jerk;
+    items[0].snap = (double *)snap;
+    std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_init_steps6(t, eta_s, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps6 launch");
+}
+
+nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
+                      const int32_t *i_idx, int32_t m, const double *acc, const double *jerk,
+                      const double *snap, double t_next, double eta, double dt_max,
+                      double dt_min)
+{
+    NB_TRY(check_system(ctx, sys, false));
+    NB_TRY(check_h6(ctx, sys, h6));
+    if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
+    if (!isfinite(t_next)) return fail(ctx, NB_EINVAL, "t_next must be finite");
+    if (m == 0) return NB_OK;
+    if (!acc || !jerk || !snap) return fail(ctx, NB_EINVAL, "acc/jerk/snap is NULL");
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].h6 = *h6;
+    items[0].i_idx = i_idx;
+    items[0].m = m;
+    items[0].acc = (double *)acc;
+    items[0].jerk = (double *)jerk;
+    items[0].snap = (double *)snap;
+    items[0].t_next = t_next;
+    std::vector<int64_t> blocks{(m + nbk::WG - 1) / nbk::WG};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_correct6(t, eta, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "correct6 launch");
 }
 
 }  // extern "C"

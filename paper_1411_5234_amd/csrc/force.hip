@@ -18,104 +18,36 @@
 // the mixed kernel forms r_j - r_i in FP64, rounds it to FP32, does the rest in
 // FP32 with the hardware reciprocal square root, accumulates short runs of
 // FP32 terms and folds them into FP64 totals.
-#include "nb_internal.h"
+#include "pair.h"
 
 namespace nbk {
 
-// FP64 reciprocal square root: hardware estimate refined by two Newton steps
-// y <- y (3 - s y^2) / 2 written as y + y (1/2 - (s/2) y^2).
-__device__ __forceinline__ double rsqrt64(double s)
+// Acceleration and jerk terms of one j-body on one i-body, all FP32 once the
+// position difference (dx, dy, dz) is formed, added to the FP32 run sums.
+__device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float dvx, float dvy,
+                                         float dvz, float mj, float eps2, float (&a)[3],
+                                         float (&jk)[3])
 {
-    double y = __builtin_amdgcn_rsq(s);
-    const double hs = 0.5 * s;
-    double e = fma(-hs, y * y, 0.5);
-    y = fma(y, e, y);
-    e = fma(-hs, y * y, 0.5);
-    y = fma(y, e, y);
-    return y;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const float mr3 = mj * rinv * rinv2;
+    const float al = -3.0f * rv * rinv2;
+    a[0] = fmaf(mr3, dx, a[0]);
+    a[1] = fmaf(mr3, dy, a[1]);
+    a[2] = fmaf(mr3, dz, a[2]);
+    jk[0] = fmaf(mr3, fmaf(al, dx, dvx), jk[0]);
+    jk[1] = fmaf(mr3, fmaf(al, dy, dvy), jk[1]);
+    jk[2] = fmaf(mr3, fmaf(al, dz, dvz), jk[2]);
 }
 
-template <int S>
-__device__ __forceinline__ double group_sum(double v)
+template <int IL, int S, int F, bool DS>
+__global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const Item *items,
+                                                                          const int64_t *starts,
+                                                                          int n_items)
 {
-    // butterfly over the S consecutive lanes of a group (S divides 64)
-#pragma unroll
-    for (int off = S / 2; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, S);
-    return v;
-}
-
-// One j-body of a mixed-precision tile, read from LDS.
-struct JMixed {
-    double x, y, z;
-    float vx, vy, vz, m;
-};
-
-// Acceleration and jerk terms of one j-body on IL i-bodies, FP32 after the FP64
-// position difference, added to the FP32 run accumulators.
-template <int IL>
-__device__ __forceinline__ void pair_mixed(const JMixed &j, const double (&xi)[IL],
-                                           const double (&yi)[IL], const double (&zi)[IL],
-                                           const float (&vxi)[IL], const float (&vyi)[IL],
-                                           const float (&vzi)[IL], float eps2,
-                                           float (&a32)[IL][3], float (&j32)[IL][3])
-{
-#pragma unroll
-    for (int u = 0; u < IL; ++u) {
-        const float dx = (float)(j.x - xi[u]);
-        const float dy = (float)(j.y - yi[u]);
-        const float dz = (float)(j.z - zi[u]);
-        const float dvx = j.vx - vxi[u], dvy = j.vy - vyi[u], dvz = j.vz - vzi[u];
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-        const float rv = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float rinv2 = rinv * rinv;
-        const float mr3 = j.m * rinv * rinv2;
-        const float al = -3.0f * rv * rinv2;
-        a32[u][0] = fmaf(mr3, dx, a32[u][0]);
-        a32[u][1] = fmaf(mr3, dy, a32[u][1]);
-        a32[u][2] = fmaf(mr3, dz, a32[u][2]);
-        j32[u][0] = fmaf(mr3, fmaf(al, dx, dvx), j32[u][0]);
-        j32[u][1] = fmaf(mr3, fmaf(al, dy, dvy), j32[u][1]);
-        j32[u][2] = fmaf(mr3, fmaf(al, dz, dvz), j32[u][2]);
-    }
-}
-
-#ifndef NBK_KAHAN
-#define NBK_KAHAN 0
-#endif
-#ifndef NBK_MIXED_WAVES
-#define NBK_MIXED_WAVES 1
-#endif
-#ifndef NBK_PREFETCH
-#define NBK_PREFETCH 1
-#endif
-
-// Running total of the FP32 run sums: FP64, or (NBK_KAHAN) an FP32 Kahan pair.
-struct Total {
-#if NBK_KAHAN
-    float s = 0.f, c = 0.f;
-    __device__ __forceinline__ void add(float v)
-    {
-        const float y = v - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-#else
-    double s = 0.0;
-    __device__ __forceinline__ void add(float v) { s += (double)v; }
-    __device__ __forceinline__ double value() const { return s; }
-#endif
-};
-
-template <int IL, int S, int F>
-__global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const Item *items, const int64_t *starts,
-                                                         int n_items)
-{
-    __shared__ double sx[TILE], sy[TILE], sz[TILE];
-    __shared__ float svx[TILE], svy[TILE], svz[TILE], sm[TILE];
+    __shared__ Tile<DS> tile;
 
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
@@ -132,7 +64,7 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
     const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp;
     const float *vx32 = p.s.vxp32, *vy32 = p.s.vyp32, *vz32 = p.s.vzp32, *m32 = p.s.m32;
 
-    double xi[IL], yi[IL], zi[IL];
+    IPos<DS> pi[IL];
     float vxi[IL], vyi[IL], vzi[IL];
     Total A[IL][3], J[IL][3];
 #pragma unroll
@@ -146,7 +78,7 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
                 i = 0;
             }
         }
-        xi[u] = xp[i]; yi[u] = yp[i]; zi[u] = zp[i];
+        pi[u] = ipos(xp[i], yp[i], zp[i], (IPos<DS> *)nullptr);
         vxi[u] = vx32[i]; vyi[u] = vy32[i]; vzi[u] = vz32[i];
     }
 
@@ -154,14 +86,10 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
         __syncthreads();
         for (int q = tid; q < TILE; q += WG) {
             const int64_t j = jt + q;
-            if (j < je) {
-                sx[q] = xp[j]; sy[q] = yp[j]; sz[q] = zp[j];
-                svx[q] = vx32[j]; svy[q] = vy32[j]; svz[q] = vz32[j];
-                sm[q] = m32[j];
-            } else {  // padding: zero mass contributes exactly zero
-                sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0;
-                svx[q] = 0.f; svy[q] = 0.f; svz[q] = 0.f; sm[q] = 0.f;
-            }
+            if (j < je)
+                tile.put(q, xp[j], yp[j], zp[j], vx32[j], vy32[j], vz32[j], m32[j]);
+            else  // padding: zero mass contributes exactly zero
+                tile.put(q, 0.0, 0.0, 0.0, 0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
         const int lim = (int)min<int64_t>(TILE, je - jt);
@@ -172,21 +100,31 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; }
 #if NBK_PREFETCH
-            JMixed cur{sx[kk + s], sy[kk + s], sz[kk + s], svx[kk + s], svy[kk + s], svz[kk + s],
-                       sm[kk + s]};
+            JBody<DS> cur = tile.get(kk + s);
 #pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
                 const int qn = kk + (f + 1 < F ? f + 1 : f) * S + s;
-                const JMixed nxt{sx[qn], sy[qn], sz[qn], svx[qn], svy[qn], svz[qn], sm[qn]};
-                pair_mixed<IL>(cur, xi, yi, zi, vxi, vyi, vzi, eps2, a32, j32);
+                const JBody<DS> nxt = tile.get(qn);
+#pragma unroll
+                for (int u = 0; u < IL; ++u) {
+                    float dx, dy, dz;
+                    diff(cur, pi[u], dx, dy, dz);
+                    pair_f32(dx, dy, dz, cur.vx - vxi[u], cur.vy - vyi[u], cur.vz - vzi[u], cur.m,
+                             eps2, a32[u], j32[u]);
+                }
                 cur = nxt;
             }
 #else
 #pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
-                const int q = kk + f * S + s;
-                const JMixed cur{sx[q], sy[q], sz[q], svx[q], svy[q], svz[q], sm[q]};
-                pair_mixed<IL>(cur, xi, yi, zi, vxi, vyi, vzi, eps2, a32, j32);
+                const JBody<DS> cur = tile.get(kk + f * S + s);
+#pragma unroll
+                for (int u = 0; u < IL; ++u) {
+                    float dx, dy, dz;
+                    diff(cur, pi[u], dx, dy, dz);
+                    pair_f32(dx, dy, dz, cur.vx - vxi[u], cur.vy - vyi[u], cur.vz - vzi[u], cur.m,
+                             eps2, a32[u], j32[u]);
+                }
             }
 #endif
 #pragma unroll
@@ -352,8 +290,11 @@ static hipError_t launch_one(int precision, const Table &t, hipStream_t st)
 {
     const dim3 grid((unsigned)t.blocks);
     if (precision == NB_MIXED)
-        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>()>), grid, dim3(WG), 0, st,
-                           t.items, t.starts, t.n);
+        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>(), false>), grid, dim3(WG), 0,
+                           st, t.items, t.starts, t.n);
+    else if (precision == NB_DS)
+        hipLaunchKernelGGL((force_mixed_kernel<IL, S, fold_mixed<S>(), true>), grid, dim3(WG), 0,
+                           st, t.items, t.starts, t.n);
     else
         hipLaunchKernelGGL((force_fp64_kernel<IL, S, fold_fp64<S>()>), grid, dim3(WG), 0, st,
                            t.items, t.starts, t.n);
@@ -384,23 +325,26 @@ hipError_t launch_force(int precision, int il, int s, const Table &t, hipStream_
 }
 
 // One thread per output value of every item with j_chunks > 1: the B partials
-// are summed in ascending chunk order.
+// are summed in ascending chunk order (6 values per body, 9 for the 6th order).
 __global__ __launch_bounds__(WG) void reduce_partials_kernel(const Item *items,
                                                              const int64_t *starts, int n_items)
 {
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
-    const int64_t idx = ((int64_t)blockIdx.x - starts[it_k]) * WG + threadIdx.x;   // < 6m
-    const int64_t six_m = 6 * (int64_t)p.m;
-    if (idx >= six_m)
+    const int64_t idx = ((int64_t)blockIdx.x - starts[it_k]) * WG + threadIdx.x;   // < K m
+    const int64_t three_m = 3 * (int64_t)p.m;
+    const int64_t km = force_outputs(p) * three_m / 3;
+    if (idx >= km)
         return;
     double v = 0.0;
     for (int b = 0; b < p.b; ++b)
-        v += p.part[(int64_t)b * six_m + idx];
-    if (idx < 3 * (int64_t)p.m)
+        v += p.part[(int64_t)b * km + idx];
+    if (idx < three_m)
         p.acc[idx] = v;
+    else if (idx < 2 * three_m)
+        p.jerk[idx - three_m] = v;
     else
-        p.jerk[idx - 3 * (int64_t)p.m] = v;
+        p.snap[idx - 2 * three_m] = v;
 }
 
 hipError_t launch_reduce(const Table &t, hipStream_t st)

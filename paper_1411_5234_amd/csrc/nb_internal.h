@@ -66,6 +66,8 @@ struct Item {
     nb_system s;                 // the system's arrays
     const int32_t *i_idx;        // active list, or null for i = k
     double *acc, *jerk;          // force outputs / corrector inputs, rows c*m + k
+    double *snap;                // 6th order: third output / input, else null
+    nb_hermite6 h6;              // 6th order: snap, crackle, predicted acceleration
     double *part;                // force partials of this item (j_chunks > 1)
     int *status;                 // error word
     double eps2;                 // softening squared
@@ -108,7 +110,12 @@ __device__ __forceinline__ int find_item(const int64_t *starts, int n, int64_t b
 
 // Force kernels for one plan shape (IL i-bodies per lane, S lanes per i-body).
 hipError_t launch_force(int precision, int il, int s, const Table &t, hipStream_t st);
-// acc/jerk[c*m + k] = sum_b part[b*6m + c*m + k] (ascending b), one thread per value.
+// 6th order: acceleration, jerk and snap.
+hipError_t launch_force6(int precision, int il, int s, const Table &t, hipStream_t st);
+// Outputs per active body: 6 (acc, jerk) or 9 (acc, jerk, snap).
+__host__ __device__ inline int force_outputs(const Item &it) { return it.snap ? 9 : 6; }
+// out[c*m + k] = sum_b part[b*K*m + c*m + k] (ascending b, K = force_outputs),
+// one thread per value, written to acc, jerk (and snap).
 hipError_t launch_reduce(const Table &t, hipStream_t st);
 // Energy of one system: rows[i] = m_i sum_{j != i} m_j / sqrt(r^2 + eps^2), then
 // compensated totals (kinetic, potential) into out[2].
@@ -125,5 +132,10 @@ hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_m
                           hipStream_t st);
 hipError_t launch_init_steps(const Table &t, double eta_s, double dt_max, double dt_min,
                              hipStream_t st);
+hipError_t launch_predict6(const Table &t, hipStream_t st);
+hipError_t launch_correct6(const Table &t, double eta, double dt_max, double dt_min,
+                           hipStream_t st);
+hipError_t launch_init_steps6(const Table &t, double eta_s, double dt_max, double dt_min,
+                              hipStream_t st);
 
 }  // namespace nbk

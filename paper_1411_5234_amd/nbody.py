@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FIELDS32, FIELDS64, NbError, NbSystem, PRECISIONS
+from ._lib import (FIELDS32, FIELDS64, H6_FIELDS32, H6_FIELDS64, NbError, NbHermite6, NbSystem,
+                   PRECISIONS)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -87,6 +88,36 @@ class System:
                 "xp": h[15:18].T.copy(), "vp": h[18:21].T.copy()}
 
 
+class Hermite6:
+    """The extra device arrays of the 6th-order scheme for one System: snap and
+    crackle at the bodies' own times and the predicted acceleration (FP64 rows in
+    H6_FIELDS64 order), plus FP32 copies of the predicted acceleration for the
+    mixed and double-single forces.  All start at zero."""
+
+    BYTES_PER_BODY = 8 * len(H6_FIELDS64) + 4 * len(H6_FIELDS32)
+
+    def __init__(self, sys: System, fp32_copies: bool = True):
+        self.n = sys.n
+        n = max(sys.n, 1)
+        self.buf64 = torch.zeros((len(H6_FIELDS64), n), dtype=torch.float64, device=sys.device)
+        self.buf32 = (torch.zeros((len(H6_FIELDS32), n), dtype=torch.float32, device=sys.device)
+                      if fp32_copies else None)
+        self._struct = NbHermite6()
+        for k, f in enumerate(H6_FIELDS64):
+            setattr(self._struct, f, self.buf64[k].data_ptr())
+        for k, f in enumerate(H6_FIELDS32):
+            setattr(self._struct, f, self.buf32[k].data_ptr() if self.buf32 is not None else None)
+
+    @property
+    def ref(self):
+        return C.byref(self._struct)
+
+    def state_numpy(self) -> dict:
+        """Snap s, crackle c and predicted acceleration ap as numpy (n, 3)."""
+        h = self.buf64[:, : self.n].cpu().numpy()
+        return {"s": h[0:3].T.copy(), "c": h[3:6].T.copy(), "ap": h[6:9].T.copy()}
+
+
 class Context:
     """An nb_ctx bound to one device and one torch (HIP) stream."""
 
@@ -151,6 +182,37 @@ class Context:
     def correct(self, sys: System, i_idx, m, acc, jerk, t_next, eta, dt_max, dt_min):
         self._check(self.L.nb_correct(self.h, sys.ref, _ptr(i_idx), int(m), _ptr(acc), _ptr(jerk),
                                       float(t_next), float(eta), float(dt_max), float(dt_min)))
+
+    # ---- 6th order ------------------------------------------------------------------
+    def predict6(self, sys: System, h6: Hermite6, t_next: float):
+        self._check(self.L.nb_predict6(self.h, sys.ref, h6.ref, float(t_next)))
+
+    def force6_active(self, sys: System, h6: Hermite6, i_idx: torch.Tensor | None, m: int,
+                      j0: int, j1: int, eps: float, precision: str, acc: torch.Tensor,
+                      jerk: torch.Tensor, snap: torch.Tensor, plan: tuple | None = None):
+        prec = PRECISIONS[precision]
+        if min(acc.numel(), jerk.numel(), snap.numel()) < 3 * m:
+            raise ValueError("acc/jerk/snap need 3*m elements")
+        if plan is None:
+            rc = self.L.nb_force6_active(self.h, sys.ref, h6.ref, _ptr(i_idx), int(m), int(j0),
+                                         int(j1), float(eps), prec, _ptr(acc), _ptr(jerk),
+                                         _ptr(snap))
+        else:
+            il, s, b = plan
+            rc = self.L.nb_force6_active_plan(self.h, sys.ref, h6.ref, _ptr(i_idx), int(m),
+                                              int(j0), int(j1), float(eps), prec, int(il), int(s),
+                                              int(b), _ptr(acc), _ptr(jerk), _ptr(snap))
+        self._check(rc)
+
+    def init_steps6(self, sys: System, h6: Hermite6, acc, jerk, snap, eta_s, dt_max, dt_min):
+        self._check(self.L.nb_init_steps6(self.h, sys.ref, h6.ref, _ptr(acc), _ptr(jerk),
+                                          _ptr(snap), float(eta_s), float(dt_max), float(dt_min)))
+
+    def correct6(self, sys: System, h6: Hermite6, i_idx, m, acc, jerk, snap, t_next, eta,
+                 dt_max, dt_min):
+        self._check(self.L.nb_correct6(self.h, sys.ref, h6.ref, _ptr(i_idx), int(m), _ptr(acc),
+                                       _ptr(jerk), _ptr(snap), float(t_next), float(eta),
+                                       float(dt_max), float(dt_min)))
 
     def energy(self, sys: System, eps: float):
         k, p = C.c_double(), C.c_double()
@@ -223,3 +285,56 @@ class Integrator:
             self._advance(t_next, m)
         self.ctx.sync()
         return self.steps, self.interactions
+
+
+@dataclass
+class Params6(Params):
+    """Step parameters of the 6th-order scheme.  Its criterion gives dt = eta/omega
+    on a circular orbit where Aarseth's 4th-order one gives sqrt(eta)/omega, so
+    eta = 0.14 takes the steps of the 4th-order eta = 0.02 there."""
+
+    eta: float = 0.14
+
+
+class Integrator6(Integrator):
+    """Hermite-6 block-step driver: select, predict to the crackle, force with
+    snap, 6th-order correct."""
+
+    def __init__(self, ctx: Context, sys: System, p: Params6, h6: Hermite6 | None = None):
+        super().__init__(ctx, sys, p)
+        self.h6 = h6 if h6 is not None else Hermite6(sys, fp32_copies=sys.buf32 is not None)
+        self.snap = torch.zeros((3, max(sys.n, 1)), dtype=torch.float64, device=sys.device)
+
+    def _force6(self, i_idx, m):
+        n = self.sys.n
+        acc = self.acc.view(-1)[: 3 * m]
+        jerk = self.jerk.view(-1)[: 3 * m]
+        snap = self.snap.view(-1)[: 3 * m]
+        self.ctx.force6_active(self.sys, self.h6, i_idx, m, 0, n, self.p.eps, self.p.precision,
+                               acc, jerk, snap)
+        return acc, jerk, snap
+
+    def startup(self):
+        """t = 0, every body active.  A first pass gives the accelerations the
+        snap needs (stored as the state by the 4th-order startup, which also sets
+        t = 0); the prediction to t = 0 copies them into the predicted
+        acceleration; the second pass gives acceleration, jerk and snap."""
+        n = self.sys.n
+        p = self.p
+        acc, jerk = self._force(None, n)
+        self.ctx.init_steps(self.sys, acc, jerk, p.eta_s, p.dt_max, p.dt_min)
+        self.ctx.predict6(self.sys, self.h6, 0.0)
+        acc, jerk, snap = self._force6(None, n)
+        self.ctx.init_steps6(self.sys, self.h6, acc, jerk, snap, p.eta_s, p.dt_max, p.dt_min)
+        self.interactions += 2 * n * n
+        self.t = 0.0
+
+    def _advance(self, t_next, m):
+        p = self.p
+        self.ctx.predict6(self.sys, self.h6, t_next)
+        acc, jerk, snap = self._force6(self.i_idx, m)
+        self.ctx.correct6(self.sys, self.h6, self.i_idx, m, acc, jerk, snap, t_next, p.eta,
+                          p.dt_max, p.dt_min)
+        self.steps += 1
+        self.interactions += m * self.sys.n
+        self.t = t_next

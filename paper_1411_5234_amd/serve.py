@@ -60,7 +60,7 @@ class _Slot:
         self.req = req
         self.n = snap.n
         self.sys = System.from_arrays(snap.x, snap.v, snap.m, device=device,
-                                      fp32_copies=(precision == "mixed"))
+                                      fp32_copies=(precision != "fp64"))
         n1 = max(self.n, 1)
         self.i_idx = torch.zeros(n1, dtype=torch.int32, device=device)
         self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=device)
@@ -80,7 +80,7 @@ class _Slot:
 
 def footprint_bytes(n: int, precision: str = "mixed") -> int:
     """Device bytes one resident system of n bodies holds (state + work buffers)."""
-    per_body = 8 * 21 + (16 if precision == "mixed" else 0) + 4 + 48
+    per_body = 8 * 21 + (16 if precision != "fp64" else 0) + 4 + 48
     return per_body * max(n, 1) + 4 + 1024
 
 

@@ -3,10 +3,17 @@ import numpy as np
 import torch
 
 # Per-body gates.  FP64 path: |g - o| / |o| <= 1e-12 for acceleration and jerk.
-# Mixed path: acceleration |g - o| / |o| <= 1e-6; jerk |g - o| / S_j <= 1e-6 with
+# Mixed and DS paths: acceleration |g - o| / |o| <= 1e-6; jerk |g - o| / S_j <= 1e-6 with
 # S_j = sum_j |jerk_ij| (FP32 pair terms carry a few ulp of error each, and the
 # jerk of a body can be a sum of terms up to ~60x larger than the result).
-TOL = {"fp64": 1e-12, "mixed": 1e-6}
+TOL = {"fp64": 1e-12, "mixed": 1e-6, "ds": 1e-6}
+# Snap (6th order): |g - o| / S_s with S_s = sum_j |snap_ij|.  A pair's snap term
+# passes through about a dozen FP32 roundings (the hardware reciprocal square root,
+# mu, alpha, beta, u and the three-part snap term) before joining an FP32 run sum
+# of up to 32 terms, so its error is bounded by about 32 u = 32 * 2^-24 = 1.9e-6
+# of S_s; a CPU emulation of the same FP32 operations reaches 0.84e-6 on the
+# N = 1024 Plummer sphere.
+TOL_SNAP = {"fp64": 1e-12, "mixed": 2e-6, "ds": 2e-6}
 
 
 def device_system(x, v, m, fp32=True):
@@ -53,7 +60,60 @@ def check(orc, precision, ga, gj, x, v, m, eps, ilist=None, j0=0, j1=None, tag="
     else:
         sa, sj = orc.force_scale(x, v, m, eps, ilist, j0, j1)
         nj = np.linalg.norm(gj[keep] - oj[keep], axis=1) / sj[keep]
-        print("   mixed jerk error / sum|jerk_ij|: max %.3e" % nj.max(initial=0), flush=True)
-        assert ea.max(initial=0) <= TOL["mixed"], ea.max()
-        assert nj.max(initial=0) <= TOL["mixed"], nj.max()
+        print("   %s jerk error / sum|jerk_ij|: max %.3e" % (precision, nj.max(initial=0)), flush=True)
+        assert ea.max(initial=0) <= TOL[precision], ea.max()
+        assert nj.max(initial=0) <= TOL[precision], nj.max()
     return oa, oj
+
+
+# ---- 6th order -------------------------------------------------------------------
+
+def device_system6(x, v, m, ap, fp32=True):
+    """A System whose predicted set is (x, v) and a Hermite6 whose predicted
+    acceleration is `ap` (FP64 and FP32 copies)."""
+    from paper_1411_5234_amd.nbody import Hermite6
+    sys = device_system(x, v, m, fp32)
+    h6 = Hermite6(sys, fp32_copies=fp32)
+    if sys.n:
+        h6.buf64[6:9, : sys.n] = torch.from_numpy(np.ascontiguousarray(np.asarray(ap).T)).cuda()
+        if fp32:
+            h6.buf32[:, : sys.n] = h6.buf64[6:9, : sys.n].float()
+    return sys, h6
+
+
+def gpu_force6(ctx, sys, h6, eps, precision, ilist=None, j0=0, j1=None, plan=None):
+    n = sys.n
+    m = n if ilist is None else len(ilist)
+    idx = None if ilist is None else torch.as_tensor(np.asarray(ilist, dtype=np.int32), device="cuda")
+    out = [torch.full((3 * max(m, 1),), np.nan, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ctx.force6_active(sys, h6, idx, m, j0, n if j1 is None else j1, eps, precision, *out, plan=plan)
+    ctx.sync()
+    return tuple(o[: 3 * m].view(3, m).T.cpu().numpy() for o in out)
+
+
+def check6(orc, precision, g, x, v, ap, m, eps, ilist=None, j0=0, j1=None, tag=""):
+    """Compare GPU (acc, jerk, snap) with the oracle.  Acceleration: relative error
+    per body.  Jerk and snap: error over the magnitude scale sum_j |term_ij| of
+    each sum (both can be sums of terms much larger than the result), gated by
+    TOL and TOL_SNAP.  FP64 additionally gates the relative jerk error."""
+    ga, gj, gs = g
+    oa, oj, os_ = orc.force6(x, v, ap, m, eps, ilist, j0, j1)
+    keep = np.linalg.norm(oa, axis=1) > 0
+    ea = rel_err(ga[keep], oa[keep])
+    _, sj = orc.force_scale(x, v, m, eps, ilist, j0, j1)
+    ss = orc.force6_scale(x, v, ap, m, eps, ilist, j0, j1)
+    nj = np.linalg.norm(gj[keep] - oj[keep], axis=1) / sj[keep]
+    ns = np.linalg.norm(gs[keep] - os_[keep], axis=1) / ss[keep]
+    es = rel_err(gs[keep], os_[keep])
+    print("%s %s: acc rel max %.3e | jerk/scale max %.3e | snap/scale max %.3e (snap rel max %.3e)"
+          % (tag, precision, ea.max(initial=0), nj.max(initial=0), ns.max(initial=0),
+             es.max(initial=0)), flush=True)
+    tol = TOL[precision]
+    assert ea.max(initial=0) <= tol, ea.max()
+    assert nj.max(initial=0) <= tol, nj.max()
+    assert ns.max(initial=0) <= TOL_SNAP[precision], ns.max()
+    if precision == "fp64":
+        ej = rel_err(gj[keep], oj[keep])
+        assert ej.max(initial=0) <= tol, ej.max()
+    assert np.all(ga[~keep] == 0.0) and np.all(gj[~keep] == 0.0) and np.all(gs[~keep] == 0.0)
+    return oa, oj, os_

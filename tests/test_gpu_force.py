@@ -1,8 +1,9 @@
 """GPU parity of nb_force_active (acc + jerk) against the FP64 oracle.
 
 Gates (maximum over bodies): FP64 path, relative error of acceleration and jerk
-<= 1e-12; mixed path, relative acceleration error <= 1e-6 and jerk error <= 1e-6
-of the jerk's magnitude scale sum_j |jerk_ij| (see gpu_helpers).  Cases: the N = 1024 Plummer sphere with
+<= 1e-12; mixed and double-single (DS) paths, relative acceleration error <= 1e-6
+and jerk error <= 1e-6 of the jerk's magnitude scale sum_j |jerk_ij| (see
+gpu_helpers).  Cases: the N = 1024 Plummer sphere with
 every body active, the N = 65536 Salpeter cluster with active blocks of 64 .. 4096
 (plus sampled bodies of larger blocks), ragged sizes and j-ranges, every launch
 plan shape, bitwise repeatability, empty blocks, error paths, and the N = 2^20
@@ -33,7 +34,7 @@ def c2():
     return s
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_plummer_1024_all_active(ctx, orc, precision):
     s = inputs.plummer(1024, 1)
     sys = device_system(s.x, s.v, s.m)
@@ -41,7 +42,7 @@ def test_plummer_1024_all_active(ctx, orc, precision):
     check(orc, precision, ga, gj, s.x, s.v, s.m, 1e-3, tag="N=1024")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 @pytest.mark.parametrize("m", [64, 256, 1000, 4096])
 def test_salpeter_65536_active_blocks(ctx, orc, c2, precision, m):
     perm = np.random.default_rng(20).permutation(c2.n)[:m]
@@ -51,7 +52,7 @@ def test_salpeter_65536_active_blocks(ctx, orc, c2, precision, m):
     check(orc, precision, ga, gj, c2.x, c2.v, c2.m, 1e-4, il, tag="N=65536 m=%d" % m)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 @pytest.mark.parametrize("m", [16384, 65536])
 def test_salpeter_65536_large_blocks_sampled(ctx, orc, c2, precision, m):
     il = np.sort(np.random.default_rng(21).permutation(c2.n)[:m])
@@ -62,7 +63,7 @@ def test_salpeter_65536_large_blocks_sampled(ctx, orc, c2, precision, m):
           tag="N=65536 m=%d (512 sampled)" % m)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_ragged_sizes_and_j_ranges(ctx, orc, precision):
     s = inputs.plummer(1000, 8, masses=inputs.salpeter_masses(1000, 9))
     sys = device_system(s.x, s.v, s.m)
@@ -76,7 +77,7 @@ def test_ragged_sizes_and_j_ranges(ctx, orc, precision):
         assert np.all(ga[~nz] == 0.0) and np.all(gj[~nz] == 0.0)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_every_plan_shape_matches(ctx, orc, precision):
     s = inputs.plummer(3000, 12)
     sys = device_system(s.x, s.v, s.m)
@@ -96,7 +97,7 @@ def test_every_plan_shape_matches(ctx, orc, precision):
                     assert (np.linalg.norm(gj - oj, axis=1) / sj).max() <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_bitwise_repeatable(ctx, precision):
     s = inputs.plummer(5000, 13)
     sys = device_system(s.x, s.v, s.m)
@@ -136,7 +137,7 @@ def test_argument_errors(ctx):
     ctx.sync()   # the word was cleared by the failing sync
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed", "ds", "fp64"])
 def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
     n = 1 << 20
     s = inputs.plummer(n, 3)

@@ -37,7 +37,7 @@ def _serve(ctx, reqs, precision="mixed", **kw):
     return {r.rid: r for r in res}, srv
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed", "ds", "fp64"])
 def test_same_result_alone_and_in_a_mix(ctx, precision):
     target = _req(0, 700, 11)
     alone, _ = _serve(ctx, [target], precision)
@@ -59,7 +59,7 @@ def test_served_equals_single_system_integrator(ctx, precision):
     req = _req(0, 512, 21, t_end=0.25)
     served, _ = _serve(ctx, [req, _req(1, 1024, 22)], precision)
     snap = req.snapshot()
-    sys_ = System.from_arrays(snap.x, snap.v, snap.m, fp32_copies=(precision == "mixed"))
+    sys_ = System.from_arrays(snap.x, snap.v, snap.m, fp32_copies=(precision != "fp64"))
     it = Integrator(ctx, sys_, Params(eps=req.eps, precision=precision))
     it.startup()
     steps, inter = it.run(req.t_end)
