@@ -518,13 +518,14 @@ static double hermite5_crackle(double h, double a0, double j0, double s0, double
  *   v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
  *   x1 = x0 + h/2 (v0 + v1) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1)
  * The crackle c1 at t_next comes from the degree-5 Hermite interpolant of the
- * step and is stored for the predictor.  New step: the generalized Aarseth
- * criterion in its lowest form, from the new acceleration, jerk and snap and the
- * interpolated crackle,
- *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||c1|) + |s1|),
- * kept a power of two by the same rule as the 4th-order scheme.  (The forms that
- * use the interpolant's 4th and 5th derivatives amplify the error of the forces
- * by h^-4 and h^-5.)
+ * step and is stored for the predictor.  New step, from the directly computed
+ * acceleration, jerk and snap only:
+ *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|),
+ * the generalized Aarseth form with its lowest interpolated term replaced by
+ * one of the same dimension built from a and j (eta/omega on circular orbits),
+ * kept a power of two by the same rule as the 4th-order scheme.  Derivatives
+ * taken from the interpolant carry the forces' rounding error multiplied by
+ * h^-3 (crackle) to h^-5 and are left out.
  * dta_out (may be NULL) receives the unquantised dtA.
  */
 int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
@@ -560,8 +561,7 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
         }
         const double an = norm3(acc_new + 3 * k), jn = norm3(jerk_new + 3 * k),
                      sN = norm3(snap_new + 3 * k);
-        const double cn = norm3(d3v);
-        const double num = sqrt(an * sN) + jn, den = sqrt(jn * cn) + sN;
+        const double num = sqrt(an * sN) + jn, den = sN + (an > 0.0 ? jn * jn / an : 0.0);
         double dta = den > 0.0 ? eta * (num / den) : INFINITY;
         if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
             return -5;

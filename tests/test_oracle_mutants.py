@@ -85,7 +85,9 @@ MUTANTS = [
      lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
     ("criterion ratio under a square root", "eta * (num / den)", "eta * sqrt(num / den)",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 0.5)),
-    ("criterion denominator without the square root", "sqrt(jn * cn) + sN", "jn * cn + sN",
+    ("criterion denominator |j|/|a| instead of |j|^2/|a|", "jn * jn / an", "jn / an",
+     lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
+    ("criterion denominator without |s|", "den = sN + (an", "den = 0.0 + (an",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
     ("criterion numerator without |j|", "num = sqrt(an * sN) + jn,", "num = sqrt(an * sN),",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
