@@ -280,12 +280,13 @@ nb_status nb_init_steps6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h
  *   crackle = -3 (20 (a0 - a1) + h^2 (s0 - 3 s1) + h (8 j0 + 12 j1)) / h^3
  * (the third derivative at t_next of the degree-5 interpolant of (a, j, s) at
  * both ends), a, j, s = a1, j1, s1, t = t_next, and the new step from the
- * generalized Aarseth criterion in its lowest form
- *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||crackle|) + |s1|),
- * kept a power of two by the rule of nb_correct.  (The higher forms of the
- * criterion need the interpolant's 4th and 5th derivatives, which amplify the
- * error of FP32 pair arithmetic by h^-4 and h^-5 and then drive the steps to
- * dt_min.)  Errors latched as nb_correct. */
+ * directly computed acceleration, jerk and snap
+ *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|)
+ * (eta/omega on a circular orbit), kept a power of two by the rule of
+ * nb_correct.  (Criteria that use the crackle or higher derivatives of the
+ * interpolant amplify the rounding error of FP32 pair arithmetic by h^-3 to
+ * h^-5, which at small steps drives them to dt_min.)  Errors latched as
+ * nb_correct. */
 nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
                       const int32_t *i_idx, int32_t m, const double *acc, const double *jerk,
                       const double *snap, double t_next, double eta, double dt_max,

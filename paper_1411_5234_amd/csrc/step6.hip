@@ -59,10 +59,10 @@ __device__ __forceinline__ double len3(const double (&u)[3])
 // Corrector of the active bodies.  The two-point quadratures use (a, j, s) at
 // both ends of the step; the crackle at the step's end is that of the degree-5
 // polynomial matching (a, j, s) at both ends, written out in closed form.  New
-// step: the generalized Aarseth criterion in its lowest form (acceleration,
-// jerk, snap and the interpolated crackle), kept a power of two as in the
-// 4th-order corrector.  The interpolant's 4th and 5th derivatives are not used:
-// they amplify the error of reduced-precision forces by h^-4 and h^-5.
+// step from the directly computed acceleration, jerk and snap only,
+// eta (sqrt(|a||s|) + |j|) / (|s| + |j|^2/|a|), kept a power of two as in the
+// 4th-order corrector: derivatives taken from the interpolant carry the forces'
+// rounding error multiplied by h^-3 to h^-5.
 __global__ __launch_bounds__(WG) void correct6_kernel(const Item *items, const int64_t *starts,
                                                       int n_items, double eta, double dt_max,
                                                       double dt_min)
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(WG) void correct6_kernel(const Item *items, const i
     }
     const double an = len3(a1v), jn = len3(j1v), sN = len3(s1v);
     const double num = sqrt(an * sN) + jn;
-    const double den = sqrt(jn * len3(c1v)) + sN;
+    const double den = sN + (an > 0.0 ? jn * jn / an : 0.0);
     const double dta = den > 0.0 ? eta * (num / den) : INFINITY;
     int err = 0;
     if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
