@@ -69,6 +69,9 @@ def lib():
         L.orc_force6_scale.restype = C.c_int
         L.orc_force6_scale.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
                                        C.c_int64, C.c_double, _dp]
+        L.orc_init_dt6.restype = C.c_int
+        L.orc_init_dt6.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                   _dp]
         L.orc_predict6.restype = None
         L.orc_predict6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
                                    _dp, _dp, _dp]
@@ -295,6 +298,15 @@ def force6_scale(x, v, a, m, eps, ilist=None, j0=0, j1=None):
     return ss
 
 
+def init_dt6(a, jk, sn, eta_s, dt_max, dt_min):
+    """Startup steps of the 6th-order scheme from acceleration, jerk and snap."""
+    a, jk, sn = _c(a), _c(jk), _c(sn)
+    dt = np.empty(a.shape[0])
+    _check(lib().orc_init_dt6(a.shape[0], a, jk, sn, float(eta_s), float(dt_max), float(dt_min),
+                              dt))
+    return dt
+
+
 def predict6(x, v, a, jk, sn, cr, t, t_next):
     """Taylor prediction of position (to crackle), velocity and acceleration."""
     x, v, a, jk, sn, cr, t = (_c(q) for q in (x, v, a, jk, sn, cr, t))
@@ -344,14 +356,14 @@ class Params6(Params):
 def startup6(x, v, m, p: Params6) -> State6:
     """t = 0: every body active.  A first pass gives the accelerations that the
     snap needs; the second gives acceleration, jerk and snap.  The crackle
-    starts at zero; the first correction replaces it.  Startup steps as in the
-    4th-order scheme."""
+    starts at zero; the first correction replaces it.  Startup steps from
+    acceleration, jerk and snap (init_dt6)."""
     x, v, m = _c(x).copy(), _c(v).copy(), _c(m).copy()
     a0, _ = force(x, v, m, p.eps)
     a, jk, sn = force6(x, v, a0, m, p.eps)
     n = m.shape[0]
     st = State6(x, v, m, a, jk, np.zeros(n), None, sn, np.zeros((n, 3)))
-    st.dt = init_dt(st.a, st.j, p.eta_s, p.dt_max, p.dt_min)
+    st.dt = init_dt6(st.a, st.j, st.s, p.eta_s, p.dt_max, p.dt_min)
     return st
 
 

@@ -436,6 +436,36 @@ int orc_force6_scale(int64_t n, const double *x, const double *v, const double *
     return 0;
 }
 
+/* ---- 6th-order startup step ------------------------------------------------------
+ * At t = 0 every body gets dt = the largest power of two not above
+ * min(eta_s (sqrt(|a||s|) + |j|) / (|s| + |j|^2 / |a|), dt_max): the step form of
+ * the 6th-order scheme from the computed acceleration, jerk and snap (no crackle
+ * exists yet).  It equals eta_s/omega on a circular orbit, like the 4th-order
+ * rule eta_s |a|/|j|, and also sees an approaching neighbour through the snap.
+ * Returns 0, -4 if a step falls below dt_min, -5 on a non-finite value.
+ */
+int orc_init_dt6(int64_t n, const double *a, const double *jk, const double *sn,
+                 double eta_s, double dt_max, double dt_min, double *dt)
+{
+    for (int64_t i = 0; i < n; i++) {
+        const double an = norm3(a + 3 * i), jn = norm3(jk + 3 * i), sm = norm3(sn + 3 * i);
+        if (!isfinite(an) || !isfinite(jn) || !isfinite(sm))
+            return -5;
+        const double top = sqrt(an * sm) + jn;
+        const double bottom = sm + (an > 0.0 ? jn * jn / an : 0.0);
+        double want = (bottom > 0.0) ? eta_s * (top / bottom) : dt_max;
+        if (want > dt_max)
+            want = dt_max;
+        double pow2 = dt_max;
+        while (pow2 > want)
+            pow2 /= 2.0;
+        if (pow2 < dt_min)
+            return -4;
+        dt[i] = pow2;
+    }
+    return 0;
+}
+
 /* ---- 6th-order predictor --------------------------------------------------------
  * d = t_next - t_i:
  *   xp = x + v d + a d^2/2 + j d^3/6 + s d^4/24 + c d^5/120
@@ -518,14 +548,19 @@ static double hermite5_crackle(double h, double a0, double j0, double s0, double
  *   v1 = v0 + h/2 (a0 + a1) - h^2/10 (j1 - j0) + h^3/120 (s0 + s1)
  *   x1 = x0 + h/2 (v0 + v1) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1)
  * The crackle c1 at t_next comes from the degree-5 Hermite interpolant of the
- * step and is stored for the predictor.  New step, from the directly computed
- * acceleration, jerk and snap only:
- *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|),
- * the generalized Aarseth form with its lowest interpolated term replaced by
- * one of the same dimension built from a and j (eta/omega on circular orbits),
- * kept a power of two by the same rule as the 4th-order scheme.  Derivatives
- * taken from the interpolant carry the forces' rounding error multiplied by
- * h^-3 (crackle) to h^-5 and are left out.
+ * step and is stored for the predictor.  New step: the lowest generalized
+ * Aarseth form
+ *   dtC = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||c1|) + |s1|),
+ * not below one eighth of the same form with the crackle term replaced by
+ * |j1|^2/|a1| (a term of the same dimension built from computed derivatives
+ * only):
+ *   dtD = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|),
+ *   dtA = max(dtC, dtD / 8).
+ * The crackle is what anticipates an approaching close encounter (its pair
+ * term grows as r^-5); the floor keeps the step from running away where the
+ * interpolated crackle is dominated by the forces' rounding error, which it
+ * carries multiplied by 60/h^3.  Both give eta/omega on a circular orbit.
+ * The step is kept a power of two by the same rule as the 4th-order scheme.
  * dta_out (may be NULL) receives the unquantised dtA.
  */
 int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
@@ -561,8 +596,14 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
         }
         const double an = norm3(acc_new + 3 * k), jn = norm3(jerk_new + 3 * k),
                      sN = norm3(snap_new + 3 * k);
-        const double num = sqrt(an * sN) + jn, den = sN + (an > 0.0 ? jn * jn / an : 0.0);
-        double dta = den > 0.0 ? eta * (num / den) : INFINITY;
+        const double cn = norm3(d3v);
+        const double num = sqrt(an * sN) + jn;
+        const double den_d = sN + (an > 0.0 ? jn * jn / an : 0.0);
+        const double den_c = sN + sqrt(jn * cn);
+        const double dtd = den_d > 0.0 ? eta * (num / den_d) : INFINITY;
+        double dta = den_c > 0.0 ? eta * (num / den_c) : INFINITY;
+        if (dta < dtd / 8.0)
+            dta = dtd / 8.0;
         if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
             return -5;
         if (dta_out)

@@ -160,7 +160,7 @@ def _run_kepler6(orc, e, t_end, eta, dt_max, eta_s=0.01, a=1.0):
     return st, xe, steps
 
 
-@pytest.mark.parametrize("e,tol", [(0.0, 4e-7), (0.5, 6e-7), (0.9, 5e-7)])
+@pytest.mark.parametrize("e,tol", [(0.0, 4e-7), (0.5, 1.5e-7), (0.9, 1e-6)])
 def test_kepler6_matches_closed_form(orc, e, tol):
     st, xe, steps = _run_kepler6(orc, e, 6.25, eta=0.14, dt_max=2.0 ** -3)
     err = np.abs(st.x - xe).max()
@@ -190,13 +190,16 @@ def test_error_scales_like_eta_to_the_sixth(orc):
 @pytest.mark.parametrize("a", [0.5, 2.0])
 def test_generalized_step_on_circular_orbits(orc, a):
     # circular, m1 + m2 = 1: omega = a^-1.5 and every |d^k acc/dt^k| = |acc| omega^k,
-    # so the criterion reduces to eta / omega (up to the integration error of the
-    # new acceleration, jerk and snap)
+    # so the criterion reduces to eta / omega.  The crackle comes from the step's
+    # interpolant, extrapolated to its end: off by O(omega h), and by more on the
+    # first steps, whose prediction had no crackle yet.
     eta = 0.14
     omega = a ** -1.5
     x0, v0 = kepler_state(0.5, 0.5, a, 0.0, 0.0)
     p = orc.Params6(eps=1e-10, eta=eta, eta_s=0.01, dt_max=2.0 ** -3)
     st = orc.startup6(x0, v0, np.array([0.5, 0.5]), p)
+    # startup: eta_s / omega, the largest power of two not above it
+    assert np.all(st.dt == 2.0 ** math.floor(math.log2(min(0.01 / omega, 2.0 ** -3))))
     seen = []
     for _ in range(12):
         t_next, il = orc.select(st.t, st.dt)
@@ -204,7 +207,7 @@ def test_generalized_step_on_circular_orbits(orc, a):
         acc, jerk, snap = orc.force6(xp, vp, ap, st.m, p.eps, il)
         seen.extend(orc.correct6(st, il, t_next, acc, jerk, snap, p.eta, p.dt_max, p.dt_min,
                                  want_dta=True))
-    np.testing.assert_allclose(seen, eta / omega, rtol=1e-5)
+    np.testing.assert_allclose(seen[4:], eta / omega, rtol=5e-2)
     want = 2.0 ** math.floor(math.log2(min(eta / omega, 2.0 ** -3)))
     assert np.all(st.dt == want)
 
@@ -226,11 +229,60 @@ def test_block_steps6_invariants_and_energy(orc):
     assert abs(e1 - e0) / abs(e0) < 1e-6
     k = np.log2(st.dt)
     assert np.all(k == np.round(k))
-    # at half the default eta the 6th order does at most 1.5x the pair work of the
-    # 4th order (eta = 0.02) for a several times smaller energy error (9x here)
+    # at the default eta the 6th order does at most 1.25x the pair work of the 4th
+    # order (eta = 0.02) for a smaller energy error (4x here)
     st4, _, inter4 = orc.integrate(s.x, s.v, s.m, 0.25, orc.Params(eps=1e-2))
     e4 = orc.energy(st4.x, st4.v, st4.m, 1e-2)[2]
-    st6, _, inter6 = orc.integrate6(s.x, s.v, s.m, 0.25, orc.Params6(eps=1e-2, eta=0.07))
-    e6 = orc.energy(st6.x, st6.v, st6.m, 1e-2)[2]
-    assert inter6 < 1.5 * inter4
-    assert abs(e6 - e0) < 0.2 * abs(e4 - e0)
+    assert inter < 1.25 * inter4
+    assert abs(e1 - e0) < 0.5 * abs(e4 - e0)
+
+
+# ---- close encounters and force noise -------------------------------------------------
+
+def _flyby(orc, sep, eta, dt_max, t_end=0.0625):
+    """Two light bodies (1e-6) meeting head-on at relative speed 2 with impact
+    parameter 1e-3 (eps = 1e-4), in the strong field of a unit mass at distance 1,
+    which dominates their acceleration."""
+    m = np.array([1.0, 1e-6, 1e-6])
+    x = np.array([[0.0, 0.0, 0.0], [1.0, -sep / 2, 0.0], [1.0, sep / 2, 1e-3]])
+    v = np.array([[0.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, -1.0, 0.0]])
+    p = orc.Params6(eps=1e-4, eta=eta, dt_max=dt_max)
+    st, steps, _ = orc.integrate6(x, v, m, t_end, p)
+    return st, steps
+
+
+@pytest.mark.parametrize("sep,tol", [(0.1, 1e-6), (0.01, 5e-9)])
+def test_close_encounter_in_a_strong_field_is_resolved(orc, sep, tol):
+    # reference: the same scheme converged (eta = 0.01, steps <= 2^-14); the
+    # encounter deflects the pair's velocities by about 1e-3.  At sep = 0.1 the
+    # encounter lies ahead and only the crackle announces it; at sep = 0.01 it is
+    # under way at t = 0 and the startup step must see it through the snap.
+    ref, _ = _flyby(orc, sep, 0.01, 2.0 ** -14)
+    st, steps = _flyby(orc, sep, 0.14, 2.0 ** -3)
+    err = np.abs(st.v[1:] - ref.v[1:]).max()
+    assert err < tol, (err, steps)
+
+
+def test_force_noise_does_not_shrink_a_small_shared_step(orc):
+    """Every body on the smallest startup step (far below its orbital time scale)
+    with FP32-sized errors (1e-7 of each sum's magnitude scale) added to the
+    forces: the interpolated crackle is then mostly noise, and the step must hold."""
+    from paper_1411_5234_amd import inputs
+    s = inputs.plummer(256, 5)
+    p = orc.Params6(eps=1e-3)
+    st = orc.startup6(s.x, s.v, s.m, p)
+    h = st.dt.min()
+    p.dt_max = h
+    st.dt[:] = h
+    rng = np.random.default_rng(1)
+    for _ in range(8):
+        t_next, il = orc.select(st.t, st.dt)
+        xp, vp, ap = orc.predict6(st.x, st.v, st.a, st.j, st.s, st.c, st.t, t_next)
+        acc, jerk, snap = orc.force6(xp, vp, ap, st.m, p.eps, il)
+        sa, sj = orc.force_scale(xp, vp, st.m, p.eps, il)
+        ss = orc.force6_scale(xp, vp, ap, st.m, p.eps, il)
+        acc = acc + 1e-7 * sa[:, None] * rng.normal(size=acc.shape)
+        jerk = jerk + 1e-7 * sj[:, None] * rng.normal(size=jerk.shape)
+        snap = snap + 1e-7 * ss[:, None] * rng.normal(size=snap.shape)
+        orc.correct6(st, il, t_next, acc, jerk, snap, p.eta, p.dt_max, p.dt_min)
+    assert np.all(st.dt == h)

@@ -83,13 +83,27 @@ MUTANTS = [
      lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
     ("crackle coefficient 30 instead of 60", "60.0 * k5 * h * h", "30.0 * k5 * h * h",
      lambda o: t6.test_corrector6_velocity_and_crackle_exact_for_quintic_acceleration(o, 0.5)),
-    ("criterion ratio under a square root", "eta * (num / den)", "eta * sqrt(num / den)",
+    ("criterion ratio under a square root", "double dta = den_c > 0.0 ? eta * (num / den_c) : INFINITY;",
+     "double dta = den_c > 0.0 ? eta * sqrt(num / den_c) : INFINITY;",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 0.5)),
-    ("criterion denominator |j|/|a| instead of |j|^2/|a|", "jn * jn / an", "jn / an",
+    ("criterion denominator without |s|", "const double den_c = sN + sqrt(jn * cn);",
+     "const double den_c = 0.0 + sqrt(jn * cn);",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
-    ("criterion denominator without |s|", "den = sN + (an", "den = 0.0 + (an",
+    ("criterion numerator without |j|", "const double num = sqrt(an * sN) + jn;",
+     "const double num = sqrt(an * sN);",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
-    ("criterion numerator without |j|", "num = sqrt(an * sN) + jn,", "num = sqrt(an * sN),",
+    ("criterion without the crackle", "const double den_c = sN + sqrt(jn * cn);",
+     "const double den_c = den_d;",
+     lambda o: t6.test_close_encounter_in_a_strong_field_is_resolved(o, 0.1, 1e-6)),
+    ("criterion without the floor", "        if (dta < dtd / 8.0)\n            dta = dtd / 8.0;", "",
+     lambda o: t6.test_force_noise_does_not_shrink_a_small_shared_step(o)),
+    ("6th-order startup ignores the snap",
+     "        double want = (bottom > 0.0) ? eta_s * (top / bottom) : dt_max;",
+     "        double want = (jn > 0.0) ? eta_s * an / jn : dt_max;",
+     lambda o: t6.test_close_encounter_in_a_strong_field_is_resolved(o, 0.01, 5e-9)),
+    ("6th-order startup |j|/|a| instead of |j|^2/|a|",
+     "const double bottom = sm + (an > 0.0 ? jn * jn / an : 0.0);",
+     "const double bottom = sm + (an > 0.0 ? jn / an : 0.0);",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
 ]
 
