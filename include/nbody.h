@@ -267,7 +267,8 @@ nb_status nb_force6_active_plan(nb_ctx *ctx, const nb_system *sys, const nb_herm
 /* Startup of the 6th-order scheme (t = 0, every body active): copy acc, jerk
  * and snap (3*n SoA each, from nb_force6_active over all bodies with the
  * accelerations of a first nb_force_active pass as predicted accelerations)
- * into the state, set the crackle to 0, t = 0 and dt as nb_init_steps.
+ * into the state, set the crackle to 0, t = 0 and dt = the largest power of
+ * two not above min(eta_s (sqrt(|a||s|) + |j|) / (|s| + |j|^2/|a|), dt_max).
  * Errors latched as nb_init_steps. */
 nb_status nb_init_steps6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
                          const double *acc, const double *jerk, const double *snap,
@@ -279,14 +280,15 @@ nb_status nb_init_steps6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h
  *   x = x + h/2 (v_old + v) - h^2/10 (a1 - a0) + h^3/120 (j0 + j1),
  *   crackle = -3 (20 (a0 - a1) + h^2 (s0 - 3 s1) + h (8 j0 + 12 j1)) / h^3
  * (the third derivative at t_next of the degree-5 interpolant of (a, j, s) at
- * both ends), a, j, s = a1, j1, s1, t = t_next, and the new step from the
- * directly computed acceleration, jerk and snap
- *   dtA = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|)
- * (eta/omega on a circular orbit), kept a power of two by the rule of
- * nb_correct.  (Criteria that use the crackle or higher derivatives of the
- * interpolant amplify the rounding error of FP32 pair arithmetic by h^-3 to
- * h^-5, which at small steps drives them to dt_min.)  Errors latched as
- * nb_correct. */
+ * both ends), a, j, s = a1, j1, s1, t = t_next, and the new step
+ *   dtC = eta (sqrt(|a1||s1|) + |j1|) / (sqrt(|j1||crackle|) + |s1|),
+ *   dtD = eta (sqrt(|a1||s1|) + |j1|) / (|s1| + |j1|^2 / |a1|),
+ *   dtA = max(dtC, dtD / 8)
+ * (both eta/omega on a circular orbit), kept a power of two by the rule of
+ * nb_correct.  The crackle announces approaching close encounters; the floor
+ * dtD/8 (computed derivatives only) keeps FP32 rounding noise in the
+ * interpolated crackle, which grows as h^-3, from driving small steps to dt_min.
+ * Errors latched as nb_correct. */
 nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
                       const int32_t *i_idx, int32_t m, const double *acc, const double *jerk,
                       const double *snap, double t_next, double eta, double dt_max,

@@ -59,10 +59,12 @@ __device__ __forceinline__ double len3(const double (&u)[3])
 // Corrector of the active bodies.  The two-point quadratures use (a, j, s) at
 // both ends of the step; the crackle at the step's end is that of the degree-5
 // polynomial matching (a, j, s) at both ends, written out in closed form.  New
-// step from the directly computed acceleration, jerk and snap only,
-// eta (sqrt(|a||s|) + |j|) / (|s| + |j|^2/|a|), kept a power of two as in the
-// 4th-order corrector: derivatives taken from the interpolant carry the forces'
-// rounding error multiplied by h^-3 to h^-5.
+// step: the lowest generalized Aarseth form with that crackle,
+// eta (sqrt(|a||s|) + |j|) / (sqrt(|j||c|) + |s|), which anticipates approaching
+// encounters, floored at one eighth of the form with |j|^2/|a| in place of the
+// crackle term (computed derivatives only), so that rounding noise in the
+// interpolated crackle cannot drive the step down; kept a power of two as in
+// the 4th-order corrector.
 __global__ __launch_bounds__(WG) void correct6_kernel(const Item *items, const int64_t *starts,
                                                       int n_items, double eta, double dt_max,
                                                       double dt_min)
@@ -109,8 +111,12 @@ __global__ __launch_bounds__(WG) void correct6_kernel(const Item *items, const i
     }
     const double an = len3(a1v), jn = len3(j1v), sN = len3(s1v);
     const double num = sqrt(an * sN) + jn;
-    const double den = sN + (an > 0.0 ? jn * jn / an : 0.0);
-    const double dta = den > 0.0 ? eta * (num / den) : INFINITY;
+    const double den_d = sN + (an > 0.0 ? jn * jn / an : 0.0);
+    const double den_c = sN + sqrt(jn * len3(c1v));
+    const double dt_d = den_d > 0.0 ? eta * (num / den_d) : INFINITY;
+    double dta = den_c > 0.0 ? eta * (num / den_c) : INFINITY;
+    if (dta < 0.125 * dt_d)
+        dta = 0.125 * dt_d;
     int err = 0;
     if (isnan(dta) || !isfinite(an) || !isfinite(jn) || !isfinite(sN))
         err |= NBK_ENAN;
@@ -141,8 +147,9 @@ hipError_t launch_correct6(const Table &t, double eta, double dt_max, double dt_
 }
 
 // Startup: store acceleration, jerk and snap, zero the crackle, and take the
-// startup step of the 4th-order scheme (largest power of two not above
-// min(eta_s |a| / |j|, dt_max)).
+// largest power of two not above min(eta_s (sqrt(|a||s|) + |j|) / (|s| +
+// |j|^2/|a|), dt_max): no crackle exists yet, and the snap shows a neighbour
+// that is already close.
 __global__ __launch_bounds__(WG) void init_steps6_kernel(const Item *items, const int64_t *starts,
                                                          int n_items, double eta_s, double dt_max,
                                                          double dt_min)
@@ -172,7 +179,8 @@ __global__ __launch_bounds__(WG) void init_steps6_kernel(const Item *items, cons
     int err = 0;
     if (!isfinite(an) || !isfinite(jn) || !isfinite(sN))
         err |= NBK_ENAN;
-    double want = jn > 0.0 ? eta_s * an / jn : dt_max;
+    const double top = sqrt(an * sN) + jn, bottom = sN + (an > 0.0 ? jn * jn / an : 0.0);
+    double want = bottom > 0.0 ? eta_s * (top / bottom) : dt_max;
     if (want > dt_max)
         want = dt_max;
     double step = dt_max;
