@@ -72,6 +72,13 @@ def lib():
         L.orc_init_dt6.restype = C.c_int
         L.orc_init_dt6.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                    _dp]
+        L.orc_tidal.restype = C.c_int
+        L.orc_tidal.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, C.c_int64, C.c_int64,
+                                C.c_double, _dp]
+        L.orc_kepler_drift.restype = C.c_int
+        L.orc_kepler_drift.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp, _dp]
+        L.orc_group_advance.restype = C.c_int
+        L.orc_group_advance.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_int64, _dp, _dp]
         L.orc_predict6.restype = None
         L.orc_predict6.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, C.c_double,
                                    _dp, _dp, _dp]
@@ -404,3 +411,146 @@ def integrate6(x, v, m, t_end, p: Params6, log=None):
         if np.all(st.t == t_end):
             break
     return st, steps, inter
+
+
+# ---------------------------------------------------------------------------
+# Tight groups (the HiGPUs-R scheme of Sec. 3): bound pairs carried as one body at
+# their centre of mass, relative orbit advanced by Kepler drifts and tidal kicks
+# ---------------------------------------------------------------------------
+
+def tidal(x, m, eps, ilist=None, j0=0, j1=None):
+    """Tidal tensor d a / d x (n_i, 3, 3) of the softened field of j in [j0, j1) at the
+    listed bodies (self term excluded)."""
+    x, m = _c(x), _c(m)
+    n = m.shape[0]
+    if ilist is None:
+        ilist = np.arange(n, dtype=np.int64)
+    ilist = _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    T = np.zeros(9 * ilist.size)
+    _check(lib().orc_tidal(n, x, m, ilist.size, ilist, int(j0), j1, float(eps), T))
+    return T.reshape(-1, 3, 3)
+
+
+def kepler_drift(M, r, v, dt):
+    """Exact two-body motion of the relative coordinate (bound pairs only)."""
+    r1, v1 = np.empty(3), np.empty(3)
+    _check(lib().orc_kepler_drift(float(M), _c(r), _c(v), float(dt), r1, v1))
+    return r1, v1
+
+
+def group_advance(M, r, v, H, nsub, T0, T1):
+    """Relative orbit over H: nsub kick-drift-kick substeps, T linear from T0 to T1."""
+    r, v = _c(r).copy(), _c(v).copy()
+    _check(lib().orc_group_advance(float(M), r, v, float(H), int(nsub), _c(T0).reshape(9),
+                                   _c(T1).reshape(9)))
+    return r, v
+
+
+def orbit_period(M, r, v):
+    inv_a = 2.0 / np.linalg.norm(r) - np.dot(v, v) / M
+    if inv_a <= 0.0:
+        raise OracleError("pair is not bound")
+    return 2.0 * np.pi * np.sqrt(inv_a ** -3 / M)
+
+
+def substeps(M, r, v, H, per_period=32, cap=1 << 20):
+    """Substeps for a relative orbit over H: per_period per orbital period."""
+    return int(min(cap, max(1, np.ceil(per_period * H / orbit_period(M, r, v)))))
+
+
+@dataclass
+class Grouped:
+    """A block-step state with pairs carried as centre-of-mass bodies.
+
+    st: the 4th-order state of the reduced system (singles first, then one body per
+    pair); pairs: (i, j) original indices; rel: relative (r, v) of each pair at
+    tpair; T: tidal tensor at each pair's centre of mass at tpair."""
+
+    st: State
+    singles: np.ndarray
+    pairs: np.ndarray
+    M: np.ndarray
+    r: np.ndarray
+    w: np.ndarray
+    T: np.ndarray
+    tpair: np.ndarray
+
+
+def group_startup(x, v, m, pairs, p: Params) -> Grouped:
+    x, v, m = _c(x), _c(v), _c(m)
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    n = m.shape[0]
+    in_pair = np.zeros(n, dtype=bool)
+    in_pair[pairs.ravel()] = True
+    singles = np.nonzero(~in_pair)[0]
+    i, j = pairs[:, 0], pairs[:, 1]
+    M = m[i] + m[j]
+    xc = (m[i, None] * x[i] + m[j, None] * x[j]) / M[:, None]
+    vc = (m[i, None] * v[i] + m[j, None] * v[j]) / M[:, None]
+    xr = np.concatenate([x[singles], xc])
+    vr = np.concatenate([v[singles], vc])
+    mr = np.concatenate([m[singles], M])
+    st = startup(xr, vr, mr, p)
+    cm = singles.size + np.arange(pairs.shape[0])
+    T = tidal(st.x, st.m, p.eps, cm)
+    return Grouped(st, singles, pairs, M, x[j] - x[i], v[j] - v[i], T, np.zeros(pairs.shape[0]))
+
+
+def group_block_step(g: Grouped, p: Params, per_period=32):
+    """One block step of the reduced system; every pair whose centre of mass was
+    in the active block then advances its relative orbit to the block time, with
+    the tidal tensor interpolated between its value at the pair's previous time
+    and its value at the block time (from the same predicted j-set as the force)."""
+    rec = block_step(g.st, p, keep=True)
+    ncm = g.singles.size
+    act = rec.ilist[rec.ilist >= ncm]
+    if act.size:
+        Tn = tidal(rec.xp, g.st.m, p.eps, act)
+        for q, b in enumerate(act - ncm):
+            H = rec.t_next - g.tpair[b]
+            ns = substeps(g.M[b], g.r[b], g.w[b], H, per_period)
+            g.r[b], g.w[b] = group_advance(g.M[b], g.r[b], g.w[b], H, ns, g.T[b], Tn[q])
+            g.T[b] = Tn[q]
+            g.tpair[b] = rec.t_next
+    return rec
+
+
+def group_energy(g: Grouped, m, eps):
+    """Energy of the grouped system: the reduced system's (pairs as point masses,
+    softened), plus each pair's two-body energy (unsoftened, as its orbit is
+    advanced) and its tidal energy -mu r.T.r / 2 in the field of the rest."""
+    m = _c(m)
+    er = energy(g.st.x, g.st.v, g.st.m, eps)[2]
+    i, j = g.pairs[:, 0], g.pairs[:, 1]
+    mu = m[i] * m[j] / g.M
+    rr = np.linalg.norm(g.r, axis=1)
+    tid = np.einsum("ka,kab,kb->k", g.r, g.T, g.r)
+    return er + float((mu * (0.5 * (g.w ** 2).sum(1) - g.M / rr - 0.5 * tid)).sum())
+
+
+def group_integrate(x, v, m, pairs, t_end, p: Params, per_period=32, log=None):
+    """Block-step integration with the pairs grouped; returns (x, v) of all bodies
+    at t_end, the number of block steps and the grouped state."""
+    m = _c(m)
+    g = group_startup(x, v, m, pairs, p)
+    steps = 0
+    while float(np.min(g.st.t + g.st.dt)) <= t_end:
+        rec = group_block_step(g, p, per_period)
+        steps += 1
+        if log is not None:
+            log.append((rec.t_next, rec.ilist))
+        if np.all(g.st.t == t_end):
+            break
+    n = m.shape[0]
+    xo, vo = np.empty((n, 3)), np.empty((n, 3))
+    ns = g.singles.size
+    xo[g.singles], vo[g.singles] = g.st.x[:ns], g.st.v[:ns]
+    i, j = g.pairs[:, 0], g.pairs[:, 1]
+    fi = (m[j] / g.M)[:, None]
+    fj = (m[i] / g.M)[:, None]
+    xo[i] = g.st.x[ns:] - fi * g.r
+    xo[j] = g.st.x[ns:] + fj * g.r
+    vo[i] = g.st.v[ns:] - fi * g.w
+    vo[j] = g.st.v[ns:] + fj * g.w
+    return xo, vo, steps, g

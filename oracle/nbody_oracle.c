@@ -624,3 +624,155 @@ int orc_correct6(int64_t n, int64_t mcount, const int64_t *ilist, double t_next,
     }
     return status;
 }
+
+/* =========================================================================
+ * Tight groups (the HiGPUs-R scheme of Sec. 3): a bound pair is carried in the
+ * N-body system as one body at its centre of mass, and its relative orbit is
+ * advanced separately: exact two-body (Kepler) motion plus the tidal field of
+ * the rest of the system, linearised about the centre of mass.
+ * ========================================================================= */
+
+/* ---- tidal tensor ------------------------------------------------------------------
+ * For each listed body i: T_ab = d a_a / d x_b of the softened field of the
+ * bodies j in [j0, j1), j != i, at x_i:
+ *   T_ab = sum_j m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),  r = x_j - x_i,
+ * s = |r|^2 + eps^2; row-major 3x3 per body (T[9k + 3a + b]).
+ */
+int orc_tidal(int64_t n, const double *x, const double *m, int64_t ni, const int64_t *ilist,
+              int64_t j0, int64_t j1, double eps, double *T)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        csum acc[9];
+        for (int q = 0; q < 9; q++) {
+            acc[q].s = 0.0;
+            acc[q].c = 0.0;
+        }
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double d[3];
+            for (int c = 0; c < 3; c++)
+                d[c] = x[3 * j + c] - x[3 * i + c];
+            const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+            const double s32 = s * sqrt(s);
+            const double s52 = s32 * s;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++)
+                    cs_add(&acc[3 * a + b],
+                           m[j] * (3.0 * d[a] * d[b] / s52 - (a == b ? 1.0 : 0.0) / s32));
+        }
+        for (int q = 0; q < 9; q++)
+            T[9 * k + q] = cs_val(&acc[q]);
+    }
+    return 0;
+}
+
+/* ---- Kepler drift -----------------------------------------------------------------
+ * Exact motion of the relative coordinate of an isolated bound pair of total
+ * mass M over a time dt (r'' = -M r / |r|^3), by the f and g functions of the
+ * eccentric-anomaly change dE, which solves
+ *   n dt = dE - (1 - r0/a) sin dE + (sigma0 / sqrt(a)) (1 - cos dE),
+ * with 1/a = 2/r0 - v0^2/M, n = sqrt(M/a^3), sigma0 = r0.v0 / sqrt(M):
+ *   f = 1 - (a/r0)(1 - cos dE),           g = dt - (dE - sin dE)/n,
+ *   r = a + (r0 - a) cos dE + sigma0 sqrt(a) sin dE,
+ *   fd = -sqrt(M a) sin dE / (r r0),      gd = 1 - (a/r)(1 - cos dE),
+ *   r1 = f r0 + g v0,  v1 = fd r0 + gd v0.
+ * Returns 0, or -1 for an unbound or degenerate pair.
+ */
+int orc_kepler_drift(double M, const double *r0, const double *v0, double dt, double *r1,
+                     double *v1)
+{
+    const double rr = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+    const double vv = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    if (!(M > 0.0) || !(rr > 0.0))
+        return -1;
+    const double inv_a = 2.0 / rr - vv / M;
+    if (!(inv_a > 0.0))
+        return -1;
+    const double a = 1.0 / inv_a;
+    const double nmean = sqrt(M * inv_a * inv_a * inv_a);
+    const double sig = (r0[0] * v0[0] + r0[1] * v0[1] + r0[2] * v0[2]) / sqrt(M);
+    const double ce = 1.0 - rr / a, se = sig / sqrt(a);   /* e cos E0, e sin E0 */
+    /* reduce n dt by whole periods, solve for the remainder */
+    const double twopi = 6.283185307179586476925286766559;
+    const double phase = nmean * dt;
+    const double turns = floor(phase / twopi);
+    const double Mrem = phase - turns * twopi;
+    /* F(x) = x - ce sin x + se (1 - cos x) - Mrem increases monotonically
+     * (F' = 1 - e cos(E0 + x) >= 1 - e > 0), F(0) = -Mrem <= 0 < F(2 pi): Newton
+     * steps kept inside a shrinking bracket, bisection when a step leaves it */
+    double lo = 0.0, hi = twopi, x = Mrem;                /* x = dE - 2 pi turns */
+    for (int it = 0; it < 200; it++) {
+        const double F = x - ce * sin(x) + se * (1.0 - cos(x)) - Mrem;
+        if (F > 0.0)
+            hi = x;
+        else
+            lo = x;
+        const double Fp = 1.0 - ce * cos(x) + se * sin(x);
+        double xn = x - F / Fp;
+        if (!(xn > lo && xn < hi))
+            xn = 0.5 * (lo + hi);
+        const double dx = xn - x;
+        x = xn;
+        if (fabs(dx) <= 4e-16 * (1.0 + fabs(x)) || hi - lo <= 4e-16 * (1.0 + hi))
+            break;
+    }
+    const double cx = cos(x), sx = sin(x);
+    const double f = 1.0 - (a / rr) * (1.0 - cx);
+    const double g = (Mrem - (x - sx)) / nmean;
+    const double r = a + (rr - a) * cx + sig * sqrt(a) * sx;
+    const double fd = -sqrt(M * a) * sx / (r * rr);
+    const double gd = 1.0 - (a / r) * (1.0 - cx);
+    for (int c = 0; c < 3; c++) {
+        r1[c] = f * r0[c] + g * v0[c];
+        v1[c] = fd * r0[c] + gd * v0[c];
+    }
+    return 0;
+}
+
+/* ---- relative orbit under a tidal field ---------------------------------------------
+ * Advance (r, v) of a pair of mass M over [0, H] in nsub equal substeps of
+ * h = H / nsub, each kick (h/2) - drift h - kick (h/2): the drift is the exact
+ * Kepler motion, a kick adds T(t) r times its length, and T(t) is interpolated
+ * linearly between T0 (at 0) and T1 (at H).  Second order in h for the tidal
+ * part, exact for T = 0.  Returns 0 or the drift's error.
+ */
+int orc_group_advance(double M, double *r, double *v, double H, int64_t nsub, const double *T0,
+                      const double *T1)
+{
+    if (nsub < 1)
+        return -1;
+    const double h = H / (double)nsub;
+    for (int64_t q = 0; q < nsub; q++) {
+        const double wa = (double)q / (double)nsub, wb = (double)(q + 1) / (double)nsub;
+        for (int half = 0; half < 2; half++) {
+            const double w = half == 0 ? wa : wb;
+            if (half == 1) {
+                double r1[3], v1[3];
+                const int rc = orc_kepler_drift(M, r, v, h, r1, v1);
+                if (rc)
+                    return rc;
+                for (int c = 0; c < 3; c++) {
+                    r[c] = r1[c];
+                    v[c] = v1[c];
+                }
+            }
+            for (int a = 0; a < 3; a++) {
+                double tr = 0.0;
+                for (int b = 0; b < 3; b++)
+                    tr += ((1.0 - w) * T0[3 * a + b] + w * T1[3 * a + b]) * r[b];
+                v[a] += 0.5 * h * tr;
+            }
+        }
+    }
+    return 0;
+}

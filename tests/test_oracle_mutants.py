@@ -16,6 +16,7 @@ import test_oracle_energy as te
 import test_oracle_force as tf
 import test_oracle_hermite as th
 import test_oracle_hermite6 as t6
+import test_oracle_groups as tg
 
 SRC = os.path.join(os.path.dirname(real_oracle.__file__), "nbody_oracle.c")
 
@@ -105,6 +106,22 @@ MUTANTS = [
      "const double bottom = sm + (an > 0.0 ? jn * jn / an : 0.0);",
      "const double bottom = sm + (an > 0.0 ? jn / an : 0.0);",
      lambda o: t6.test_generalized_step_on_circular_orbits(o, 2.0)),
+    # tight groups
+    ("tidal tensor without the isotropic term", "- (a == b ? 1.0 : 0.0) / s32", "",
+     lambda o: tg.test_tidal_is_minus_hessian_of_potential(o, 7)),
+    ("tidal tensor factor 2 instead of 3", "m[j] * (3.0 * d[a] * d[b] / s52", "m[j] * (2.0 * d[a] * d[b] / s52",
+     lambda o: tg.test_tidal_is_minus_hessian_of_potential(o, 7)),
+    ("Kepler drift g without the time", "const double g = (Mrem - (x - sx)) / nmean;",
+     "const double g = (0.0 - (x - sx)) / nmean;",
+     lambda o: tg.test_kepler_drift_matches_closed_form(o, 0.3, 1.7)),
+    ("Kepler drift sign of sigma term", "+ se * (1.0 - cos(x)) - Mrem;", "- se * (1.0 - cos(x)) - Mrem;",
+     lambda o: tg.test_kepler_drift_matches_closed_form(o, 0.3, 1.7)),
+    ("Kepler solver without its bracket", "        if (!(xn > lo && xn < hi))\n            xn = 0.5 * (lo + hi);\n", "",
+     lambda o: tg.test_kepler_drift_invariants_at_high_eccentricity(o)),
+    ("tidal kick of the wrong sign", "v[a] += 0.5 * h * tr;", "v[a] -= 0.5 * h * tr;",
+     lambda o: tg.test_group_advance_conserves_the_jacobi_integral_of_a_constant_tide(o)),
+    ("tidal kicks at the substep start only", "const double w = half == 0 ? wa : wb;", "const double w = wa;",
+     lambda o: tg.test_group_advance_is_second_order(o)),
 ]
 
 
