@@ -67,12 +67,15 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
     ap.add_argument("--no-energy", action="store_true")
-    ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve", "copy"], default="step",
+    ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve", "copy", "groups"],
+                    default="step",
                     help="step: the headline (default); sweep: active-block sizes 2^6..2^16 at "
                          "N=65536 (Salpeter), FP64 vs mixed, planned j-split vs none; integrate: "
                          "block-step integration of the N=2^20 Plummer sphere to t_end with energy "
                          "drift; serve: Poisson request stream through the continuous-batching server; "
-                         "copy: a plain 1 GiB device copy (calibrates the HBM traffic counters)")
+                         "copy: a plain 1 GiB device copy (calibrates the HBM traffic counters); "
+                         "groups: a cluster with hard binaries integrated directly and with the "
+                         "pairs carried as centre-of-mass bodies (CPU pair work overlapped or not)")
     ap.add_argument("--t-end", type=float, default=0.125)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
@@ -85,7 +88,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.mode == "sweep":
@@ -96,6 +99,8 @@ def main():
         return mode_serve(args)
     if args.mode == "copy":
         return mode_copy(args)
+    if args.mode == "groups":
+        return mode_groups(args)
 
     return mode_step(args)
 
@@ -192,6 +197,7 @@ def mode_step(args):
     peak = PEAK_FP32_TFLOPS if args.precision != "fp64" else PEAK_FP64_TFLOPS
 
     extra = {}
+    alt_sample = {}
     if ms[-1] == n:
         # the other precisions on the same predicted state and launch shape: one
         # warm-up and two HIP-event-timed force launches each
@@ -213,6 +219,10 @@ def mode_step(args):
             alt[prec] = {"kernel_ms": best * 1e3, "interactions_per_s": n * n / best,
                          "tflops": flops * n * n / best / 1e12,
                          "plan": list(_lib.force_plan(n, n, prec))}
+            if args.cpu_sample > 0:
+                k = min(args.cpu_sample, n)
+                alt_sample[prec] = (it.acc.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy(),
+                                    it.jerk.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy())
         extra["other_precisions_same_state"] = alt
         # leave the results of the benchmarked precision in place for the CPU check
         force(n, args.precision)
@@ -231,7 +241,7 @@ def mode_step(args):
         tc = time.perf_counter()
         if h6:
             ap = it.h6.state_numpy()["ap"]
-            oa, oj, _ = oracle.force6(st["xp"], st["vp"], ap, st["m"], args.eps, il)
+            oa, oj, osn = oracle.force6(st["xp"], st["vp"], ap, st["m"], args.eps, il)
         else:
             oa, oj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, il)
         tcpu = time.perf_counter() - tc
@@ -249,6 +259,19 @@ def mode_step(args):
                 "bodies": k, "acc_rel_max": float(ea.max()),
                 "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
                 "jerk_rel_max": float(ej.max()), "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
+            if h6:
+                gs = it.snap.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
+                ss = oracle.force6_scale(st["xp"], st["vp"], ap, st["m"], args.eps, il)
+                es = np.linalg.norm(gs - osn, axis=1) / ss
+                extra["error_vs_oracle_sample"]["snap_over_scale_max"] = float(es.max())
+            # the other precisions' results on the same sample
+            for prec, (pa, pj) in alt_sample.items():
+                ea = np.linalg.norm(pa - oa, axis=1) / np.linalg.norm(oa, axis=1)
+                ej = np.linalg.norm(pj - oj, axis=1) / np.linalg.norm(oj, axis=1)
+                extra["other_precisions_same_state"][prec]["error_vs_oracle_sample"] = {
+                    "acc_rel_max": float(ea.max()), "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
+                    "jerk_rel_max": float(ej.max()),
+                    "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
 
     kname = "force%s_%s_kernel" % ("6" if h6 else "",
                                    "fp64" if args.precision == "fp64" else "mixed")
@@ -353,17 +376,23 @@ def mode_sweep(args):
 
 
 def mode_integrate(args):
-    """Block-step Hermite-4 integration of the N=2^20 Plummer sphere to t_end."""
+    """Block-step Hermite integration (order 4, or 6 with --order 6) of the N=2^20
+    Plummer sphere to t_end."""
     import torch
 
     from paper_1411_5234_amd import inputs
-    from paper_1411_5234_amd.nbody import Context, Integrator, Params, System
+    from paper_1411_5234_amd.nbody import (Context, Integrator, Integrator6, Params, Params6,
+                                           System)
     n = args.n
     snap = inputs.plummer(n, args.seed)
     ctx = Context(0)
     system = System.from_arrays(snap.x, snap.v, snap.m)
-    p = Params(eps=args.eps, precision=args.precision)
-    it = Integrator(ctx, system, p)
+    if args.order == 6:
+        p = Params6(eps=args.eps, precision=args.precision)
+        it = Integrator6(ctx, system, p)
+    else:
+        p = Params(eps=args.eps, precision=args.precision)
+        it = Integrator(ctx, system, p)
     E0 = ctx.energy(system, args.eps)[2]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -389,9 +418,12 @@ def mode_integrate(args):
     ctx.close()
     out = {"metric": "pair-interactions/s over a block-step integration", "mode": "integrate",
            "value": it.interactions / wall, "unit": "pair-interactions/s",
-           "config": {"workload": "plummer_n%d_eps%g_%s_to_t%g" % (n, args.eps, args.precision, args.t_end),
-                      "n": n, "eps": args.eps, "precision": args.precision, "t_end": args.t_end,
+           "config": {"workload": "plummer_n%d_eps%g_%s_hermite%d_to_t%g"
+                                  % (n, args.eps, args.precision, args.order, args.t_end),
+                      "n": n, "eps": args.eps, "precision": args.precision, "order": args.order,
+                      "t_end": args.t_end,
                       "eta": p.eta, "eta_s": p.eta_s, "dt_max": p.dt_max},
+           "flops_per_interaction": FLOPS_PER_INTERACTION6 if args.order == 6 else FLOPS_PER_INTERACTION,
            "block_steps": it.steps, "interactions": it.interactions, "wall_s": wall,
            "energy0": E0, "energy1": E1, "energy_drift": abs(E1 - E0) / abs(E0)}
     print(json.dumps(out), flush=True)
@@ -481,6 +513,103 @@ def mode_serve(args):
     ctx.close()
     out["value"] = poisson["solves_per_s"]
     out["unit"] = "solves/s"
+    print(json.dumps(out), flush=True)
+
+
+def mode_groups(args):
+    """Kroupa cluster of --n bodies (default 16384 here) with 10% of them in hard
+    binaries (a log-uniform in [1e-4, 1e-3], thermal e), eps = 1e-5, to --t-end
+    (default 1/64 here): integrated directly, then with the pairs carried as
+    centre-of-mass bodies whose relative orbits advance on CPU threads.  Then, to
+    8 x t_end, the grouped run with the CPU pair work overlapped with the GPU
+    block steps against the same work run between them (best of two each)."""
+    import numpy as np
+
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.groups import GroupedIntegrator
+    from paper_1411_5234_amd.nbody import Context, Integrator, Params, System
+    n = args.n if args.n != (1 << 20) else 16384
+    t_end = args.t_end if args.t_end != 0.125 else 1.0 / 64
+    eps = 1e-5
+    s = inputs.with_binaries(n, 6, frac_members=0.1, a_lo=1e-4, a_hi=1e-3, imf="kroupa")
+    npairs = s.meta["n_pairs"]
+    pairs = [(2 * k, 2 * k + 1) for k in range(npairs)]
+    ctx = Context(0)
+    out = {"metric": "block steps, wall time and energy error with and without grouped pairs",
+           "mode": "groups",
+           "config": {"workload": "kroupa_binaries_n%d_eps%g_to_t%g" % (n, eps, t_end), "n": n,
+                      "pairs": npairs, "a_range": [1e-4, 1e-3], "eps": eps, "t_end": t_end,
+                      "precision": args.precision}}
+    last = [time.perf_counter()]
+
+    def progress(tag, t, steps):
+        now = time.perf_counter()
+        if now - last[0] > 10:
+            last[0] = now
+            print("  %s: t=%.6f steps=%d" % (tag, t, steps), file=sys.stderr, flush=True)
+
+    # direct
+    system = System.from_arrays(s.x, s.v, s.m)
+    it = Integrator(ctx, system, Params(eps=eps, precision=args.precision))
+    E0 = ctx.energy(system, eps)[2]
+    t0 = time.perf_counter()
+    it.startup()
+    while True:
+        t_next, m = ctx.select_active(system, it.i_idx)
+        if t_next > t_end:
+            break
+        it._advance(t_next, m)
+        progress("direct", t_next, it.steps)
+    ctx.sync()
+    wall = time.perf_counter() - t0
+    E1 = ctx.energy(system, eps)[2]
+    out["direct"] = {"block_steps": it.steps, "interactions": it.interactions, "wall_s": wall,
+                     "energy_error": abs(E1 - E0) / abs(E0)}
+    print("direct: %s" % out["direct"], file=sys.stderr, flush=True)
+    del it, system
+    def grouped(overlap, t_stop, per_period=32):
+        gi = GroupedIntegrator(ctx, s.x, s.v, s.m, pairs, Params(eps=eps, precision=args.precision),
+                               overlap=overlap, per_period=per_period)
+        t0 = time.perf_counter()
+        gi.startup()
+        e0 = gi.energy()
+        steps, inter = gi.run(t_stop)
+        wall = time.perf_counter() - t0
+        e1 = gi.energy()
+        res = {"block_steps": steps, "interactions": inter, "wall_s": wall,
+               "cpu_pair_advances": gi.cpu_pairs_advanced, "per_period": per_period,
+               "scheme_energy_error": abs(e1 - e0) / abs(e0)}
+        if overlap:
+            res["host_blocked_on_pairs_s"] = gi.wait_seconds
+        else:
+            res["pair_advance_cpu_s"] = gi.cpu_seconds
+        del gi
+        return res
+
+    grouped(True, t_end / 8)                       # warm-up (first launches, thread start)
+    out["grouped"] = grouped(True, t_end)
+    print("grouped: %s" % out["grouped"], file=sys.stderr, flush=True)
+    # the CPU pair work overlapped with the GPU block steps, or run between them: a
+    # longer run, best of two of each, alternating; with 32 substeps per orbital
+    # period (the default) and with 256 (eight times the CPU work)
+    t_long = 8 * t_end
+    for per_period in (32, 256):
+        runs = {True: [], False: []}
+        for overlap in (True, False, True, False):
+            runs[overlap].append(grouped(overlap, t_long, per_period))
+        for overlap, key in ((True, "overlapped"), (False, "serialized")):
+            best = min(runs[overlap], key=lambda r: r["wall_s"])
+            best["t_end"] = t_long
+            out["grouped_%s_%d" % (key, per_period)] = best
+            print("%s %d: %s" % (key, per_period, best), file=sys.stderr, flush=True)
+    ctx.close()
+    out["speedup_grouped_vs_direct"] = out["direct"]["wall_s"] / out["grouped"]["wall_s"]
+    for per_period in (32, 256):
+        ser, ovl = out["grouped_serialized_%d" % per_period], out["grouped_overlapped_%d" % per_period]
+        out["overlap_%d" % per_period] = {
+            "wall_saved_s": ser["wall_s"] - ovl["wall_s"],
+            "pair_advance_cpu_s": ser["pair_advance_cpu_s"],
+            "hidden_fraction": 1.0 - ovl["host_blocked_on_pairs_s"] / max(ser["pair_advance_cpu_s"], 1e-12)}
     print(json.dumps(out), flush=True)
 
 

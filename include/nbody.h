@@ -42,7 +42,8 @@ typedef enum {
     NB_EDEVICE = -3,  /* a HIP runtime call failed                             */
     NB_ERANGE = -4,   /* a new time step fell below dt_min                      */
     NB_ENAN = -5,     /* non-finite acceleration, jerk or time step            */
-    NB_EINDEX = -6    /* an active index was outside [0, n)                     */
+    NB_EINDEX = -6,   /* an active index was outside [0, n)                     */
+    NB_EUNBOUND = -7  /* a pair handed to the two-body drift is not bound        */
 } nb_status;
 
 typedef enum {
@@ -293,6 +294,53 @@ nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
                       const int32_t *i_idx, int32_t m, const double *acc, const double *jerk,
                       const double *snap, double t_next, double eta, double dt_max,
                       double dt_min);
+
+/* ---- tight pairs (the HiGPUs-R scheme of Sec. 3) -------------------------------------
+ * Tight groups are taken out of the N-body integration and advanced apart from
+ * it, on CPU threads, while the GPU kernels run.  Here a group is a bound pair:
+ * the block-step system carries it as one body of mass M = m1 + m2 at its
+ * centre of mass, and its relative coordinate r = x2 - x1, w = v2 - v1 is
+ * advanced over each step of that body by exact two-body drifts and kicks from
+ * the tidal tensor of the rest of the system (linear about the centre of mass).
+ * The two-body motion is unsoftened. */
+
+/* Tidal tensor T_ab = d a_a / d x_b of the softened field of the predicted bodies
+ * j in [j0, j1), j != i, at the predicted position of each listed body i
+ * (i = i_idx[k], or k when i_idx is NULL):
+ *   T_ab = sum_j m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),  r = xp_j - xp_i,
+ * s = |r|^2 + eps^2.  FP64.  tensor: device, 9*m doubles, T_ab of body k at
+ * tensor[(3a+b)*m + k].  One workgroup per listed body; bitwise reproducible.
+ * Returns NB_EINVAL for eps < 0, bad ranges or m < 0; m == 0 is a no-op. */
+nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                          int32_t m, int64_t j0, int64_t j1, double eps, double *tensor);
+
+/* Host.  Two-body motion of a bound relative coordinate (r0, v0) of total mass M
+ * over dt (any sign, any length): r'' = -M r / |r|^3.  All pointers are HOST
+ * arrays of 3 doubles.  Returns NB_OK, NB_EINVAL, or NB_EUNBOUND when
+ * |v0|^2/2 - M/|r0| >= 0. */
+nb_status nb_kepler_drift(double M, const double *r0, const double *v0, double dt,
+                          double *r1, double *v1);
+
+/* Host.  Advance n pairs: pair k (mass M[k], relative r[3k..], v[3k..], updated in
+ * place) over H[k] >= 0 in nsub = min(max_sub, max(1, ceil(per_period H / P)))
+ * equal substeps (P its current orbital period), each kick (h/2) - drift h -
+ * kick (h/2), a kick adding T(t) r times its length with T linear in t from
+ * T0[9k..] to T1[9k..] (row-major 3x3).  OpenMP over pairs.  status (may be
+ * NULL): per pair NB_OK or NB_EUNBOUND.  All arrays are HOST memory.  Returns
+ * NB_OK, NB_EINVAL or NB_EUNBOUND if any pair failed. */
+nb_status nb_groups_advance(int32_t n, const double *M, double *r, double *v, const double *H,
+                            const double *T0, const double *T1, int32_t per_period,
+                            int64_t max_sub, int32_t *status);
+
+/* The same on a host thread of the context: returns at once, so that the caller
+ * can enqueue GPU work meanwhile; the arrays must stay valid and untouched until
+ * nb_groups_wait, which joins the thread and returns its result.  One advance at
+ * a time per context (NB_EINVAL otherwise).  nb_ctx_destroy waits for it. */
+nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const double *M, double *r,
+                                  double *v, const double *H, const double *T0,
+                                  const double *T1, int32_t per_period, int64_t max_sub,
+                                  int32_t *status);
+nb_status nb_groups_wait(nb_ctx *ctx);
 
 /* Library version string. */
 const char *nb_version(void);

@@ -25,7 +25,7 @@ NB_DS = 2
 PRECISIONS = {"fp64": NB_FP64, "mixed": NB_MIXED, "ds": NB_DS}
 
 STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
-          -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX"}
+          -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX", -7: "NB_EUNBOUND"}
 
 # Every symbol include/nbody.h declares.
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
@@ -33,7 +33,8 @@ EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_se
            "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
            "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
-           "nb_correct6"]
+           "nb_correct6", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
+           "nb_groups_advance_async", "nb_groups_wait"]
 
 
 class NbSystem(C.Structure):
@@ -99,6 +100,11 @@ def load() -> C.CDLL:
                                             i32, vp, vp, vp]),
         "nb_init_steps6": (C.c_int, [vp, ps, ph, vp, vp, vp, f64, f64, f64]),
         "nb_correct6": (C.c_int, [vp, ps, ph, vp, i32, vp, vp, vp, f64, f64, f64, f64]),
+        "nb_tidal_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, vp]),
+        "nb_kepler_drift": (C.c_int, [f64, vp, vp, f64, vp, vp]),
+        "nb_groups_advance": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
+        "nb_groups_advance_async": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
+        "nb_groups_wait": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

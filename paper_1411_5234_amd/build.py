@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["api.hip", "force.hip", "force6.hip", "step.hip", "step6.hip"]
+SOURCES = ["api.hip", "force.hip", "force6.hip", "step.hip", "step6.hip", "groups.hip"]
 ARCH = "gfx950"
 
 
@@ -30,7 +30,7 @@ def hipcc() -> str:
 def compile_flags() -> list[str]:
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
+            "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result", "-fopenmp"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:

@@ -15,7 +15,7 @@
 
 #include "nb_internal.h"
 
-#define NB_VERSION "0.4.0"
+#define NB_VERSION "0.5.0"
 
 using nbk::Item;
 using nbk::SelResult;
@@ -601,6 +601,14 @@ nb_status nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
 nb_status nb_ctx_destroy(nb_ctx *ctx)
 {
     if (!ctx) return NB_EINVAL;
+    if (ctx->worker.th.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(ctx->worker.mu);
+            ctx->worker.quit = true;
+        }
+        ctx->worker.cv.notify_all();
+        ctx->worker.th.join();   // a running job finishes first
+    }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
@@ -944,6 +952,52 @@ nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
     NB_TRY(make_table(ctx, items, blocks, &t));
     hipError_t e = nbk::launch_correct6(t, eta, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "correct6 launch");
+}
+
+// ---- tight pairs -------------------------------------------------------------------
+
+nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
+                          int64_t j0, int64_t j1, double eps, double *tensor)
+{
+    NB_TRY(check_system(ctx, sys, true));
+    if (!(eps >= 0.0) || !isfinite(eps)) return fail(ctx, NB_EINVAL, "eps must be >= 0 and finite");
+    if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
+    if (j0 < 0 || j1 > sys->n || j0 > j1) return fail(ctx, NB_EINVAL, "bad j-range");
+    if (m == 0) return NB_OK;
+    if (!tensor) return fail(ctx, NB_EINVAL, "tensor is NULL");
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].i_idx = i_idx;
+    items[0].m = m;
+    items[0].j0 = j0;
+    items[0].j1 = j1;
+    items[0].eps2 = eps * eps;
+    std::vector<int64_t> blocks{m};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_tidal(t, tensor, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
+}
+
+nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const double *M, double *r,
+                                  double *v, const double *H, const double *T0,
+                                  const double *T1, int32_t per_period, int64_t max_sub,
+                                  int32_t *status)
+{
+    if (!ctx) return NB_EINVAL;
+    return nb_groups_run(ctx, n, M, r, v, H, T0, T1, per_period, max_sub, status, true);
+}
+
+nb_status nb_groups_wait(nb_ctx *ctx)
+{
+    if (!ctx) return NB_EINVAL;
+    nb_ctx::Worker &w = ctx->worker;
+    std::unique_lock<std::mutex> lk(w.mu);
+    w.cv.wait(lk, [&w]() { return !w.busy; });
+    const nb_status r = (nb_status)w.result;
+    w.result = NB_OK;
+    lk.unlock();
+    if (r != NB_OK) fail(ctx, r, "a pair handed to the two-body drift is not bound");
+    return r;
 }
 
 }  // extern "C"

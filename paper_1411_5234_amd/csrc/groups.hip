@@ -1,0 +1,295 @@
+// Tight pairs, carried in the block-step system as one body at their centre of
+// mass (the HiGPUs-R scheme of Sec. 3 of the paper: tight groups are treated
+// apart from the N-body integration, on CPU threads, while the GPU works).
+//
+//  - GPU: the tidal tensor d a / d x of the softened field at each listed body,
+//    FP64, one workgroup per body.
+//  - CPU: the relative orbit of each pair over a block step, in substeps of
+//    kick (h/2) - exact two-body drift h - kick (h/2), the kicks from the tidal
+//    tensor interpolated linearly over the step; OpenMP, one pair per thread
+//    at a time; optionally on a thread of the context, so that it runs while
+//    the host goes on enqueueing GPU work.
+//  - The two-body drift uses universal variables (Stumpff functions), with the
+//    universal anomaly found by Newton steps kept inside a bracket.
+#include <math.h>
+#include <omp.h>
+
+#include "nb_internal.h"
+
+namespace nbk {
+
+// T[(3a+b) m + k] = sum_{j != i} m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),
+// r = xp_j - xp_i, s = |r|^2 + eps^2, for the k-th listed body i.  Each thread
+// sums a strided slice of j in order; the 256 partial sums are combined in a
+// fixed tree order.
+__global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int64_t *starts,
+                                                   int n_items, double *T)
+{
+    __shared__ double part[9][WG];
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t k = (int64_t)blockIdx.x - starts[it_k];   // one workgroup per body
+    const int64_t m = p.m;
+    int64_t i = p.i_idx ? (int64_t)p.i_idx[k] : k;
+    if (i < 0 || i >= p.s.n) {
+        if (threadIdx.x == 0)
+            atomicOr(p.status, (int)NBK_EINDEX);
+        i = 0;
+    }
+    const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp, *mass = p.s.m;
+    const double xi = xp[i], yi = yp[i], zi = zp[i];
+    double acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        acc[q] = 0.0;
+    for (int64_t j = p.j0 + threadIdx.x; j < p.j1; j += WG) {
+        if (j == i)
+            continue;
+        const double d[3] = {xp[j] - xi, yp[j] - yi, zp[j] - zi};
+        const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + p.eps2;
+        const double inv_s = 1.0 / s;
+        const double w3 = mass[j] * inv_s / sqrt(s);     // m / s^(3/2)
+        const double w5 = 3.0 * w3 * inv_s;              // 3 m / s^(5/2)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                acc[3 * a + b] += w5 * d[a] * d[b] - (a == b ? w3 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        part[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int half = WG / 2; half >= 1; half >>= 1) {
+        if ((int)threadIdx.x < half)
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                part[q][threadIdx.x] += part[q][threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9)
+        T[threadIdx.x * m + k] = part[threadIdx.x][0];
+}
+
+hipError_t launch_tidal(const Table &t, double *T, hipStream_t st)
+{
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tidal_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
+                       t.n, T);
+    return hipGetLastError();
+}
+
+}  // namespace nbk
+
+// ---- host: two-body drift and the relative orbit of a pair -------------------------
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Stumpff functions c2(z) = (1 - cos sqrt z) / z and c3(z) = (sqrt z - sin sqrt z) / z^1.5
+// for z >= 0 (series below 1e-3).
+void stumpff(double z, double &c2, double &c3)
+{
+    if (z > 1e-3) {
+        const double sz = sqrt(z);
+        c2 = (1.0 - cos(sz)) / z;
+        c3 = (sz - sin(sz)) / (z * sz);
+    } else {
+        c2 = 0.5 - z / 24.0 + z * z / 720.0 - z * z * z / 40320.0;
+        c3 = 1.0 / 6.0 - z / 120.0 + z * z / 5040.0 - z * z * z / 362880.0;
+    }
+}
+
+// Bound two-body motion of the relative coordinate over dt (mu = total mass).
+// Returns false for an unbound or degenerate pair.
+bool drift(double mu, const double *r0, const double *v0, double dt, double *r1, double *v1)
+{
+    const double r0n = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+    const double v2 = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    if (!(mu > 0.0) || !(r0n > 0.0))
+        return false;
+    const double alpha = 2.0 / r0n - v2 / mu;                 // 1 / a
+    if (!(alpha > 0.0))
+        return false;
+    const double smu = sqrt(mu);
+    const double period = kTwoPi / (smu * alpha * sqrt(alpha));
+    double t = fmod(dt, period);                              // Kepler motion is periodic
+    if (t < 0.0)
+        t += period;
+    const double rv = (r0[0] * v0[0] + r0[1] * v0[1] + r0[2] * v0[2]) / smu;
+    // F(chi) = rv chi^2 c2 + (1 - alpha r0) chi^3 c3 + r0 chi - sqrt(mu) t, with
+    // F' = |r(chi)| > 0; over one period chi runs from 0 to 2 pi / sqrt(alpha)
+    double lo = 0.0, hi = kTwoPi / sqrt(alpha);
+    double chi = smu * alpha * t;
+    if (!(chi > lo && chi < hi))
+        chi = 0.5 * (lo + hi);
+    double c2 = 0.5, c3 = 1.0 / 6.0, rn = r0n;
+    for (int it = 0; it < 200; ++it) {
+        const double z = alpha * chi * chi;
+        stumpff(z, c2, c3);
+        const double chi2 = chi * chi;
+        const double F = rv * chi2 * c2 + (1.0 - alpha * r0n) * chi2 * chi * c3 + r0n * chi -
+                         smu * t;
+        rn = chi2 * c2 + rv * chi * (1.0 - z * c3) + r0n * (1.0 - z * c2);
+        if (F > 0.0)
+            hi = chi;
+        else
+            lo = chi;
+        double next = chi - F / rn;
+        if (!(next > lo && next < hi))
+            next = 0.5 * (lo + hi);
+        const double step = next - chi;
+        chi = next;
+        if (fabs(step) <= 4e-16 * (1.0 + chi) || hi - lo <= 4e-16 * (1.0 + hi))
+            break;
+    }
+    const double z = alpha * chi * chi;
+    stumpff(z, c2, c3);
+    const double chi2 = chi * chi;
+    const double f = 1.0 - chi2 / r0n * c2;
+    const double g = t - chi2 * chi / smu * c3;
+    double r[3];
+    for (int c = 0; c < 3; ++c)
+        r[c] = f * r0[c] + g * v0[c];
+    const double r1n = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double fd = smu / (r1n * r0n) * chi * (z * c3 - 1.0);
+    const double gd = 1.0 - chi2 / r1n * c2;
+    for (int c = 0; c < 3; ++c) {
+        v1[c] = fd * r0[c] + gd * v0[c];
+        r1[c] = r[c];
+    }
+    return true;
+}
+
+// One pair over H: nsub substeps of kick - drift - kick, T linear from T0 to T1.
+bool advance_pair(double mu, double *r, double *v, double H, const double *T0, const double *T1,
+                  int per_period, int64_t max_sub)
+{
+    const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double alpha = 2.0 / rn - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / mu;
+    if (!(alpha > 0.0) || !(H >= 0.0))
+        return false;
+    const double period = kTwoPi / (sqrt(mu) * alpha * sqrt(alpha));
+    int64_t nsub = (int64_t)ceil((double)per_period * H / period);
+    if (nsub < 1) nsub = 1;
+    if (nsub > max_sub) nsub = max_sub;
+    const double h = H / (double)nsub;
+    auto kick = [&](double w) {
+        double tr[3];
+        for (int a = 0; a < 3; ++a) {
+            tr[a] = 0.0;
+            for (int b = 0; b < 3; ++b)
+                tr[a] += ((1.0 - w) * T0[3 * a + b] + w * T1[3 * a + b]) * r[b];
+        }
+        for (int a = 0; a < 3; ++a)
+            v[a] += 0.5 * h * tr[a];
+    };
+    for (int64_t q = 0; q < nsub; ++q) {
+        kick((double)q / (double)nsub);
+        double r1[3], v1[3];
+        if (!drift(mu, r, v, h, r1, v1))
+            return false;
+        for (int c = 0; c < 3; ++c) {
+            r[c] = r1[c];
+            v[c] = v1[c];
+        }
+        kick((double)(q + 1) / (double)nsub);
+    }
+    return true;
+}
+
+struct GroupJob {
+    int32_t n;
+    const double *M;
+    double *r, *v;
+    const double *H, *T0, *T1;
+    int32_t per_period;
+    int64_t max_sub;
+    int32_t *status;
+};
+
+nb_status run_groups(const GroupJob &j)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int32_t k = 0; k < j.n; ++k) {
+        const bool ok = advance_pair(j.M[k], j.r + 3 * k, j.v + 3 * k, j.H[k], j.T0 + 9 * k,
+                                     j.T1 + 9 * k, j.per_period, j.max_sub);
+        if (j.status) j.status[k] = ok ? NB_OK : NB_EUNBOUND;
+        bad += ok ? 0 : 1;
+    }
+    return bad ? NB_EUNBOUND : NB_OK;
+}
+
+nb_status check_group_args(int32_t n, const double *M, const double *r, const double *v,
+                           const double *H, const double *T0, const double *T1,
+                           int32_t per_period, int64_t max_sub)
+{
+    if (n < 0 || per_period < 1 || max_sub < 1) return NB_EINVAL;
+    if (n > 0 && (!M || !r || !v || !H || !T0 || !T1)) return NB_EINVAL;
+    return NB_OK;
+}
+
+}  // namespace
+
+nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const double *M, double *r, double *v,
+                        const double *H, const double *T0, const double *T1,
+                        int32_t per_period, int64_t max_sub, int32_t *status, bool async)
+{
+    const nb_status e = check_group_args(n, M, r, v, H, T0, T1, per_period, max_sub);
+    if (e != NB_OK) {
+        if (ctx) ctx->err = "nb_groups_advance: bad argument";
+        return e;
+    }
+    GroupJob job{n, M, r, v, H, T0, T1, per_period, max_sub, status};
+    if (!async)
+        return run_groups(job);
+    nb_ctx::Worker &w = ctx->worker;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        if (w.busy) {
+            ctx->err = "nb_groups_advance_async: a group advance is already running";
+            return NB_EINVAL;
+        }
+        w.job = [job]() { return (int)run_groups(job); };
+        w.busy = true;
+    }
+    if (!w.th.joinable()) {
+        w.th = std::thread([&w]() {
+            std::unique_lock<std::mutex> lk(w.mu);
+            for (;;) {
+                w.cv.wait(lk, [&w]() { return w.quit || (w.busy && w.job); });
+                if (w.quit) return;
+                std::function<int()> f = std::move(w.job);
+                w.job = nullptr;
+                lk.unlock();
+                const int r = f();
+                lk.lock();
+                w.result = r;
+                w.busy = false;
+                w.cv.notify_all();
+            }
+        });
+    }
+    w.cv.notify_all();
+    return NB_OK;
+}
+
+extern "C" {
+
+nb_status nb_kepler_drift(double M, const double *r0, const double *v0, double dt, double *r1,
+                          double *v1)
+{
+    if (!r0 || !v0 || !r1 || !v1 || !isfinite(dt)) return NB_EINVAL;
+    return drift(M, r0, v0, dt, r1, v1) ? NB_OK : NB_EUNBOUND;
+}
+
+nb_status nb_groups_advance(int32_t n, const double *M, double *r, double *v, const double *H,
+                            const double *T0, const double *T1, int32_t per_period,
+                            int64_t max_sub, int32_t *status)
+{
+    return nb_groups_run(nullptr, n, M, r, v, H, T0, T1, per_period, max_sub, status, false);
+}
+
+}  // extern "C"

@@ -10,7 +10,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 
 #include "../../include/nbody.h"
 
@@ -44,7 +48,22 @@ struct nb_ctx {
     char *stage_dev = nullptr;        // device ring mirrored by stage_host
     size_t stage_bytes = 0, stage_off = 0;
     std::string err;
+    // Host worker of nb_groups_advance_async: one persistent thread per context,
+    // started on first use, running one job at a time.
+    struct Worker {
+        std::thread th;
+        std::mutex mu;
+        std::condition_variable cv;
+        std::function<int()> job;
+        bool busy = false, quit = false;
+        int result = 0;
+    } worker;
 };
+
+// Pair advance (csrc/groups.hip); async = run on the context's thread.
+nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const double *M, double *r, double *v,
+                        const double *H, const double *T0, const double *T1, int32_t per_period,
+                        int64_t max_sub, int32_t *status, bool async);
 
 namespace nbk {
 
@@ -122,6 +141,8 @@ hipError_t launch_reduce(const Table &t, hipStream_t st);
 hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *out,
                          hipStream_t st);
 
+// Tidal tensors of the listed bodies, one workgroup per body, rows (3a+b)*m + k.
+hipError_t launch_tidal(const Table &t, double *T, hipStream_t st);
 // Selection: three passes over per-item workgroup slices, then per-item results.
 hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
                          hipStream_t st);

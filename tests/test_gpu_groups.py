@@ -1,0 +1,139 @@
+"""GPU parity of the tight-pair treatment (the HiGPUs-R scheme of Sec. 3, with
+bound pairs as the groups): nb_tidal_active against the oracle's tidal tensor, and
+the grouped block-step integration (GPU block steps + CPU-thread pair advance,
+overlapped) against the oracle's grouped integration."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import device_system
+from paper_1411_5234_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1411_5234_amd.nbody import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_tidal(ctx, sys, ilist, eps, j0=0, j1=None):
+    n = sys.n
+    m = len(ilist)
+    idx = torch.as_tensor(np.asarray(ilist, dtype=np.int32), device="cuda")
+    T = torch.full((9 * max(m, 1),), np.nan, dtype=torch.float64, device="cuda")
+    ctx._check(ctx.L.nb_tidal_active(ctx.h, sys.ref, idx.data_ptr(), m, j0, n if j1 is None else j1,
+                                     float(eps), T.data_ptr()))
+    ctx.sync()
+    return T[: 9 * m].view(9, m).T.cpu().numpy().reshape(m, 3, 3)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_tidal_matches_oracle(ctx, orc, eps):
+    s = inputs.plummer(3000, 81, masses=inputs.salpeter_masses(3000, 82))
+    sys = device_system(s.x, s.v, s.m)
+    il = np.sort(np.random.default_rng(83).choice(3000, 77, replace=False))
+    for j0, j1 in [(0, 3000), (13, 2911), (0, 1), (2999, 3000)]:
+        g = _gpu_tidal(ctx, sys, il, eps, j0, j1)
+        o = orc.tidal(s.x, s.m, eps, il, j0, j1)
+        scale = np.abs(o).max(axis=(1, 2)) + 1e-300
+        err = np.abs(g - o).max(axis=(1, 2)) / scale
+        print("tidal eps=%g [%d,%d): max rel %.3e" % (eps, j0, j1, err.max()), flush=True)
+        assert err.max() <= 1e-12
+
+
+def _cluster(a_hi=1e-3):
+    s = inputs.with_binaries(160, 10, frac_members=0.2, a_lo=1e-4, a_hi=a_hi, imf="equal")
+    return s, [(2 * k, 2 * k + 1) for k in range(16)]
+
+
+def _elements(M, r, w):
+    """Kepler energy, angular momentum and Laplace-Runge-Lenz vector per pair."""
+    rn = np.linalg.norm(r, axis=1)
+    E = 0.5 * (w ** 2).sum(1) - M / rn
+    h = np.cross(r, w)
+    lrl = np.cross(w, h) / M[:, None] - r / rn[:, None]
+    return E, h, lrl
+
+
+def test_grouped_integration_matches_oracle(ctx, orc):
+    """FP64 path.  The reduced system (single bodies and centres of mass) must follow
+    the oracle's to rounding and take the same block steps.  The pairs' relative
+    orbits are advanced by two independent FP64 implementations over up to ~2e3
+    orbits and ~1e5 substeps: rounding differences of ~1e-15 per substep shift
+    the orbital phase quadratically in the number of substeps (Kepler shear), so
+    the phase is compared loosely and the orbital elements, which the shear
+    leaves alone, tightly."""
+    from paper_1411_5234_amd.groups import GroupedIntegrator
+    from paper_1411_5234_amd.nbody import Params
+    s, pairs = _cluster()
+    eps = 1e-5
+    gi = GroupedIntegrator(ctx, s.x, s.v, s.m, pairs, Params(eps=eps, precision="fp64"))
+    gi.startup()
+    e0 = gi.energy()
+    glog = []
+    steps, _ = gi.run(0.125, log=glog)
+    x, v = gi.members()
+    olog = []
+    xo, vo, osteps, g = orc.group_integrate(s.x, s.v, s.m, pairs, 0.125, orc.Params(eps=eps),
+                                            log=olog)
+    print("GPU %d block steps, oracle %d; pairs advanced on the CPU: %d" % (
+        steps, osteps, gi.cpu_pairs_advanced), flush=True)
+    assert steps == osteps
+    for (tg, ig), (to, io) in zip(glog, olog):
+        assert tg == to and np.array_equal(ig, io)
+    st = gi.sys.state_numpy()
+    assert np.abs(st["x"] - g.st.x).max() <= 1e-12
+    assert np.abs(st["v"] - g.st.v).max() <= 1e-12 * (1 + np.abs(g.st.v).max())
+    Eg, hg, lg = _elements(gi.M, gi.r, gi.w)
+    Eo, ho, lo = _elements(g.M, g.r, g.w)
+    dE = np.abs(Eg - Eo) / np.abs(Eo)
+    dh = np.abs(hg - ho).max(1) / np.linalg.norm(ho, axis=1)
+    dl = np.abs(lg - lo).max(1)
+    dr = np.abs(gi.r - g.r).max(1) / np.linalg.norm(g.r, axis=1)
+    print("pairs: max rel energy %.2e, angular momentum %.2e, |dLRL| %.2e, phase (|dr|/r) %.2e"
+          % (dE.max(), dh.max(), dl.max(), dr.max()), flush=True)
+    assert dE.max() <= 1e-8 and dh.max() <= 1e-8 and dl.max() <= 1e-8
+    assert dr.max() <= 1e-4
+    assert np.abs(x - xo).max() <= 1e-4 * np.linalg.norm(g.r, axis=1).max()
+    e1 = gi.energy()
+    assert abs(e1 - e0) / abs(e0) < 1e-6
+    assert abs(e1 - orc.group_energy(g, s.m, eps)) <= 1e-8 * abs(e1)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_overlap_does_not_change_the_result(ctx, precision):
+    from paper_1411_5234_amd.groups import GroupedIntegrator
+    from paper_1411_5234_amd.nbody import Params
+    s, pairs = _cluster(3e-4)
+    out = []
+    for overlap in (True, False):
+        gi = GroupedIntegrator(ctx, s.x, s.v, s.m, pairs, Params(eps=1e-5, precision=precision),
+                               overlap=overlap)
+        gi.startup()
+        e0 = gi.energy()
+        gi.run(0.0625)
+        out.append(gi.members())
+        e1 = gi.energy()
+        print("%s overlap=%s: scheme |dE/E| = %.3e" % (precision, overlap, abs(e1 - e0) / abs(e0)),
+              flush=True)
+        assert abs(e1 - e0) / abs(e0) < 1e-5
+    assert out[0][0].tobytes() == out[1][0].tobytes()
+    assert out[0][1].tobytes() == out[1][1].tobytes()
+
+
+def test_unbound_pair_is_reported(ctx):
+    from paper_1411_5234_amd import _lib
+    from paper_1411_5234_amd.groups import GroupedIntegrator
+    from paper_1411_5234_amd.nbody import Params
+    s = inputs.plummer(64, 84)
+    x, v = s.x.copy(), s.v.copy()
+    v[1] = v[0] + np.array([10.0, 0.0, 0.0])      # bodies 0 and 1: far from bound
+    gi = GroupedIntegrator(ctx, x, v, s.m, [(0, 1)], Params(eps=1e-3, precision="fp64"))
+    gi.startup()
+    with pytest.raises(_lib.NbError) as e:
+        gi.run(0.125)
+    assert e.value.name == "NB_EUNBOUND"

@@ -1,0 +1,95 @@
+"""Host (CPU) parts of the tight-pair treatment in libnbody.so, against the oracle
+and the Kepler closed form.  No GPU is used: these are the library's CPU-thread
+routines (the HiGPUs-R scheme of Sec. 3 runs them beside the GPU kernels)."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+from test_oracle_hermite import kepler_state
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1411_5234_amd import _lib
+    return _lib.load()
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _drift(L, M, r0, v0, dt):
+    r0, v0 = np.ascontiguousarray(r0, float), np.ascontiguousarray(v0, float)
+    r1, v1 = np.empty(3), np.empty(3)
+    rc = L.nb_kepler_drift(float(M), _p(r0), _p(v0), float(dt), _p(r1), _p(v1))
+    return rc, r1, v1
+
+
+@pytest.mark.parametrize("e", [0.0, 0.4, 0.95, 0.9999])
+@pytest.mark.parametrize("t", [1e-3, 0.8, -3.1, 57.0])
+def test_library_drift_matches_oracle_and_closed_form(L, orc, e, t):
+    x0, v0 = kepler_state(0.35, 0.65, 0.7, e, 0.0, M0=1.1)
+    r0, w0 = x0[1] - x0[0], v0[1] - v0[0]
+    rc, r1, w1 = _drift(L, 1.0, r0, w0, t)
+    assert rc == 0
+    ro, wo = orc.kepler_drift(1.0, r0, w0, t)
+    vs = np.abs(wo).max() + 1.0
+    assert np.abs(r1 - ro).max() <= 1e-11 * (1 + abs(t))
+    assert np.abs(w1 - wo).max() <= 1e-11 * (1 + abs(t)) * vs
+    if e < 0.99:
+        xe, ve = kepler_state(0.35, 0.65, 0.7, e, t, M0=1.1)
+        assert np.abs(r1 - (xe[1] - xe[0])).max() <= 1e-11 * (1 + abs(t))
+
+
+def test_library_drift_refuses_unbound_and_bad_input(L):
+    rc, _, _ = _drift(L, 1.0, [1.0, 0, 0], [0, 1.5, 0], 0.1)
+    assert rc == -7
+    rc, _, _ = _drift(L, 0.0, [1.0, 0, 0], [0, 0.5, 0], 0.1)
+    assert rc == -7
+    rc, _, _ = _drift(L, 1.0, [1.0, 0, 0], [0, 0.5, 0], float("nan"))
+    assert rc == -1
+
+
+def test_library_group_advance_matches_oracle(L, orc):
+    rng = np.random.default_rng(11)
+    n = 40
+    M = rng.uniform(0.5, 2.0, n)
+    r = np.empty((n, 3))
+    v = np.empty((n, 3))
+    for k in range(n):
+        x0, v0 = kepler_state(0.5 * M[k], 0.5 * M[k], rng.uniform(0.2, 1.0), rng.uniform(0, 0.97),
+                              0.0, M0=rng.uniform(0, 6.28))
+        r[k], v[k] = x0[1] - x0[0], v0[1] - v0[0]
+    A = rng.normal(size=(n, 3, 3)) * 0.01
+    T0 = A + np.transpose(A, (0, 2, 1))
+    B = rng.normal(size=(n, 3, 3)) * 0.01
+    T1 = T0 + B + np.transpose(B, (0, 2, 1))
+    H = rng.uniform(0.0, 5.0, n)
+    H[0] = 0.0
+    rl, vl = r.copy(), v.copy()
+    status = np.full(n, 99, dtype=np.int32)
+    rc = L.nb_groups_advance(n, _p(M), _p(rl), _p(vl), _p(H), _p(np.ascontiguousarray(T0)),
+                             _p(np.ascontiguousarray(T1)), 32, 1 << 20, _p(status))
+    assert rc == 0 and np.all(status == 0)
+    for k in range(n):
+        Mk, rk, vk = M[k], r[k], v[k]
+        ns = orc.substeps(Mk, rk, vk, H[k], 32) if H[k] > 0 else 1
+        ro, vo = orc.group_advance(Mk, rk, vk, H[k], ns, T0[k], T1[k])
+        assert np.abs(rl[k] - ro).max() <= 1e-10, k
+        assert np.abs(vl[k] - vo).max() <= 1e-10 * (1 + np.abs(vo).max()), k
+    np.testing.assert_array_equal(rl[0], r[0])
+
+
+def test_library_group_advance_reports_unbound_pairs(L):
+    M = np.array([1.0, 1.0])
+    r = np.array([[1.0, 0, 0], [1.0, 0, 0]])
+    v = np.array([[0, 0.5, 0], [0, 2.0, 0]])     # the second is unbound
+    H = np.array([0.3, 0.3])
+    Z = np.zeros((2, 9))
+    status = np.zeros(2, dtype=np.int32)
+    rc = L.nb_groups_advance(2, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 32, 1 << 20, _p(status))
+    assert rc == -7 and list(status) == [0, -7]
+    assert L.nb_groups_advance(2, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 0, 1 << 20,
+                               None) == -1
