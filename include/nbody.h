@@ -321,23 +321,31 @@ nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
 nb_status nb_kepler_drift(double M, const double *r0, const double *v0, double dt,
                           double *r1, double *v1);
 
-/* Host.  Advance n pairs: pair k (mass M[k], relative r[3k..], v[3k..], updated in
- * place) over H[k] >= 0 in nsub = min(max_sub, max(1, ceil(per_period H / P)))
+/* Host.  Advance n pairs: pair k is row q = idx[k] (q = k when idx is NULL) of
+ * M, r, v and status: mass M[q], relative r[3q..], v[3q..] (updated in place),
+ * advanced over H[k] >= 0 in nsub = min(max_sub, max(1, ceil(per_period H / P)))
  * equal substeps (P its current orbital period), each kick (h/2) - drift h -
  * kick (h/2), a kick adding T(t) r times its length with T linear in t from
- * T0[9k..] to T1[9k..] (row-major 3x3).  OpenMP over pairs.  status (may be
- * NULL): per pair NB_OK or NB_EUNBOUND.  All arrays are HOST memory.  Returns
- * NB_OK, NB_EINVAL or NB_EUNBOUND if any pair failed. */
-nb_status nb_groups_advance(int32_t n, const double *M, double *r, double *v, const double *H,
-                            const double *T0, const double *T1, int32_t per_period,
-                            int64_t max_sub, int32_t *status);
+ * T0[9k..] to T1[9k..] (row-major 3x3).  H, T0 and T1 are indexed by k.  The
+ * rows in idx must be distinct and >= 0; the caller's arrays must hold every
+ * row named.  OpenMP over pairs.  status (may be NULL): per pair NB_OK or
+ * NB_EUNBOUND.  All arrays are HOST memory.  Returns NB_OK, NB_EINVAL or
+ * NB_EUNBOUND if any pair failed. */
+nb_status nb_groups_advance(int32_t n, const int32_t *idx, const double *M, double *r,
+                            double *v, const double *H, const double *T0, const double *T1,
+                            int32_t per_period, int64_t max_sub, int32_t *status);
 
-/* The same on a host thread of the context: returns at once, so that the caller
- * can enqueue GPU work meanwhile; the arrays must stay valid and untouched until
- * nb_groups_wait, which joins the thread and returns its result.  One advance at
- * a time per context (NB_EINVAL otherwise).  nb_ctx_destroy waits for it. */
-nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const double *M, double *r,
-                                  double *v, const double *H, const double *T0,
+/* The same, queued on a host thread of the context: returns at once, so that the
+ * caller can enqueue GPU work meanwhile.  Calls run one after another in call
+ * order (each with one OpenMP thread fewer than the default, leaving a core to
+ * the caller), so a later call may name rows that an earlier one is still
+ * advancing.  Every array of every queued call must stay valid, and r, v and
+ * status untouched, until nb_groups_wait, which blocks until the queue is empty
+ * and returns the first failure since the previous wait (NB_OK if none).
+ * NB_EINVAL (bad arguments) is returned at once and nothing is queued.
+ * nb_ctx_destroy runs what is queued before it returns. */
+nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const int32_t *idx, const double *M,
+                                  double *r, double *v, const double *H, const double *T0,
                                   const double *T1, int32_t per_period, int64_t max_sub,
                                   int32_t *status);
 nb_status nb_groups_wait(nb_ctx *ctx);

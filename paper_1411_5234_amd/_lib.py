@@ -102,8 +102,8 @@ def load() -> C.CDLL:
         "nb_correct6": (C.c_int, [vp, ps, ph, vp, i32, vp, vp, vp, f64, f64, f64, f64]),
         "nb_tidal_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, vp]),
         "nb_kepler_drift": (C.c_int, [f64, vp, vp, f64, vp, vp]),
-        "nb_groups_advance": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
-        "nb_groups_advance_async": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
+        "nb_groups_advance": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
+        "nb_groups_advance_async": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
         "nb_groups_wait": (C.c_int, [vp]),
     }
     for name, (res, args) in sig.items():

@@ -607,7 +607,7 @@ nb_status nb_ctx_destroy(nb_ctx *ctx)
             ctx->worker.quit = true;
         }
         ctx->worker.cv.notify_all();
-        ctx->worker.th.join();   // a running job finishes first
+        ctx->worker.th.join();   // queued pair advances finish first
     }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
@@ -978,13 +978,13 @@ nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
 }
 
-nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const double *M, double *r,
-                                  double *v, const double *H, const double *T0,
+nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const int32_t *idx, const double *M,
+                                  double *r, double *v, const double *H, const double *T0,
                                   const double *T1, int32_t per_period, int64_t max_sub,
                                   int32_t *status)
 {
     if (!ctx) return NB_EINVAL;
-    return nb_groups_run(ctx, n, M, r, v, H, T0, T1, per_period, max_sub, status, true);
+    return nb_groups_run(ctx, n, idx, M, r, v, H, T0, T1, per_period, max_sub, status, true);
 }
 
 nb_status nb_groups_wait(nb_ctx *ctx)
@@ -992,7 +992,7 @@ nb_status nb_groups_wait(nb_ctx *ctx)
     if (!ctx) return NB_EINVAL;
     nb_ctx::Worker &w = ctx->worker;
     std::unique_lock<std::mutex> lk(w.mu);
-    w.cv.wait(lk, [&w]() { return !w.busy; });
+    w.cv.wait(lk, [&w]() { return w.queue.empty() && !w.running; });
     const nb_status r = (nb_status)w.result;
     w.result = NB_OK;
     lk.unlock();

@@ -7,12 +7,16 @@
 //  - CPU: the relative orbit of each pair over a block step, in substeps of
 //    kick (h/2) - exact two-body drift h - kick (h/2), the kicks from the tidal
 //    tensor interpolated linearly over the step; OpenMP, one pair per thread
-//    at a time; optionally on a thread of the context, so that it runs while
-//    the host goes on enqueueing GPU work.
+//    at a time; optionally queued on a thread of the context, so that it runs
+//    while the host goes on enqueueing GPU work, as many block steps behind the
+//    GPU as the CPU needs.
 //  - The two-body drift uses universal variables (Stumpff functions), with the
 //    universal anomaly found by Newton steps kept inside a bracket.
 #include <math.h>
 #include <omp.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "nb_internal.h"
 
@@ -201,6 +205,7 @@ bool advance_pair(double mu, double *r, double *v, double H, const double *T0, c
 
 struct GroupJob {
     int32_t n;
+    const int32_t *idx;   // row of pair k in M, r, v, status; NULL = k
     const double *M;
     double *r, *v;
     const double *H, *T0, *T1;
@@ -209,65 +214,73 @@ struct GroupJob {
     int32_t *status;
 };
 
-nb_status run_groups(const GroupJob &j)
+// threads: OpenMP team size (0 = the runtime's default).
+nb_status run_groups(const GroupJob &j, int threads)
 {
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    const int nt = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad) num_threads(nt)
     for (int32_t k = 0; k < j.n; ++k) {
-        const bool ok = advance_pair(j.M[k], j.r + 3 * k, j.v + 3 * k, j.H[k], j.T0 + 9 * k,
-                                     j.T1 + 9 * k, j.per_period, j.max_sub);
-        if (j.status) j.status[k] = ok ? NB_OK : NB_EUNBOUND;
+        const int64_t row = j.idx ? j.idx[k] : k;
+        const bool ok = advance_pair(j.M[row], j.r + 3 * row, j.v + 3 * row, j.H[k],
+                                     j.T0 + 9 * k, j.T1 + 9 * k, j.per_period, j.max_sub);
+        if (j.status) j.status[row] = ok ? NB_OK : NB_EUNBOUND;
         bad += ok ? 0 : 1;
     }
     return bad ? NB_EUNBOUND : NB_OK;
 }
 
-nb_status check_group_args(int32_t n, const double *M, const double *r, const double *v,
-                           const double *H, const double *T0, const double *T1,
-                           int32_t per_period, int64_t max_sub)
+nb_status check_group_args(int32_t n, const int32_t *idx, const double *M, const double *r,
+                           const double *v, const double *H, const double *T0,
+                           const double *T1, int32_t per_period, int64_t max_sub)
 {
     if (n < 0 || per_period < 1 || max_sub < 1) return NB_EINVAL;
     if (n > 0 && (!M || !r || !v || !H || !T0 || !T1)) return NB_EINVAL;
+    if (idx && n > 0) {
+        // rows must be distinct: two threads must never advance one pair
+        std::vector<int32_t> rows(idx, idx + n);
+        std::sort(rows.begin(), rows.end());
+        if (rows.front() < 0 || std::adjacent_find(rows.begin(), rows.end()) != rows.end())
+            return NB_EINVAL;
+    }
     return NB_OK;
 }
 
 }  // namespace
 
-nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const double *M, double *r, double *v,
-                        const double *H, const double *T0, const double *T1,
+nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const int32_t *idx, const double *M, double *r,
+                        double *v, const double *H, const double *T0, const double *T1,
                         int32_t per_period, int64_t max_sub, int32_t *status, bool async)
 {
-    const nb_status e = check_group_args(n, M, r, v, H, T0, T1, per_period, max_sub);
+    const nb_status e = check_group_args(n, idx, M, r, v, H, T0, T1, per_period, max_sub);
     if (e != NB_OK) {
         if (ctx) ctx->err = "nb_groups_advance: bad argument";
         return e;
     }
-    GroupJob job{n, M, r, v, H, T0, T1, per_period, max_sub, status};
+    const GroupJob job{n, idx, M, r, v, H, T0, T1, per_period, max_sub, status};
     if (!async)
-        return run_groups(job);
+        return run_groups(job, 0);
+    // On the worker, leave one core to the thread that drives the GPU.
+    const int threads = omp_get_max_threads() > 1 ? omp_get_max_threads() - 1 : 1;
     nb_ctx::Worker &w = ctx->worker;
     {
         std::lock_guard<std::mutex> lk(w.mu);
-        if (w.busy) {
-            ctx->err = "nb_groups_advance_async: a group advance is already running";
-            return NB_EINVAL;
-        }
-        w.job = [job]() { return (int)run_groups(job); };
-        w.busy = true;
+        w.queue.push_back([job, threads]() { return (int)run_groups(job, threads); });
     }
     if (!w.th.joinable()) {
         w.th = std::thread([&w]() {
             std::unique_lock<std::mutex> lk(w.mu);
             for (;;) {
-                w.cv.wait(lk, [&w]() { return w.quit || (w.busy && w.job); });
-                if (w.quit) return;
-                std::function<int()> f = std::move(w.job);
-                w.job = nullptr;
+                w.cv.wait(lk, [&w]() { return w.quit || !w.queue.empty(); });
+                if (w.queue.empty()) return;   // quit, nothing left to run
+                std::function<int()> f = std::move(w.queue.front());
+                w.queue.pop_front();
+                w.running = true;
                 lk.unlock();
                 const int r = f();
                 lk.lock();
-                w.result = r;
-                w.busy = false;
+                if (w.result == NB_OK) w.result = r;
+                w.running = false;
                 w.cv.notify_all();
             }
         });
@@ -285,11 +298,11 @@ nb_status nb_kepler_drift(double M, const double *r0, const double *v0, double d
     return drift(M, r0, v0, dt, r1, v1) ? NB_OK : NB_EUNBOUND;
 }
 
-nb_status nb_groups_advance(int32_t n, const double *M, double *r, double *v, const double *H,
-                            const double *T0, const double *T1, int32_t per_period,
-                            int64_t max_sub, int32_t *status)
+nb_status nb_groups_advance(int32_t n, const int32_t *idx, const double *M, double *r,
+                            double *v, const double *H, const double *T0, const double *T1,
+                            int32_t per_period, int64_t max_sub, int32_t *status)
 {
-    return nb_groups_run(nullptr, n, M, r, v, H, T0, T1, per_period, max_sub, status, false);
+    return nb_groups_run(nullptr, n, idx, M, r, v, H, T0, T1, per_period, max_sub, status, false);
 }
 
 }  // extern "C"

@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <condition_variable>
+#include <deque>
 #include <functional>
 #include <mutex>
 #include <string>
@@ -50,20 +51,22 @@ struct nb_ctx {
     std::string err;
     // Host worker of nb_groups_advance_async: one persistent thread per context,
     // started on first use, running one job at a time.
+    // Host thread for pair advances: a FIFO of jobs run in call order; result is
+    // the first failure since the last wait.
     struct Worker {
         std::thread th;
         std::mutex mu;
         std::condition_variable cv;
-        std::function<int()> job;
-        bool busy = false, quit = false;
+        std::deque<std::function<int()>> queue;
+        bool running = false, quit = false;
         int result = 0;
     } worker;
 };
 
-// Pair advance (csrc/groups.hip); async = run on the context's thread.
-nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const double *M, double *r, double *v,
-                        const double *H, const double *T0, const double *T1, int32_t per_period,
-                        int64_t max_sub, int32_t *status, bool async);
+// Pair advance (csrc/groups.hip); async = queue on the context's thread.
+nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const int32_t *idx, const double *M, double *r,
+                        double *v, const double *H, const double *T0, const double *T1,
+                        int32_t per_period, int64_t max_sub, int32_t *status, bool async);
 
 namespace nbk {
 

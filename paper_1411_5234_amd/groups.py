@@ -8,11 +8,14 @@ block step also computes, on the GPU, the tidal tensor of the rest of the system
 at every pair's centre of mass (`nb_tidal_active`, from the same predicted set as
 the force).  A pair whose centre of mass was in a block advances its relative
 orbit to that block time on the host (`nb_groups_advance_async`: exact two-body
-drifts and tidal kicks, OpenMP over pairs), one block later: the host hands the
-previous block's pairs to the CPU threads right after the selection's host sync
-and then enqueues the next block's GPU work, so the two overlap.  Tensors and
-times come back through pinned buffers copied at the end of each block, so the
-pipeline adds no host sync of its own.
+drifts and tidal kicks, OpenMP over pairs).  The GPU never reads a pair's
+relative orbit, so the host only queues that work: right after the selection's
+host sync of the next block it queues the previous block's pairs on the
+context's CPU thread and goes on enqueueing GPU work.  The queue runs in order
+and may fall any number of blocks behind; the host waits for it only at the end
+of a run (or when reading the pairs).  Tensors and times come back through pinned
+buffers copied at the end of each block, so the pipeline adds no host sync of
+its own.
 """
 from __future__ import annotations
 
@@ -77,12 +80,19 @@ class GroupedIntegrator:
         self.T = np.zeros((k, 9))                 # tensor at each pair's own time
         self.tpair = np.zeros(k)
         self.status = np.zeros(k, dtype=np.int32)
-        self._job = None                          # arrays of the advance in flight
-        self._sync_rc = 0
+        self._pending = []                        # buffers of the queued advances
         self._prev_t = None                       # block time of the last GPU step
         self.cpu_pairs_advanced = 0
         self.cpu_seconds = 0.0                    # pair advance run on this thread
-        self.wait_seconds = 0.0                   # time blocked waiting for the worker
+        self.wait_seconds = 0.0                   # time blocked waiting for the queue
+
+    def __del__(self):
+        # the CPU thread writes into this object's arrays: never free them under it
+        try:
+            if self._pending:
+                self.ctx.L.nb_groups_wait(self.ctx.h)
+        except Exception:
+            pass
 
     # ---- GPU side --------------------------------------------------------------------
     def _tidal_to_host(self):
@@ -108,27 +118,26 @@ class GroupedIntegrator:
         self.tpair[:] = 0.0
 
     # ---- CPU side --------------------------------------------------------------------
-    def _wait(self):
-        if self._job is None:
+    MAX_QUEUED = 4096
+
+    def _fail(self, rc):
+        bad = np.nonzero(self.status[: self.np] != 0)[0]
+        raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
+
+    def _drain(self):
+        """Wait until every queued pair advance has run (self.r, self.w current)."""
+        if not self._pending:
             return
-        idx, M, r, w, H, T0, T1, st = self._job
-        if self.overlap:
-            t0 = time.perf_counter()
-            rc = self.ctx.L.nb_groups_wait(self.ctx.h)
-            self.wait_seconds += time.perf_counter() - t0
-        else:
-            rc = self._sync_rc
-        self._job = None
-        self.r[idx], self.w[idx] = r, w
-        self.status[idx] = st
+        t0 = time.perf_counter()
+        rc = self.ctx.L.nb_groups_wait(self.ctx.h)
+        self.wait_seconds += time.perf_counter() - t0
+        self._pending.clear()
         if rc != 0:
-            bad = idx[st != 0]
-            raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
+            self._fail(rc)
 
     def _launch(self):
-        """Hand the pairs advanced to the previous block time to the CPU threads
-        (their tensors and times are on the host after the selection's sync)."""
-        self._wait()
+        """Queue the advance of the pairs whose centre of mass was in the previous
+        block (their tensors and times are on the host after the selection's sync)."""
         if self._prev_t is None or self.np == 0:
             return
         tcm = self.tcm_host.numpy()[: self.np]
@@ -137,25 +146,26 @@ class GroupedIntegrator:
         if idx.size == 0:
             return
         Tn = self._host_tensor()[idx]
+        rows = np.ascontiguousarray(idx, dtype=np.int32)
         H = np.ascontiguousarray(self._prev_t - self.tpair[idx])
         T0 = np.ascontiguousarray(self.T[idx])
         T1 = np.ascontiguousarray(Tn)
-        M = np.ascontiguousarray(self.M[idx])
-        r = np.ascontiguousarray(self.r[idx])
-        w = np.ascontiguousarray(self.w[idx])
-        st = np.zeros(idx.size, dtype=np.int32)
-        self._job = (idx, M, r, w, H, T0, T1, st)
         self.T[idx] = Tn
         self.tpair[idx] = self._prev_t
         self.cpu_pairs_advanced += idx.size
-        args = (int(idx.size), _p(M), _p(r), _p(w), _p(H), _p(T0), _p(T1), self.per_period,
-                self.max_sub, _p(st))
+        args = (int(idx.size), _p(rows), _p(self.M), _p(self.r), _p(self.w), _p(H), _p(T0),
+                _p(T1), self.per_period, self.max_sub, _p(self.status))
         if self.overlap:
+            if len(self._pending) >= self.MAX_QUEUED:
+                self._drain()
+            self._pending.append((rows, H, T0, T1))
             self.ctx._check(self.ctx.L.nb_groups_advance_async(self.ctx.h, *args))
         else:
             t0 = time.perf_counter()
-            self._sync_rc = self.ctx.L.nb_groups_advance(*args)
+            rc = self.ctx.L.nb_groups_advance(*args)
             self.cpu_seconds += time.perf_counter() - t0
+            if rc != 0:
+                self._fail(rc)
 
     # ---- block steps -----------------------------------------------------------------
     def step(self):
@@ -182,13 +192,14 @@ class GroupedIntegrator:
             self._prev_t = t_next
         self.ctx.sync()
         self._launch()
-        self._wait()
+        self._drain()
         return self.it.steps, self.it.interactions
 
     # ---- results ---------------------------------------------------------------------
     def members(self):
         """(x, v) of all n original bodies; valid when every body and pair is at the
         same time (after run)."""
+        self._drain()
         st = self.sys.state_numpy()
         x, v = np.empty((self.n, 3)), np.empty((self.n, 3))
         ns = self.cm0
@@ -205,6 +216,7 @@ class GroupedIntegrator:
     def energy(self):
         """Reduced system's energy (softened) + each pair's two-body energy and tidal
         energy -mu r.T.r / 2 (the quantity the scheme conserves)."""
+        self._drain()
         er = self.ctx.energy(self.sys, self.p.eps)[2]
         if self.np == 0:
             return er

@@ -137,3 +137,60 @@ def test_unbound_pair_is_reported(ctx):
     with pytest.raises(_lib.NbError) as e:
         gi.run(0.125)
     assert e.value.name == "NB_EUNBOUND"
+
+
+def test_queued_advances_run_in_call_order(ctx):
+    """Queued calls that name the same rows run one after another, in call order:
+    the result equals the same calls made on the calling thread, bitwise; a failure
+    is reported by the next wait only."""
+    import ctypes as C
+
+    def p(a):
+        return a.ctypes.data_as(C.c_void_p)
+
+    rng = np.random.default_rng(31)
+    n = 6
+    M = rng.uniform(0.5, 2.0, n)
+    r = rng.normal(size=(n, 3))
+    rn = np.linalg.norm(r, axis=1)
+    w = np.cross(r, rng.normal(size=(n, 3)))
+    w *= (0.8 * np.sqrt(M / rn) / np.linalg.norm(w, axis=1))[:, None]
+    calls = []
+    for q in range(40):
+        k = int(rng.integers(1, n + 1))
+        rows = np.ascontiguousarray(rng.choice(n, k, replace=False), dtype=np.int32)
+        H = rng.uniform(0.0, 0.7, k)
+        T0 = rng.normal(size=(k, 9)) * 1e-3
+        T1 = rng.normal(size=(k, 9)) * 1e-3
+        calls.append((rows, H, T0, T1))
+    res = []
+    for queued in (True, False):
+        rr, ww = r.copy(), w.copy()
+        st = np.full(n, 99, dtype=np.int32)
+        for rows, H, T0, T1 in calls:
+            args = (rows.size, p(rows), p(M), p(rr), p(ww), p(H), p(T0), p(T1), 32, 1 << 20, p(st))
+            if queued:
+                assert ctx.L.nb_groups_advance_async(ctx.h, *args) == 0
+            else:
+                assert ctx.L.nb_groups_advance(*args) == 0
+        if queued:
+            assert ctx.L.nb_groups_wait(ctx.h) == 0
+        assert np.all(st == 0)
+        res.append((rr, ww))
+    assert res[0][0].tobytes() == res[1][0].tobytes()
+    assert res[0][1].tobytes() == res[1][1].tobytes()
+
+    # an unbound row fails its call; the queue goes on and the next wait reports it
+    wb = w.copy()
+    wb[2] *= 5.0
+    rr = r.copy()
+    st = np.zeros(n, dtype=np.int32)
+    rows = np.arange(n, dtype=np.int32)
+    H = np.full(n, 0.1)
+    Z = np.zeros((n, 9))
+    for _ in range(3):
+        assert ctx.L.nb_groups_advance_async(ctx.h, n, p(rows), p(M), p(rr), p(wb), p(H), p(Z),
+                                             p(Z), 32, 1 << 20, p(st)) == 0
+    assert ctx.L.nb_groups_wait(ctx.h) == -7
+    assert list(st) == [0, 0, -7, 0, 0, 0]
+    assert ctx.L.nb_groups_wait(ctx.h) == 0

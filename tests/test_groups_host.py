@@ -70,7 +70,7 @@ def test_library_group_advance_matches_oracle(L, orc):
     H[0] = 0.0
     rl, vl = r.copy(), v.copy()
     status = np.full(n, 99, dtype=np.int32)
-    rc = L.nb_groups_advance(n, _p(M), _p(rl), _p(vl), _p(H), _p(np.ascontiguousarray(T0)),
+    rc = L.nb_groups_advance(n, None, _p(M), _p(rl), _p(vl), _p(H), _p(np.ascontiguousarray(T0)),
                              _p(np.ascontiguousarray(T1)), 32, 1 << 20, _p(status))
     assert rc == 0 and np.all(status == 0)
     for k in range(n):
@@ -89,7 +89,55 @@ def test_library_group_advance_reports_unbound_pairs(L):
     H = np.array([0.3, 0.3])
     Z = np.zeros((2, 9))
     status = np.zeros(2, dtype=np.int32)
-    rc = L.nb_groups_advance(2, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 32, 1 << 20, _p(status))
+    rc = L.nb_groups_advance(2, None, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 32, 1 << 20, _p(status))
     assert rc == -7 and list(status) == [0, -7]
-    assert L.nb_groups_advance(2, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 0, 1 << 20,
+    assert L.nb_groups_advance(2, None, _p(M), _p(r), _p(v), _p(H), _p(Z), _p(Z), 0, 1 << 20,
                                None) == -1
+
+
+def _pairs(seed, n):
+    rng = np.random.default_rng(seed)
+    M = rng.uniform(0.5, 2.0, n)
+    r, v = np.empty((n, 3)), np.empty((n, 3))
+    for k in range(n):
+        x0, v0 = kepler_state(0.5 * M[k], 0.5 * M[k], rng.uniform(0.2, 1.0), rng.uniform(0, 0.9),
+                              0.0, M0=rng.uniform(0, 6.28))
+        r[k], v[k] = x0[1] - x0[0], v0[1] - v0[0]
+    A = rng.normal(size=(n, 9)) * 0.01
+    return M, r, v, A
+
+
+def test_library_group_advance_by_rows_equals_gathered_call(L):
+    """Rows named by idx advance exactly as the same pairs passed contiguously;
+    rows not named are left alone."""
+    n = 12
+    M, r, v, T = _pairs(5, n)
+    idx = np.array([7, 2, 11, 0], dtype=np.int32)
+    H = np.array([0.3, 1.1, 0.0, 2.5])
+    T0 = np.ascontiguousarray(T[:4])
+    T1 = np.ascontiguousarray(T[4:8])
+    rr, vv = r.copy(), v.copy()
+    status = np.full(n, 99, dtype=np.int32)
+    assert L.nb_groups_advance(4, _p(idx), _p(M), _p(rr), _p(vv), _p(H), _p(T0), _p(T1), 32,
+                               1 << 20, _p(status)) == 0
+    Mg, rg, vg = M[idx].copy(), r[idx].copy(), v[idx].copy()
+    assert L.nb_groups_advance(4, None, _p(Mg), _p(rg), _p(vg), _p(H), _p(T0), _p(T1), 32,
+                               1 << 20, None) == 0
+    np.testing.assert_array_equal(rr[idx], rg)
+    np.testing.assert_array_equal(vv[idx], vg)
+    rest = np.setdiff1d(np.arange(n), idx)
+    np.testing.assert_array_equal(rr[rest], r[rest])
+    np.testing.assert_array_equal(vv[rest], v[rest])
+    assert list(status[idx]) == [0] * 4 and np.all(status[rest] == 99)
+
+
+@pytest.mark.parametrize("idx", [[1, 1], [0, -1]])
+def test_library_group_advance_refuses_repeated_or_negative_rows(L, idx):
+    M, r, v, T = _pairs(6, 3)
+    idx = np.array(idx, dtype=np.int32)
+    H = np.array([0.1, 0.1])
+    T0 = np.ascontiguousarray(T[:2])
+    rr = r.copy()
+    assert L.nb_groups_advance(2, _p(idx), _p(M), _p(rr), _p(v.copy()), _p(H), _p(T0), _p(T0),
+                               32, 1 << 20, None) == -1
+    np.testing.assert_array_equal(rr, r)
