@@ -120,13 +120,86 @@ __device__ __forceinline__ void store9(const Item &p, int64_t bidx, int64_t k, c
     }
 }
 
+// LDS tile of the 6th-order mixed and DS kernels: one 64-byte record per j-body
+// (position as FP64 or as double-single hi/lo parts, then FP32 velocity, mass
+// and predicted acceleration), read with 16-byte LDS loads at immediate offsets
+// from one byte offset b = 64 q that the kernel keeps in a VGPR.  This takes
+// the address arithmetic of the structure-of-arrays tile (one SGPR-to-VGPR move
+// per array and j pair) out of the pair loop.  TILE6_PAD leaves room for the
+// read one run past the tile.
+constexpr int TILE6_PAD = TILE + 64;
+template <bool DS>
+struct Rec6;
+template <>
+struct Rec6<false> {
+    double x, y, z;
+    float vx, vy, vz, m, ax, ay, az, pad;
+};
+template <>
+struct Rec6<true> {
+    float xh, yh, zh, xl, yl, zl, vx, vy, vz, m, ax, ay, az, pad0, pad1, pad2;
+};
+
+template <bool DS>
+struct Tile6 {
+    static constexpr int REC = 64;
+    struct alignas(16) Slot {
+        Rec6<DS> e;
+    };
+    static_assert(sizeof(Slot) == 64, "64-byte j records");
+    Slot r[TILE6_PAD];
+    __device__ __forceinline__ void put(int q, double px, double py, double pz, float pvx,
+                                        float pvy, float pvz, float pm, float pax, float pay,
+                                        float paz)
+    {
+        Rec6<DS> e;
+        if constexpr (DS) {
+            split_ds(px, e.xh, e.xl);
+            split_ds(py, e.yh, e.yl);
+            split_ds(pz, e.zh, e.zl);
+            e.pad0 = 0.f; e.pad1 = 0.f; e.pad2 = 0.f;
+        } else {
+            e.x = px; e.y = py; e.z = pz;
+            e.pad = 0.f;
+        }
+        e.vx = pvx; e.vy = pvy; e.vz = pvz; e.m = pm;
+        e.ax = pax; e.ay = pay; e.az = paz;
+        r[q].e = e;
+    }
+    // j-body and its predicted acceleration at byte offset b (four 16-byte loads)
+    __device__ __forceinline__ JBody<DS> at(int b, float &ax, float &ay, float &az) const
+    {
+        const char *p = reinterpret_cast<const char *>(r) + b;
+        const float4 c = *reinterpret_cast<const float4 *>(p + 16);
+        const float4 d = *reinterpret_cast<const float4 *>(p + 32);
+        const float4 e = *reinterpret_cast<const float4 *>(p + 48);
+        // both layouts end in (vz, m, ax, ay), (az, pad...)
+        ax = d.z; ay = d.w; az = e.x;
+        if constexpr (DS) {
+            const float4 a = *reinterpret_cast<const float4 *>(p);
+            return JBody<true>{a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w, d.x, d.y};
+        } else {
+            const double2 xy = *reinterpret_cast<const double2 *>(p);
+            const double z = __hiloint2double(__float_as_int(c.y), __float_as_int(c.x));
+            return JBody<false>{xy.x, xy.y, z, c.z, c.w, d.x, d.y};
+        }
+    }
+};
+
+// The value v in a VGPR, so that offsets derived from it stay in VGPRs.
+__device__ __forceinline__ int in_vgpr(int v)
+{
+    int r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 template <int IL, int S, int F, bool DS>
 __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force6_mixed_kernel(const Item *items,
                                                                            const int64_t *starts,
                                                                            int n_items)
 {
-    __shared__ Tile<DS> tile;
-    __shared__ float tax[TILE], tay[TILE], taz[TILE];
+    __shared__ Tile6<DS> tile;
 
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
@@ -158,13 +231,11 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force6_mixed_kernel(const
         __syncthreads();
         for (int q = tid; q < TILE; q += WG) {
             const int64_t j = jt + q;
-            if (j < je) {
-                tile.put(q, xp[j], yp[j], zp[j], vx32[j], vy32[j], vz32[j], m32[j]);
-                tax[q] = ax32[j]; tay[q] = ay32[j]; taz[q] = az32[j];
-            } else {   // padding: zero mass contributes exactly zero
-                tile.put(q, 0.0, 0.0, 0.0, 0.f, 0.f, 0.f, 0.f);
-                tax[q] = 0.f; tay[q] = 0.f; taz[q] = 0.f;
-            }
+            if (j < je)
+                tile.put(q, xp[j], yp[j], zp[j], vx32[j], vy32[j], vz32[j], m32[j], ax32[j],
+                         ay32[j], az32[j]);
+            else   // padding: zero mass contributes exactly zero
+                tile.put(q, 0.0, 0.0, 0.0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
         const int lim = (int)min<int64_t>(TILE, je - jt);
@@ -174,15 +245,16 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force6_mixed_kernel(const
             for (int u = 0; u < IL; ++u)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; s32[u][c] = 0.f; }
-            int q = kk + s;
-            JBody<DS> cur = tile.get(q);
-            float cax = tax[q], cay = tay[q], caz = taz[q];
+            // byte offset of this lane's j; the next j is read ahead of this one's
+            // arithmetic (one run past the tile at the last step, into the padding)
+            int b = in_vgpr(Tile6<DS>::REC * (kk + s));
+            float cax, cay, caz;
+            JBody<DS> cur = tile.at(b, cax, cay, caz);
 #pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
-                // next j-body read ahead of this one's arithmetic
-                const int qn = kk + (f + 1 < F ? f + 1 : f) * S + s;
-                const JBody<DS> nxt = tile.get(qn);
-                const float nax = tax[qn], nay = tay[qn], naz = taz[qn];
+                b += Tile6<DS>::REC * S;
+                float nax, nay, naz;
+                const JBody<DS> nxt = tile.at(b, nax, nay, naz);
 #pragma unroll
                 for (int u = 0; u < IL; ++u) {
                     float dx, dy, dz;
