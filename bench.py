@@ -399,20 +399,14 @@ def mode_integrate(args):
     it.startup()
     last = [time.perf_counter()]
 
-    def progress(step_t, m):
+    def progress(step_t, steps):
         now = time.perf_counter()
         if now - last[0] > 10:
             last[0] = now
-            print("t=%.6f steps=%d interactions=%.3e wall=%.1fs" % (step_t, it.steps, it.interactions,
+            print("t=%.6f steps=%d interactions=%.3e wall=%.1fs" % (step_t, steps, it.interactions,
                                                                    now - t0), file=sys.stderr, flush=True)
 
-    while True:
-        t_next, m = ctx.select_active(system, it.i_idx)
-        if t_next > args.t_end:
-            break
-        it._advance(t_next, m)
-        progress(t_next, m)
-    ctx.sync()
+    it.run(args.t_end, progress=progress)
     wall = time.perf_counter() - t0
     E1 = ctx.energy(system, args.eps)[2]
     ctx.close()

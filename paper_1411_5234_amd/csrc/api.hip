@@ -157,7 +157,7 @@ nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
     return NB_OK;
 }
 
-// Upload the items with a positive workgroup count and their offsets.
+// Upload the items with a positive workgroup count and their offsets, in one copy.
 nb_status make_table(nb_ctx *ctx, const std::vector<Item> &items,
                      const std::vector<int64_t> &blocks, Table *t)
 {
@@ -177,11 +177,16 @@ nb_status make_table(nb_ctx *ctx, const std::vector<Item> &items,
     t->starts = nullptr;
     if (total == 0) return NB_OK;
     if (total > (int64_t)INT32_MAX) return fail(ctx, NB_EINVAL, "launch too large");
+    // one upload: the items, then their offsets (Item is a multiple of 8 bytes)
+    static_assert(sizeof(Item) % 8 == 0, "Item size");
+    const size_t ib = keep.size() * sizeof(Item), sb = starts.size() * sizeof(int64_t);
+    std::vector<char> buf(ib + sb);
+    memcpy(buf.data(), keep.data(), ib);
+    memcpy(buf.data() + ib, starts.data(), sb);
     const void *d = nullptr;
-    NB_TRY(upload(ctx, keep.data(), keep.size() * sizeof(Item), &d));
+    NB_TRY(upload(ctx, buf.data(), buf.size(), &d));
     t->items = (const Item *)d;
-    NB_TRY(upload(ctx, starts.data(), starts.size() * sizeof(int64_t), &d));
-    t->starts = (const int64_t *)d;
+    t->starts = (const int64_t *)((const char *)d + ib);
     return NB_OK;
 }
 
@@ -314,9 +319,13 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
     std::vector<int64_t> rblocks;
     for (ForceJob &j : jobs) {
         if (j.it.b > 1 && j.it.m > 0) {
+            // lanes per output value: about 16 chunks per lane, 1 to 64 lanes
+            int lanes = 1;
+            while (lanes < 64 && lanes * 16 <= j.it.b) lanes *= 2;
+            j.it.red_lanes = lanes;
             red.push_back(j.it);
-            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + nbk::WG - 1) /
-                              nbk::WG);
+            const int64_t per = nbk::WG / lanes;
+            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + per - 1) / per);
         }
     }
     if (!red.empty()) {

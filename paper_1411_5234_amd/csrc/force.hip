@@ -324,21 +324,37 @@ hipError_t launch_force(int precision, int il, int s, const Table &t, hipStream_
     }
 }
 
-// One thread per output value of every item with j_chunks > 1: the B partials
-// are summed in ascending chunk order (6 values per body, 9 for the 6th order).
+// Partial sums of every item with j_chunks B > 1, reduced to acc, jerk (and
+// snap): 6 values per body, 9 for the 6th order.  L = red_lanes lanes (a power
+// of two dividing WG) share an output value: lane l adds chunks l, l + L, l + 2L,
+// ... in ascending order, then the L lane sums are added in ascending l.  The
+// order depends on B and L only, so results are bitwise reproducible; with
+// L = 1 it is the plain ascending sum.  Many lanes per value keep the loads of a
+// large B (small active blocks) in flight together instead of in one chain.
 __global__ __launch_bounds__(WG) void reduce_partials_kernel(const Item *items,
                                                              const int64_t *starts, int n_items)
 {
+    __shared__ double lane_sum[WG];
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
-    const int64_t idx = ((int64_t)blockIdx.x - starts[it_k]) * WG + threadIdx.x;   // < K m
+    const int L = p.red_lanes;
+    const int per = WG / L;                                  // values per workgroup
+    const int ii = threadIdx.x % per, l = threadIdx.x / per;
+    const int64_t idx = ((int64_t)blockIdx.x - starts[it_k]) * per + ii;   // < K m
     const int64_t three_m = 3 * (int64_t)p.m;
     const int64_t km = force_outputs(p) * three_m / 3;
-    if (idx >= km)
-        return;
     double v = 0.0;
-    for (int b = 0; b < p.b; ++b)
-        v += p.part[(int64_t)b * km + idx];
+    if (idx < km) {
+#pragma unroll 8
+        for (int b = l; b < p.b; b += L)
+            v += p.part[(int64_t)b * km + idx];
+    }
+    lane_sum[threadIdx.x] = v;
+    __syncthreads();
+    if (l != 0 || idx >= km)
+        return;
+    for (int q = 1; q < L; ++q)
+        v += lane_sum[q * per + ii];
     if (idx < three_m)
         p.acc[idx] = v;
     else if (idx < 2 * three_m)

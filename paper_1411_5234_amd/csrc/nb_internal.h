@@ -101,7 +101,7 @@ struct Item {
     int64_t sel_slice;           // selection: bodies per workgroup
     int64_t sel_off;             // selection: first slot of this item's temporaries
     int32_t sel_blocks;          // selection: workgroups
-    int32_t pad;
+    int32_t red_lanes;           // partial reduction: lanes per output value
 };
 
 // Per-item selection results written by the selection kernels.

@@ -12,8 +12,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (FIELDS32, FIELDS64, H6_FIELDS32, H6_FIELDS64, NbError, NbHermite6, NbSystem,
-                   PRECISIONS)
+from ._lib import (FIELDS32, FIELDS64, H6_FIELDS32, H6_FIELDS64, NbBatchItem, NbError,
+                   NbHermite6, NbSystem, PRECISIONS)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -233,6 +233,8 @@ class Params:
 class Integrator:
     """Hermite-4 block-step driver (Sec. 2 items 1-2): select, predict, force, correct."""
 
+    NATIVE_STEP = True          # run() may step through nb_step_batch
+
     def __init__(self, ctx: Context, sys: System, p: Params):
         self.ctx, self.sys, self.p = ctx, sys, p
         n = max(sys.n, 1)
@@ -274,15 +276,51 @@ class Integrator:
         self.interactions += m * self.sys.n
         self.t = t_next
 
-    def run(self, t_end: float, log: list | None = None):
-        """Advance block steps until every body reaches t_end (a multiple of dt_max)."""
+    def run(self, t_end: float, log: list | None = None, progress=None):
+        """Advance block steps until every body reaches t_end (a multiple of dt_max).
+
+        With log (a list that receives (t_next, active indices) per block), or
+        for the 6th order, every step goes through the separate calls.  Otherwise
+        each step is one nb_step_batch call on this one system (selection,
+        predictor, force and corrector in one native call: the same kernels and
+        results).  progress, if given, is called as progress(t, steps) after
+        each step."""
+        if log is not None or not self.NATIVE_STEP:
+            while True:
+                t_next, m = self.ctx.select_active(self.sys, self.i_idx)
+                if t_next > t_end:
+                    break
+                if log is not None:
+                    log.append((t_next, self.i_idx[:m].cpu().numpy().astype(np.int64)))
+                self._advance(t_next, m)
+                if progress is not None:
+                    progress(self.t, self.steps)
+            self.ctx.sync()
+            return self.steps, self.interactions
+        item = NbBatchItem()
+        item.sys = self.sys._struct
+        item.i_idx = self.i_idx.data_ptr()
+        item.acc = self.acc.data_ptr()
+        item.jerk = self.jerk.data_ptr()
+        item.status = None
+        item.eps = float(self.p.eps)
+        item.t_end = float(t_end)
+        item.startup = 0
+        p, n = self.p, self.sys.n
+        args = (self.ctx.h, C.byref(item), 1, PRECISIONS[p.precision], float(p.eta),
+                float(p.eta_s), float(p.dt_max), float(p.dt_min))
+        step = self.ctx.L.nb_step_batch
         while True:
-            t_next, m = self.ctx.select_active(self.sys, self.i_idx)
-            if t_next > t_end:
+            self.ctx._check(step(*args))
+            if item.error:
+                raise NbError(item.error, "block step at t = %.17g" % item.t_next)
+            if item.done:
                 break
-            if log is not None:
-                log.append((t_next, self.i_idx[:m].cpu().numpy().astype(np.int64)))
-            self._advance(t_next, m)
+            self.steps += 1
+            self.interactions += item.m * n
+            self.t = item.t_next
+            if progress is not None:
+                progress(self.t, self.steps)
         self.ctx.sync()
         return self.steps, self.interactions
 
@@ -299,6 +337,8 @@ class Params6(Params):
 class Integrator6(Integrator):
     """Hermite-6 block-step driver: select, predict to the crackle, force with
     snap, 6th-order correct."""
+
+    NATIVE_STEP = False         # no batched 6th-order step: run() uses the separate calls
 
     def __init__(self, ctx: Context, sys: System, p: Params6, h6: Hermite6 | None = None):
         super().__init__(ctx, sys, p)

@@ -98,6 +98,28 @@ def test_every_plan_shape_matches(ctx, orc, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+def test_many_j_chunks(ctx, orc, c2, precision):
+    """Small active blocks split over up to 128 j-chunks: the partial sums are
+    reduced with several lanes per output value (in a fixed order) and must match
+    the oracle and repeat bitwise."""
+    il = np.sort(np.random.default_rng(23).permutation(c2.n)[:37])
+    sys = device_system(c2.x, c2.v, c2.m)
+    oa, oj = orc.force(c2.x, c2.v, c2.m, 1e-4, il)
+    sa, sj = orc.force_scale(c2.x, c2.v, c2.m, 1e-4, il)
+    for plan in [(1, 64, 16), (1, 64, 32), (1, 16, 64), (1, 64, 128), (2, 4, 100)]:
+        ga, gj = gpu_force(ctx, sys, 1e-4, precision, il, plan=plan)
+        ea, ej = report("chunks %s %s" % (plan, precision), ga, gj, oa, oj)
+        assert ea.max() <= TOL[precision]
+        if precision == "fp64":
+            assert ej.max() <= TOL[precision]
+        else:
+            assert (np.linalg.norm(gj - oj, axis=1) / sj).max() <= TOL[precision]
+    a1, j1 = gpu_force(ctx, sys, 1e-4, precision, il, plan=(1, 64, 128))
+    a2, j2 = gpu_force(ctx, sys, 1e-4, precision, il, plan=(1, 64, 128))
+    assert a1.tobytes() == a2.tobytes() and j1.tobytes() == j2.tobytes()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_bitwise_repeatable(ctx, precision):
     s = inputs.plummer(5000, 13)
     sys = device_system(s.x, s.v, s.m)

@@ -69,6 +69,18 @@ def test_force6_every_plan_shape(ctx, orc, precision):
         check6(orc, precision, g, s.x, s.v, ap, s.m, 1e-2, il, tag="plan %s" % (plan,))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+def test_force6_many_j_chunks(ctx, orc, salpeter16k, precision):
+    """A small active block over 32 j-chunks: nine partial sums per body reduced
+    with two lanes per output value."""
+    s, ap = salpeter16k
+    il = np.sort(np.random.default_rng(70).permutation(s.n)[:50])
+    sys, h6 = device_system6(s.x, s.v, s.m, ap)
+    for plan in [(1, 64, 32), (2, 16, 32), (1, 4, 20)]:
+        g = gpu_force6(ctx, sys, h6, 1e-4, precision, il, plan=plan)
+        check6(orc, precision, g, s.x, s.v, ap, s.m, 1e-4, il, tag="chunks %s" % (plan,))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_force6_ragged_j_ranges_and_repeatability(ctx, orc, precision):
     s = inputs.plummer(1000, 68, masses=inputs.salpeter_masses(1000, 69))

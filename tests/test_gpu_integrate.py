@@ -88,3 +88,27 @@ def test_mixed_integration_energy_drift(ctx, orc):
     # the mixed path's drift stays at the integrator's level, not the FP32 round-off floor
     assert res["fp64"] < 1e-6
     assert res["mixed"] < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_native_steps_equal_separate_calls(ctx, precision):
+    """Integrator.run steps through nb_step_batch (one native call per block step)
+    unless a log is asked for; both routes give the same block sequence and the
+    same final state, bitwise."""
+    from paper_1411_5234_amd.nbody import Integrator, Params
+    s = inputs.plummer(2000, 31, masses=inputs.salpeter_masses(2000, 32))
+    out = []
+    for use_log in (False, True):
+        sys = device_system(s.x, s.v, s.m)
+        it = Integrator(ctx, sys, Params(eps=1e-3, precision=precision))
+        it.startup()
+        seen = []
+        steps, inter = it.run(0.25, log=[] if use_log else None,
+                              progress=lambda t, k: seen.append((t, k)))
+        st = sys.state_numpy()
+        out.append((steps, inter, st, [t for t, _ in seen]))
+    (s0, i0, st0, t0), (s1, i1, st1, t1) = out
+    print("%s: %d steps, %d interactions" % (precision, s0, i0), flush=True)
+    assert s0 == s1 and i0 == i1 and t0 == t1 and len(t0) == s0
+    for k in st0:
+        assert st0[k].tobytes() == st1[k].tobytes(), k
