@@ -267,6 +267,18 @@ struct ForceJob {
     Plan plan;
 };
 
+nb_status ensure_side_streams(nb_ctx *ctx)
+{
+    if (ctx->side_ready) return NB_OK;
+    NB_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    for (int q = 0; q < nb_ctx::NSIDE; ++q) {
+        NB_HIP(ctx, hipStreamCreateWithFlags(&ctx->side[q], hipStreamNonBlocking));
+        NB_HIP(ctx, hipEventCreateWithFlags(&ctx->join[q], hipEventDisableTiming));
+    }
+    ctx->side_ready = true;
+    return NB_OK;
+}
+
 // Launch the force kernels (one launch per plan shape) and the partial reduction
 // for a set of jobs; every job's item already has its system, i_idx, m, j-range,
 // eps2, acc/jerk and status set.
@@ -299,9 +311,14 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
     for (size_t k = 0; k < jobs.size(); ++k)
         if (jobs[k].it.m > 0)
             shapes[{jobs[k].plan.il, jobs[k].plan.s, jobs[k].it.snap != nullptr}].push_back(k);
+    struct Launch {
+        int il, s;
+        bool h6;
+        Table t;
+    };
+    std::vector<Launch> launches;
     for (auto &kv : shapes) {
         const int il = std::get<0>(kv.first), s = std::get<1>(kv.first);
-        const bool h6 = std::get<2>(kv.first);
         const int iwg = (nbk::WG / s) * il;
         std::vector<Item> items;
         std::vector<int64_t> blocks;
@@ -309,11 +326,32 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
             items.push_back(jobs[k].it);
             blocks.push_back((int64_t)((jobs[k].it.m + iwg - 1) / iwg) * jobs[k].it.b);
         }
-        Table t;
-        NB_TRY(make_table(ctx, items, blocks, &t));
-        hipError_t e = h6 ? nbk::launch_force6(prec, il, s, t, ctx->stream)
-                          : nbk::launch_force(prec, il, s, t, ctx->stream);
+        Launch l{il, s, std::get<2>(kv.first), Table{}};
+        NB_TRY(make_table(ctx, items, blocks, &l.t));
+        launches.push_back(l);
+    }
+    // One launch per plan shape.  Several shapes (ragged batches) run side by side:
+    // the first on the context's stream, the others on side streams forked after
+    // the table uploads and joined back before the partial reduction.  Every item
+    // writes only its own outputs and partials, so the results do not depend on
+    // how the launches overlap.
+    const int nl = (int)launches.size();
+    if (nl > 1) {
+        NB_TRY(ensure_side_streams(ctx));
+        NB_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
+        for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q)
+            NB_HIP(ctx, hipStreamWaitEvent(ctx->side[q], ctx->fork, 0));
+    }
+    for (int k = 0; k < nl; ++k) {
+        const Launch &l = launches[k];
+        hipStream_t st = k == 0 ? ctx->stream : ctx->side[(k - 1) % nb_ctx::NSIDE];
+        hipError_t e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
+                            : nbk::launch_force(prec, l.il, l.s, l.t, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
+    }
+    for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q) {
+        NB_HIP(ctx, hipEventRecord(ctx->join[q], ctx->side[q]));
+        NB_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[q], 0));
     }
     std::vector<Item> red;
     std::vector<int64_t> rblocks;
@@ -620,6 +658,11 @@ nb_status nb_ctx_destroy(nb_ctx *ctx)
     }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (int q = 0; q < nb_ctx::NSIDE; ++q) {
+        if (ctx->side[q]) (void)hipStreamDestroy(ctx->side[q]);
+        if (ctx->join[q]) (void)hipEventDestroy(ctx->join[q]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->selbuf) (void)hipFree(ctx->selbuf);
     if (ctx->res) (void)hipFree(ctx->res);

@@ -49,10 +49,15 @@ struct nb_ctx {
     char *stage_dev = nullptr;        // device ring mirrored by stage_host
     size_t stage_bytes = 0, stage_off = 0;
     std::string err;
-    // Host worker of nb_groups_advance_async: one persistent thread per context,
-    // started on first use, running one job at a time.
-    // Host thread for pair advances: a FIFO of jobs run in call order; result is
-    // the first failure since the last wait.
+    // Side streams (default priority, created on first use) on which force
+    // launches of different plan shapes in one call run beside the one on
+    // `stream`, forked from and joined back to it with events.
+    static constexpr int NSIDE = 3;
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t fork = nullptr, join[NSIDE] = {};
+    bool side_ready = false;
+    // Host thread for pair advances (started on first use): a FIFO of jobs run in
+    // call order; result is the first failure since the last wait.
     struct Worker {
         std::thread th;
         std::mutex mu;
