@@ -13,7 +13,7 @@
 #include <utility>
 #include <vector>
 
-#include "nb_internal.h"
+#include "ctx.h"
 
 #define NB_VERSION "0.5.0"
 

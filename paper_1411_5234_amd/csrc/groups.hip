@@ -18,7 +18,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "nb_internal.h"
+#include "ctx.h"
 
 namespace nbk {
 
