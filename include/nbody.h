@@ -295,6 +295,19 @@ nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
                       const double *snap, double t_next, double eta, double dt_max,
                       double dt_min);
 
+/* One whole 6th-order block step of one system in one call (Sec. 2 items 1-2):
+ * nb_select_active (waits for the stream; t_next, m to the host pointers), then,
+ * if t_next <= t_end, nb_predict6 to t_next, nb_force6_active of the m active
+ * bodies from all n (eps, precision) and nb_correct6 (eta, dt_max, dt_min) —
+ * the same kernels and results as those calls made one by one.  Otherwise
+ * *done_host = 1 and nothing is enqueued.  i_idx (capacity n), acc, jerk, snap
+ * (3n each) are device arrays; t_next_host, m_host, done_host host scalars.
+ * Returns the first failing call's status (latched kernel errors included). */
+nb_status nb_step6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, int32_t *i_idx,
+                   double *acc, double *jerk, double *snap, double eps, nb_precision precision,
+                   double eta, double dt_max, double dt_min, double t_end, double *t_next_host,
+                   int32_t *m_host, int32_t *done_host);
+
 /* ---- tight pairs (the HiGPUs-R scheme of Sec. 3) -------------------------------------
  * Tight groups are taken out of the N-body integration and advanced apart from
  * it, on CPU threads, while the GPU kernels run.  Here a group is a bound pair:

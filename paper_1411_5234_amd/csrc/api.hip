@@ -1008,6 +1008,28 @@ nb_status nb_correct6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6,
 
 // ---- tight pairs -------------------------------------------------------------------
 
+nb_status nb_step6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, int32_t *i_idx,
+                   double *acc, double *jerk, double *snap, double eps, nb_precision precision,
+                   double eta, double dt_max, double dt_min, double t_end, double *t_next_host,
+                   int32_t *m_host, int32_t *done_host)
+{
+    if (!ctx) return NB_EINVAL;
+    if (!done_host) return fail(ctx, NB_EINVAL, "done is NULL");
+    *done_host = 0;
+    NB_TRY(check_h6(ctx, sys, h6));
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
+    NB_TRY(nb_select_active(ctx, sys, t_next_host, i_idx, m_host));
+    if (!(*t_next_host <= t_end)) {
+        *done_host = 1;
+        return NB_OK;
+    }
+    NB_TRY(nb_predict6(ctx, sys, h6, *t_next_host));
+    NB_TRY(nb_force6_active(ctx, sys, h6, i_idx, *m_host, 0, sys->n, eps, precision, acc, jerk,
+                            snap));
+    return nb_correct6(ctx, sys, h6, i_idx, *m_host, acc, jerk, snap, *t_next_host, eta, dt_max,
+                       dt_min);
+}
+
 nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
                           int64_t j0, int64_t j1, double eps, double *tensor)
 {

@@ -279,10 +279,10 @@ class Integrator:
     def run(self, t_end: float, log: list | None = None, progress=None):
         """Advance block steps until every body reaches t_end (a multiple of dt_max).
 
-        With log (a list that receives (t_next, active indices) per block), or
-        for the 6th order, every step goes through the separate calls.  Otherwise
-        each step is one nb_step_batch call on this one system (selection,
-        predictor, force and corrector in one native call: the same kernels and
+        With log (a list that receives (t_next, active indices) per block) every
+        step goes through the separate calls.  Otherwise each step is one native
+        call (nb_step_batch on this one system, nb_step6 for the 6th order:
+        selection, predictor, force and corrector with the same kernels and
         results).  progress, if given, is called as progress(t, steps) after
         each step."""
         if log is not None or not self.NATIVE_STEP:
@@ -297,6 +297,11 @@ class Integrator:
                     progress(self.t, self.steps)
             self.ctx.sync()
             return self.steps, self.interactions
+        self._run_native(t_end, progress)
+        self.ctx.sync()
+        return self.steps, self.interactions
+
+    def _run_native(self, t_end, progress):
         item = NbBatchItem()
         item.sys = self.sys._struct
         item.i_idx = self.i_idx.data_ptr()
@@ -321,8 +326,6 @@ class Integrator:
             self.t = item.t_next
             if progress is not None:
                 progress(self.t, self.steps)
-        self.ctx.sync()
-        return self.steps, self.interactions
 
 
 @dataclass
@@ -338,7 +341,7 @@ class Integrator6(Integrator):
     """Hermite-6 block-step driver: select, predict to the crackle, force with
     snap, 6th-order correct."""
 
-    NATIVE_STEP = False         # no batched 6th-order step: run() uses the separate calls
+    NATIVE_STEP = True          # run() may step through nb_step6
 
     def __init__(self, ctx: Context, sys: System, p: Params6, h6: Hermite6 | None = None):
         super().__init__(ctx, sys, p)
@@ -368,6 +371,24 @@ class Integrator6(Integrator):
         self.ctx.init_steps6(self.sys, self.h6, acc, jerk, snap, p.eta_s, p.dt_max, p.dt_min)
         self.interactions += 2 * n * n
         self.t = 0.0
+
+    def _run_native(self, t_end, progress):
+        p, n = self.p, self.sys.n
+        tn, m, done = C.c_double(), C.c_int32(), C.c_int32()
+        args = (self.ctx.h, self.sys.ref, self.h6.ref, self.i_idx.data_ptr(),
+                self.acc.data_ptr(), self.jerk.data_ptr(), self.snap.data_ptr(), float(p.eps),
+                PRECISIONS[p.precision], float(p.eta), float(p.dt_max), float(p.dt_min),
+                float(t_end), C.byref(tn), C.byref(m), C.byref(done))
+        step = self.ctx.L.nb_step6
+        while True:
+            self.ctx._check(step(*args))
+            if done.value:
+                break
+            self.steps += 1
+            self.interactions += m.value * n
+            self.t = tn.value
+            if progress is not None:
+                progress(self.t, self.steps)
 
     def _advance(self, t_next, m):
         p = self.p

@@ -236,3 +236,49 @@ def test_hermite6_argument_errors(ctx):
     with pytest.raises(_lib.NbError):
         ctx.correct6(sys, h6, None, 65, out, out, out, 0.125, 0.14, 0.125, 2.0 ** -40)
     ctx.sync()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_step6_native_equals_separate_calls(ctx, precision):
+    """Integrator6.run steps through nb_step6 unless a log is asked for; both routes
+    give the same block sequence and the same final state, bitwise."""
+    from paper_1411_5234_amd.nbody import Integrator6, Params6, System
+    s = inputs.plummer(1500, 71, masses=inputs.salpeter_masses(1500, 72))
+    out = []
+    for use_log in (False, True):
+        sys = System.from_arrays(s.x, s.v, s.m)
+        it = Integrator6(ctx, sys, Params6(eps=1e-3, precision=precision))
+        it.startup()
+        seen = []
+        steps, inter = it.run(0.125, log=[] if use_log else None,
+                              progress=lambda t, k: seen.append(t))
+        out.append((steps, inter, sys.state_numpy(), it.h6.state_numpy(), seen))
+    (s0, i0, st0, h0, t0), (s1, i1, st1, h1, t1) = out
+    print("%s: %d steps" % (precision, s0), flush=True)
+    assert s0 == s1 and i0 == i1 and t0 == t1 and len(t0) == s0 > 0
+    for k in st0:
+        assert st0[k].tobytes() == st1[k].tobytes(), k
+    for k in h0:
+        assert h0[k].tobytes() == h1[k].tobytes(), k
+
+
+def test_step6_reports_done_and_bad_arguments(ctx):
+    import ctypes as C
+
+    from paper_1411_5234_amd._lib import PRECISIONS
+    from paper_1411_5234_amd.nbody import Integrator6, Params6, System
+    s = inputs.plummer(200, 73)
+    sys = System.from_arrays(s.x, s.v, s.m)
+    it = Integrator6(ctx, sys, Params6(eps=1e-3))
+    it.startup()
+    tn, m, done = C.c_double(), C.c_int32(), C.c_int32()
+    base = [ctx.h, sys.ref, it.h6.ref, it.i_idx.data_ptr(), it.acc.data_ptr(), it.jerk.data_ptr(),
+            it.snap.data_ptr(), 1e-3, PRECISIONS["mixed"], 0.14, 0.125, 2.0 ** -40]
+    # t_end before the first block time: nothing is enqueued
+    assert ctx.L.nb_step6(*base, -1.0, C.byref(tn), C.byref(m), C.byref(done)) == 0
+    assert done.value == 1 and tn.value > 0 and m.value > 0
+    # bad step parameters, missing done pointer
+    bad = list(base)
+    bad[9] = -0.1
+    assert ctx.L.nb_step6(*bad, 1.0, C.byref(tn), C.byref(m), C.byref(done)) == -1
+    assert ctx.L.nb_step6(*base, 1.0, C.byref(tn), C.byref(m), None) == -1
