@@ -157,9 +157,36 @@ nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
     return NB_OK;
 }
 
-// Upload the items with a positive workgroup count and their offsets, in one copy.
+// Tables of one call that are uploaded together: make_table appends each to
+// `buf` and records where its pointers go; flush uploads the buffer in one copy
+// and sets them.  The Tables must stay in place until the flush.
+struct Staging {
+    std::vector<char> buf;
+    struct Fix {
+        Table *t;
+        size_t items_off, starts_off;
+    };
+    std::vector<Fix> fix;
+};
+
+nb_status flush(nb_ctx *ctx, Staging *st)
+{
+    if (st->fix.empty()) return NB_OK;
+    const void *d = nullptr;
+    NB_TRY(upload(ctx, st->buf.data(), st->buf.size(), &d));
+    for (const Staging::Fix &f : st->fix) {
+        f.t->items = (const Item *)((const char *)d + f.items_off);
+        f.t->starts = (const int64_t *)((const char *)d + f.starts_off);
+    }
+    st->buf.clear();
+    st->fix.clear();
+    return NB_OK;
+}
+
+// The table of the items with a positive workgroup count: items, then their
+// workgroup offsets.  Uploaded at once (st == nullptr) or at st's flush.
 nb_status make_table(nb_ctx *ctx, const std::vector<Item> &items,
-                     const std::vector<int64_t> &blocks, Table *t)
+                     const std::vector<int64_t> &blocks, Table *t, Staging *st = nullptr)
 {
     std::vector<Item> keep;
     std::vector<int64_t> starts;
@@ -177,17 +204,16 @@ nb_status make_table(nb_ctx *ctx, const std::vector<Item> &items,
     t->starts = nullptr;
     if (total == 0) return NB_OK;
     if (total > (int64_t)INT32_MAX) return fail(ctx, NB_EINVAL, "launch too large");
-    // one upload: the items, then their offsets (Item is a multiple of 8 bytes)
     static_assert(sizeof(Item) % 8 == 0, "Item size");
     const size_t ib = keep.size() * sizeof(Item), sb = starts.size() * sizeof(int64_t);
-    std::vector<char> buf(ib + sb);
-    memcpy(buf.data(), keep.data(), ib);
-    memcpy(buf.data() + ib, starts.data(), sb);
-    const void *d = nullptr;
-    NB_TRY(upload(ctx, buf.data(), buf.size(), &d));
-    t->items = (const Item *)d;
-    t->starts = (const int64_t *)((const char *)d + ib);
-    return NB_OK;
+    Staging local;
+    Staging *s = st ? st : &local;
+    const size_t off = (s->buf.size() + 255) / 256 * 256;
+    s->buf.resize(off + ib + sb);
+    memcpy(s->buf.data() + off, keep.data(), ib);
+    memcpy(s->buf.data() + off + ib, starts.data(), sb);
+    s->fix.push_back({t, off, off + ib});
+    return st ? NB_OK : flush(ctx, &local);
 }
 
 nb_status take_status(nb_ctx *ctx, int word)
@@ -279,10 +305,20 @@ nb_status ensure_side_streams(nb_ctx *ctx)
     return NB_OK;
 }
 
-// Launch the force kernels (one launch per plan shape) and the partial reduction
-// for a set of jobs; every job's item already has its system, i_idx, m, j-range,
-// eps2, acc/jerk and status set.
-nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
+// The force launches of a set of jobs: one per plan shape, then the partial
+// reduction.  prepare_force fixes each job's chunks and partials and stages the
+// tables; launch_force enqueues them once the tables are uploaded.
+struct ForceLaunch {
+    int il, s;
+    bool h6;
+    Table t;
+};
+struct ForcePlan {
+    std::vector<ForceLaunch> launches;   // reserved up front: staged Tables stay in place
+    Table red{};
+};
+
+nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, ForcePlan *fp, Staging *st)
 {
     size_t part_doubles = 0;
     for (ForceJob &j : jobs) {
@@ -305,18 +341,18 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
         if (j.it.b > 1) {
             j.it.part = (double *)ctx->scratch + off;
             off += nbk::force_outputs(j.it) * (size_t)j.it.m * (size_t)j.it.b;
+            // lanes per output value of the reduction: about 16 chunks per lane, 1 to 64
+            int lanes = 1;
+            while (lanes < 64 && lanes * 16 <= j.it.b) lanes *= 2;
+            j.it.red_lanes = lanes;
         }
     }
     std::map<std::tuple<int, int, bool>, std::vector<size_t>> shapes;
     for (size_t k = 0; k < jobs.size(); ++k)
         if (jobs[k].it.m > 0)
             shapes[{jobs[k].plan.il, jobs[k].plan.s, jobs[k].it.snap != nullptr}].push_back(k);
-    struct Launch {
-        int il, s;
-        bool h6;
-        Table t;
-    };
-    std::vector<Launch> launches;
+    fp->launches.clear();
+    fp->launches.reserve(shapes.size());
     for (auto &kv : shapes) {
         const int il = std::get<0>(kv.first), s = std::get<1>(kv.first);
         const int iwg = (nbk::WG / s) * il;
@@ -326,16 +362,29 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
             items.push_back(jobs[k].it);
             blocks.push_back((int64_t)((jobs[k].it.m + iwg - 1) / iwg) * jobs[k].it.b);
         }
-        Launch l{il, s, std::get<2>(kv.first), Table{}};
-        NB_TRY(make_table(ctx, items, blocks, &l.t));
-        launches.push_back(l);
+        fp->launches.push_back(ForceLaunch{il, s, std::get<2>(kv.first), Table{}});
+        NB_TRY(make_table(ctx, items, blocks, &fp->launches.back().t, st));
     }
-    // One launch per plan shape.  Several shapes (ragged batches) run side by side:
-    // the first on the context's stream, the others on side streams forked after
-    // the table uploads and joined back before the partial reduction.  Every item
-    // writes only its own outputs and partials, so the results do not depend on
-    // how the launches overlap.
-    const int nl = (int)launches.size();
+    std::vector<Item> red;
+    std::vector<int64_t> rblocks;
+    for (ForceJob &j : jobs) {
+        if (j.it.b > 1 && j.it.m > 0) {
+            red.push_back(j.it);
+            const int64_t per = nbk::WG / j.it.red_lanes;
+            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + per - 1) / per);
+        }
+    }
+    return make_table(ctx, red, rblocks, &fp->red, st);
+}
+
+// One launch per plan shape.  Several shapes (ragged batches) run side by side:
+// the first on the context's stream, the others on side streams forked after the
+// table uploads and joined back before the partial reduction.  Every item writes
+// only its own outputs and partials, so the results do not depend on how the
+// launches overlap.
+nb_status launch_force(nb_ctx *ctx, const ForcePlan &fp, int prec)
+{
+    const int nl = (int)fp.launches.size();
     if (nl > 1) {
         NB_TRY(ensure_side_streams(ctx));
         NB_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
@@ -343,7 +392,7 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
             NB_HIP(ctx, hipStreamWaitEvent(ctx->side[q], ctx->fork, 0));
     }
     for (int k = 0; k < nl; ++k) {
-        const Launch &l = launches[k];
+        const ForceLaunch &l = fp.launches[k];
         hipStream_t st = k == 0 ? ctx->stream : ctx->side[(k - 1) % nb_ctx::NSIDE];
         hipError_t e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
                             : nbk::launch_force(prec, l.il, l.s, l.t, st);
@@ -353,26 +402,19 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
         NB_HIP(ctx, hipEventRecord(ctx->join[q], ctx->side[q]));
         NB_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[q], 0));
     }
-    std::vector<Item> red;
-    std::vector<int64_t> rblocks;
-    for (ForceJob &j : jobs) {
-        if (j.it.b > 1 && j.it.m > 0) {
-            // lanes per output value: about 16 chunks per lane, 1 to 64 lanes
-            int lanes = 1;
-            while (lanes < 64 && lanes * 16 <= j.it.b) lanes *= 2;
-            j.it.red_lanes = lanes;
-            red.push_back(j.it);
-            const int64_t per = nbk::WG / lanes;
-            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + per - 1) / per);
-        }
-    }
-    if (!red.empty()) {
-        Table t;
-        NB_TRY(make_table(ctx, red, rblocks, &t));
-        hipError_t e = nbk::launch_reduce(t, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "partial reduction launch");
-    }
-    return NB_OK;
+    hipError_t e = nbk::launch_reduce(fp.red, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "partial reduction launch");
+}
+
+// Force for a set of jobs; every job's item already has its system, i_idx, m,
+// j-range, eps2, acc/jerk and status set.
+nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
+{
+    Staging st;
+    ForcePlan fp;
+    NB_TRY(prepare_force(ctx, jobs, &fp, &st));
+    NB_TRY(flush(ctx, &st));
+    return launch_force(ctx, fp, prec);
 }
 
 nb_status check_force_args(nb_ctx *ctx, const nb_system *sys, int32_t m, int64_t j0, int64_t j1,
@@ -592,16 +634,21 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
         job.plan = make_plan(items[k].sys.n, it.m, precision);
         jobs.push_back(job);
     }
-    Table t;
-    NB_TRY(make_table(ctx, pred, pblocks, &t));
-    hipError_t e = nbk::launch_predict(t, ctx->stream);
+    // every table of the iteration in one upload
+    Staging st;
+    Table tp, tc, ti;
+    ForcePlan fp;
+    NB_TRY(make_table(ctx, pred, pblocks, &tp, &st));
+    NB_TRY(prepare_force(ctx, jobs, &fp, &st));
+    NB_TRY(make_table(ctx, cor, cblocks, &tc, &st));
+    NB_TRY(make_table(ctx, ini, iblocks, &ti, &st));
+    NB_TRY(flush(ctx, &st));
+    hipError_t e = nbk::launch_predict(tp, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
-    NB_TRY(run_force(ctx, jobs, precision));
-    NB_TRY(make_table(ctx, cor, cblocks, &t));
-    e = nbk::launch_correct(t, eta, dt_max, dt_min, ctx->stream);
+    NB_TRY(launch_force(ctx, fp, precision));
+    e = nbk::launch_correct(tc, eta, dt_max, dt_min, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "correct launch");
-    NB_TRY(make_table(ctx, ini, iblocks, &t));
-    e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
+    e = nbk::launch_init_steps(ti, eta_s, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
 }
 
