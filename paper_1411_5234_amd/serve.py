@@ -154,6 +154,14 @@ class Server:
         self.results: list[Result] = []
         self.iterations = 0
         self.t0 = None
+        # the resident systems' batch items, one contiguous array handed to every
+        # nb_step_batch call and updated in place by it; rebuilt only when the set
+        # of resident systems changes.  _view reads its host fields with numpy.
+        self._arr = None
+        self._view = None
+        self._n = None
+        self._steps = None
+        self._inter = None
 
     # ---- admission -----------------------------------------------------------
     @property
@@ -184,9 +192,12 @@ class Server:
             slot = _Slot(req, self.device, self.precision, self._now())
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
+            self._sync_items()
             self.slots.append(slot)
+            self._arr = None
 
     def _retire(self, slot: _Slot, error: str | None):
+        self._sync_items()
         r = slot.result
         r.error = error
         if error is None:
@@ -198,36 +209,64 @@ class Server:
         self.results.append(r)
         self.adm.release(slot.req)
         self.slots.remove(slot)
+        self._arr = None
 
     # ---- one iteration: one block step of every resident system ---------------
     def _check(self, rc):
         if rc != 0:
             raise NbError(rc, self.L.nb_last_error(self.ctx.h).decode())
 
+    _FIELDS = ("t_next", "m", "startup", "error", "done")
+    _DTYPE = np.dtype({"names": list(_FIELDS), "formats": ["<f8", "<i4", "<i4", "<i4", "<i4"],
+                       "offsets": [getattr(NbBatchItem, f).offset for f in _FIELDS],
+                       "itemsize": C.sizeof(NbBatchItem)})
+
+    def _sync_items(self):
+        """Copy the item array's state (updated by the native calls) and the step
+        counters back into the slots, before the resident set changes."""
+        if self._arr is None:
+            return
+        for k, sl in enumerate(self.slots):
+            sl.item = NbBatchItem.from_buffer_copy(self._arr[k])
+            sl.result.steps = int(self._steps[k])
+            sl.result.interactions = int(self._inter[k])
+
+    def _build_items(self):
+        k = len(self.slots)
+        self._arr = (NbBatchItem * k)(*[sl.item for sl in self.slots])
+        raw = (C.c_char * C.sizeof(self._arr)).from_address(C.addressof(self._arr))
+        self._view = np.frombuffer(raw, dtype=self._DTYPE)
+        self._n = np.array([sl.n for sl in self.slots], dtype=np.int64)
+        self._steps = np.array([sl.result.steps for sl in self.slots], dtype=np.int64)
+        self._inter = np.array([sl.result.interactions for sl in self.slots], dtype=np.int64)
+
     def step(self):
         """One iteration: every resident system advances one block step in one
         native call (select, then predict, force and correct for every system not
         yet past its t_end, one launch per phase); finished or failed systems are
-        retired."""
-        slots = list(self.slots)
-        if not slots:
+        retired.  The items live in one array across iterations and the per-system
+        bookkeeping is vectorised, so the host work per iteration does not grow with
+        the number of resident systems."""
+        if not self.slots:
             return
-        items = (NbBatchItem * len(slots))(*[s.item for s in slots])
-        self._check(self.L.nb_step_batch(self.ctx.h, items, len(slots), self.prec_code, self.eta,
-                                         self.eta_s, self.dt_max, self.dt_min))
-        for s, it in zip(slots, items):
-            if it.error != 0:
-                self._retire(s, _lib.STATUS.get(it.error, str(it.error)))
-            elif it.done:
-                self._retire(s, None)
-            else:
-                if s.item.startup:
-                    s.result.interactions += s.n * s.n
-                else:
-                    s.result.steps += 1
-                    s.result.interactions += it.m * s.n
-                s.item.t_next, s.item.m, s.item.startup = it.t_next, it.m, it.startup
+        if self._arr is None:
+            self._build_items()
+        v = self._view
+        startup = v["startup"] != 0          # before the call, which clears it
+        self._check(self.L.nb_step_batch(self.ctx.h, self._arr, len(self.slots), self.prec_code,
+                                         self.eta, self.eta_s, self.dt_max, self.dt_min))
+        err, done = v["error"], v["done"]
+        ran = (err == 0) & (done == 0)
+        n = self._n
+        inc = np.where(startup, n * n, v["m"].astype(np.int64) * n)
+        self._inter[ran] += inc[ran]
+        self._steps[ran & ~startup] += 1
         self.iterations += 1
+        leave = np.flatnonzero((err != 0) | (done != 0))
+        if leave.size:
+            gone = [(self.slots[k], int(err[k])) for k in leave]
+            for sl, e in gone:
+                self._retire(sl, _lib.STATUS.get(e, str(e)) if e != 0 else None)
 
     # ---- driving a request stream ------------------------------------------------
     def run(self, requests, realtime: bool = True, on_iteration=None):
