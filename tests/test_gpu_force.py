@@ -171,3 +171,42 @@ def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
     # momentum balance over every body (a property at any size)
     ma = (s.m[:, None] * ga).sum(0)
     assert np.all(np.abs(ma) <= 1e-6 * (s.m[:, None] * np.abs(ga)).sum(0))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+def test_single_body_and_coincident_bodies(ctx, precision):
+    """A lone body feels exactly zero.  Bodies at one point (eps > 0) exert exactly
+    zero acceleration on each other (r = 0 zeroes every pair term), while the jerk
+    keeps its softened closed form: the time derivative of m r / (r^2 + eps^2)^(3/2)
+    at r = 0 is m (v_j - v_i) / eps^3."""
+    eps = 1e-3
+    x = np.array([[0.3, -0.2, 0.1]])
+    v = np.array([[1.0, 2.0, 3.0]])
+    sys = device_system(x, v, np.array([1.0]))
+    ga, gj = gpu_force(ctx, sys, eps, precision)
+    assert np.all(ga == 0.0) and np.all(gj == 0.0)
+    x3 = np.repeat(x, 3, axis=0)
+    v3 = np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.0], [-1.0, 0.5, 2.0]])
+    m3 = np.array([1.0, 2.0, 0.5])
+    sys = device_system(x3, v3, m3)
+    ga, gj = gpu_force(ctx, sys, eps, precision)
+    assert np.all(ga == 0.0)
+    want = np.array([(m3[:, None] * (v3 - v3[i])).sum(0) for i in range(3)]) / eps ** 3
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert np.abs(gj - want).max() <= tol * np.abs(want).max()
+    assert np.all(gj[0] == gj[1])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_n_2pow23_small_active_block(ctx, orc, precision):
+    """N = 2^23 (8 times the benchmarked system): a block of 200 active bodies
+    against every body, split over the plan's largest chunk count, against the
+    oracle."""
+    n = 1 << 23
+    s = inputs.plummer(n, 9)
+    sys = device_system(s.x, s.v, s.m)
+    il = np.sort(np.random.default_rng(31).choice(n, 200, replace=False))
+    ga, gj = gpu_force(ctx, sys, 1e-4, precision, il)
+    check(orc, precision, ga, gj, s.x, s.v, s.m, 1e-4, il, tag="N=2^23 m=200")
+    del sys
+    torch.cuda.empty_cache()

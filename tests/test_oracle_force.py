@@ -108,6 +108,13 @@ def test_self_term_and_coincident_bodies(orc):
     v2 = np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.0]])
     a, j = orc.force(x2, v2, np.array([1.0, 2.0]), 1e-3)
     assert np.all(a == 0.0) and np.all(j == 0.0)
+    # with different velocities the jerk is the softened closed form at r = 0:
+    # d/dt [m r (r^2 + eps^2)^(-3/2)] = m (v_j - v_i) / eps^3 there
+    v2[1] = [-0.5, 0.0, 4.0]
+    a, j = orc.force(x2, v2, np.array([1.0, 2.0]), 1e-3)
+    assert np.all(a == 0.0)
+    np.testing.assert_allclose(j[0], 2.0 * (v2[1] - v2[0]) / 1e-9, rtol=1e-14)
+    np.testing.assert_allclose(j[1], 1.0 * (v2[0] - v2[1]) / 1e-9, rtol=1e-14)
 
 
 def test_two_body_magnitude_scales_like_softened_inverse_square(orc):
