@@ -497,28 +497,39 @@ void sel_shape(int64_t n, int32_t *blocks_out, int64_t *slice_out)
 
 // Device selection for `items` (each with s, i_idx and status set; every item
 // has n >= 1); fills res (host copy, one SelResult per item).  Waits for the stream.
-nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResult> &res)
+// predict: after the results are copied out, every item is also predicted to its
+// t_next unless that is past the item's t_next field (its horizon); the host
+// waits only for the copy, so the prediction runs while it reads the results
+// and prepares the next launches.
+nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResult> &res,
+                     bool predict = false)
 {
     res.assign(items.size(), SelResult{INFINITY, 0, 0});
     if (items.empty()) return NB_OK;
     int64_t total = 0;
-    std::vector<int64_t> blocks;
+    std::vector<int64_t> blocks, pblocks;
     for (Item &it : items) {
         sel_shape(it.s.n, &it.sel_blocks, &it.sel_slice);
         it.sel_off = total;
         total += it.sel_blocks;
         blocks.push_back(it.sel_blocks);
+        pblocks.push_back((it.s.n + nbk::WG - 1) / nbk::WG);
     }
     size_t have = ctx->selbuf_bytes;
     NB_TRY(grow(ctx, &ctx->selbuf, &have, (size_t)total * (sizeof(double) + sizeof(int32_t)),
                 "selection temporaries"));
     ctx->selbuf_bytes = have;
     NB_TRY(ensure_res(ctx, items.size() * sizeof(SelResult)));
+    if (predict && !ctx->sel_done)
+        NB_HIP(ctx, hipEventCreateWithFlags(&ctx->sel_done, hipEventDisableTiming));
     double *blockval = (double *)ctx->selbuf;
     int32_t *blockcnt = (int32_t *)(blockval + total);
     SelResult *dres = (SelResult *)ctx->res;
-    Table t;
-    NB_TRY(make_table(ctx, items, blocks, &t));
+    Staging st;
+    Table t, tp;
+    NB_TRY(make_table(ctx, items, blocks, &t, &st));
+    if (predict) NB_TRY(make_table(ctx, items, pblocks, &tp, &st));
+    NB_TRY(flush(ctx, &st));
     if (t.n != (int)items.size()) return fail(ctx, NB_EINVAL, "selection of an empty system");
     hipError_t e = nbk::launch_select(t, blockval, blockcnt, dres, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "selection launch");
@@ -526,7 +537,14 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
     if (e != hipSuccess) return hip_fail(ctx, e, "status collection launch");
     NB_HIP(ctx, hipMemcpyAsync(ctx->res_host, dres, items.size() * sizeof(SelResult),
                                hipMemcpyDeviceToHost, ctx->stream));
-    NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (predict) {
+        NB_HIP(ctx, hipEventRecord(ctx->sel_done, ctx->stream));
+        e = nbk::launch_predict(tp, dres, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
+        NB_HIP(ctx, hipEventSynchronize(ctx->sel_done));
+    } else {
+        NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
     memcpy(res.data(), ctx->res_host, items.size() * sizeof(SelResult));
     return NB_OK;
 }
@@ -567,7 +585,9 @@ Item batch_item(nb_ctx *ctx, const nb_batch_item &b)
 }
 
 // a1 for every item (see nb_select_active_batch).
-nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items)
+// predict: non-startup items are also predicted to their t_next unless it is past
+// their t_end (see run_select).
+nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items, bool predict = false)
 {
     std::vector<Item> dev;
     std::vector<int32_t> which;
@@ -588,11 +608,12 @@ nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items)
         Item it = base_item(ctx, items[k].sys);
         if (items[k].status) it.status = items[k].status;
         it.i_idx = items[k].i_idx;
+        it.t_next = items[k].startup ? -INFINITY : items[k].t_end;   // prediction horizon
         dev.push_back(it);
         which.push_back(k);
     }
     std::vector<SelResult> res;
-    NB_TRY(run_select(ctx, dev, res));
+    NB_TRY(run_select(ctx, dev, res, predict));
     for (size_t q = 0; q < which.size(); ++q) {
         nb_batch_item &b = items[which[q]];
         if (!b.startup) {
@@ -605,9 +626,10 @@ nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items)
 }
 
 // a2 .. a5 for the items flagged in `run` (see the batch entry points).
+// predicted: the selection already predicted the non-startup items.
 nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
                         const std::vector<char> &run, nb_precision precision, double eta,
-                        double eta_s, double dt_max, double dt_min)
+                        double eta_s, double dt_max, double dt_min, bool predicted = false)
 {
     std::vector<Item> pred, cor, ini;
     std::vector<int64_t> pblocks, cblocks, iblocks;
@@ -622,8 +644,10 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
             ini.push_back(it);
             iblocks.push_back(nb);
         } else {
-            pred.push_back(it);
-            pblocks.push_back(nb);
+            if (!predicted) {
+                pred.push_back(it);
+                pblocks.push_back(nb);
+            }
             if (it.m > 0) {
                 cor.push_back(it);
                 cblocks.push_back((it.m + nbk::WG - 1) / nbk::WG);
@@ -643,7 +667,7 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
     NB_TRY(make_table(ctx, cor, cblocks, &tc, &st));
     NB_TRY(make_table(ctx, ini, iblocks, &ti, &st));
     NB_TRY(flush(ctx, &st));
-    hipError_t e = nbk::launch_predict(tp, ctx->stream);
+    hipError_t e = nbk::launch_predict(tp, nullptr, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
     NB_TRY(launch_force(ctx, fp, precision));
     e = nbk::launch_correct(tc, eta, dt_max, dt_min, ctx->stream);
@@ -710,6 +734,7 @@ nb_status nb_ctx_destroy(nb_ctx *ctx)
         if (ctx->join[q]) (void)hipEventDestroy(ctx->join[q]);
     }
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->sel_done) (void)hipEventDestroy(ctx->sel_done);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->selbuf) (void)hipFree(ctx->selbuf);
     if (ctx->res) (void)hipFree(ctx->res);
@@ -768,7 +793,7 @@ nb_status nb_predict(nb_ctx *ctx, const nb_system *sys, double t_next)
     std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
     Table t;
     NB_TRY(make_table(ctx, items, blocks, &t));
-    hipError_t e = nbk::launch_predict(t, ctx->stream);
+    hipError_t e = nbk::launch_predict(t, nullptr, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict launch");
 }
 
@@ -885,7 +910,7 @@ nb_status nb_predict_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_it
     }
     Table t;
     NB_TRY(make_table(ctx, dev, blocks, &t));
-    hipError_t e = nbk::launch_predict(t, ctx->stream);
+    hipError_t e = nbk::launch_predict(t, nullptr, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict launch");
 }
 
@@ -950,7 +975,7 @@ nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
         return fail(ctx, NB_EINVAL, "unknown precision");
     NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
     if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
-    NB_TRY(select_items(ctx, items, n_items));
+    NB_TRY(select_items(ctx, items, n_items, true));
     std::vector<char> run(n_items, 0);
     for (int32_t k = 0; k < n_items; ++k) {
         nb_batch_item &b = items[k];
@@ -963,7 +988,7 @@ nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
         NB_TRY(check_item(ctx, b, true));
         run[k] = 1;
     }
-    NB_TRY(advance_items(ctx, items, n_items, run, precision, eta, eta_s, dt_max, dt_min));
+    NB_TRY(advance_items(ctx, items, n_items, run, precision, eta, eta_s, dt_max, dt_min, true));
     for (int32_t k = 0; k < n_items; ++k)
         if (run[k]) items[k].startup = 0;
     return NB_OK;

@@ -35,6 +35,8 @@ struct nb_ctx {
     hipStream_t side[NSIDE] = {};
     hipEvent_t fork = nullptr, join[NSIDE] = {};
     bool side_ready = false;
+    // Recorded after the selection results' copy when a prediction follows it.
+    hipEvent_t sel_done = nullptr;
     // Host thread for pair advances (started on first use): a FIFO of jobs run in
     // call order; result is the first failure since the last wait.
     struct Worker {

@@ -110,7 +110,8 @@ hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, Se
                          hipStream_t st);
 // Copy each item's status word into res[k].status, then clear the words.
 hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipStream_t st);
-hipError_t launch_predict(const Table &t, hipStream_t st);
+// sel: null, or the device selection results of the same items (see predict_kernel).
+hipError_t launch_predict(const Table &t, const SelResult *sel, hipStream_t st);
 hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_min,
                           hipStream_t st);
 hipError_t launch_init_steps(const Table &t, double eta_s, double dt_max, double dt_min,

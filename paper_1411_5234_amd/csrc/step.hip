@@ -8,6 +8,28 @@
 
 namespace nbk {
 
+// Hermite-4 prediction of body i to t_next: position to the jerk term, velocity
+// to the jerk term, FP64, plus the FP32 copies of the predicted velocity and mass.
+__device__ __forceinline__ void predict_body(const nb_system &s, int64_t i, double t_next)
+{
+    const double d = t_next - s.t[i];
+    const double d2 = d * d * 0.5, d3 = d * d * d * (1.0 / 6.0);
+    const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+    const double ax = s.ax[i], ay = s.ay[i], az = s.az[i];
+    const double jx = s.jx[i], jy = s.jy[i], jz = s.jz[i];
+    s.xp[i] = s.x[i] + vx * d + ax * d2 + jx * d3;
+    s.yp[i] = s.y[i] + vy * d + ay * d2 + jy * d3;
+    s.zp[i] = s.z[i] + vz * d + az * d2 + jz * d3;
+    const double px = vx + ax * d + jx * d2;
+    const double py = vy + ay * d + jy * d2;
+    const double pz = vz + az * d + jz * d2;
+    s.vxp[i] = px; s.vyp[i] = py; s.vzp[i] = pz;
+    if (s.vxp32) {
+        s.vxp32[i] = (float)px; s.vyp32[i] = (float)py; s.vzp32[i] = (float)pz;
+        s.m32[i] = (float)s.m[i];
+    }
+}
+
 // ---- selection ---------------------------------------------------------------
 // Per item, the bodies are cut into sel_blocks contiguous slices of sel_slice.
 // Pass 1: each workgroup takes the minimum of t + dt over its slice.
@@ -164,38 +186,31 @@ hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipSt
 
 // ---- predictor -----------------------------------------------------------------
 
+// Each item's bodies to its t_next; or, with sel (the selection results of the
+// same items, still on the device), to sel[k].t_next when that is not past the
+// item's t_next field (then its horizon), so that the prediction can follow the
+// selection on the stream while the host reads the results.
 __global__ __launch_bounds__(WG) void predict_kernel(const Item *items, const int64_t *starts,
-                                                     int n_items)
+                                                     int n_items, const SelResult *sel)
 {
     const int k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[k];
     const int64_t i = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
-    const nb_system &s = p.s;
-    if (i >= s.n)
-        return;
-    const double d = p.t_next - s.t[i];
-    const double d2 = d * d * 0.5, d3 = d * d * d * (1.0 / 6.0);
-    const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-    const double ax = s.ax[i], ay = s.ay[i], az = s.az[i];
-    const double jx = s.jx[i], jy = s.jy[i], jz = s.jz[i];
-    s.xp[i] = s.x[i] + vx * d + ax * d2 + jx * d3;
-    s.yp[i] = s.y[i] + vy * d + ay * d2 + jy * d3;
-    s.zp[i] = s.z[i] + vz * d + az * d2 + jz * d3;
-    const double px = vx + ax * d + jx * d2;
-    const double py = vy + ay * d + jy * d2;
-    const double pz = vz + az * d + jz * d2;
-    s.vxp[i] = px; s.vyp[i] = py; s.vzp[i] = pz;
-    if (s.vxp32) {
-        s.vxp32[i] = (float)px; s.vyp32[i] = (float)py; s.vzp32[i] = (float)pz;
-        s.m32[i] = (float)s.m[i];
+    double tn = p.t_next;
+    if (sel) {
+        tn = sel[k].t_next;
+        if (!(tn <= p.t_next))
+            return;
     }
+    if (i < p.s.n)
+        predict_body(p.s, i, tn);
 }
 
-hipError_t launch_predict(const Table &t, hipStream_t st)
+hipError_t launch_predict(const Table &t, const SelResult *sel, hipStream_t st)
 {
     if (t.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(predict_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
-                       t.n);
+                       t.n, sel);
     return hipGetLastError();
 }
 

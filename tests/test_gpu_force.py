@@ -120,6 +120,19 @@ def test_many_j_chunks(ctx, orc, c2, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+def test_result_does_not_depend_on_active_order(ctx, c2, precision):
+    """The same active bodies listed in another order get the same bits: a body's
+    sum runs over the same j in the same order whichever lane or workgroup
+    holds it."""
+    il = np.sort(np.random.default_rng(24).permutation(c2.n)[:1000])
+    perm = np.random.default_rng(25).permutation(il.size)
+    sys = device_system(c2.x, c2.v, c2.m)
+    a1, j1 = gpu_force(ctx, sys, 1e-4, precision, il)
+    a2, j2 = gpu_force(ctx, sys, 1e-4, precision, il[perm])
+    assert a1[perm].tobytes() == a2.tobytes() and j1[perm].tobytes() == j2.tobytes()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_bitwise_repeatable(ctx, precision):
     s = inputs.plummer(5000, 13)
     sys = device_system(s.x, s.v, s.m)
