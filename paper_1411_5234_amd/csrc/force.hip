@@ -99,10 +99,10 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
             for (int u = 0; u < IL; ++u)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { a32[u][c] = 0.f; j32[u][c] = 0.f; }
-#if NBK_PREFETCH
             JBody<DS> cur = tile.get(kk + s);
 #pragma unroll NBK_UNROLL
             for (int f = 0; f < F; ++f) {
+                // the next j-body is read ahead of this one's arithmetic
                 const int qn = kk + (f + 1 < F ? f + 1 : f) * S + s;
                 const JBody<DS> nxt = tile.get(qn);
 #pragma unroll
@@ -114,19 +114,6 @@ __global__ __launch_bounds__(WG, NBK_MIXED_WAVES) void force_mixed_kernel(const 
                 }
                 cur = nxt;
             }
-#else
-#pragma unroll NBK_UNROLL
-            for (int f = 0; f < F; ++f) {
-                const JBody<DS> cur = tile.get(kk + f * S + s);
-#pragma unroll
-                for (int u = 0; u < IL; ++u) {
-                    float dx, dy, dz;
-                    diff(cur, pi[u], dx, dy, dz);
-                    pair_f32(dx, dy, dz, cur.vx - vxi[u], cur.vy - vyi[u], cur.vz - vzi[u], cur.m,
-                             eps2, a32[u], j32[u]);
-                }
-            }
-#endif
 #pragma unroll
             for (int u = 0; u < IL; ++u)
 #pragma unroll

@@ -89,9 +89,6 @@ __device__ __forceinline__ void diff(const JBody<true> &j, const IPos<true> &i, 
 #ifndef NBK_MIXED_WAVES
 #define NBK_MIXED_WAVES 1
 #endif
-#ifndef NBK_PREFETCH
-#define NBK_PREFETCH 1
-#endif
 
 // Running total of the FP32 run sums: FP64, or (NBK_KAHAN) an FP32 Kahan pair.
 struct Total {
