@@ -112,3 +112,35 @@ def test_native_steps_equal_separate_calls(ctx, precision):
     assert s0 == s1 and i0 == i1 and t0 == t1 and len(t0) == s0
     for k in st0:
         assert st0[k].tobytes() == st1[k].tobytes(), k
+
+
+def test_n_2pow20_integration_force_parity_sampled(ctx, orc):
+    """The benchmarked N = 2^20 Plummer system (eps = 1e-4, mixed precision) in its
+    real block-step integration: at several block steps, up to 64 of the active
+    bodies' forces, computed by the production launch on the GPU's own predicted
+    state, against the oracle on that state."""
+    from gpu_helpers import check
+    from paper_1411_5234_amd.nbody import Integrator, Params
+    n = 1 << 20
+    s = inputs.plummer(n, 3)
+    sys = device_system(s.x, s.v, s.m)
+    it = Integrator(ctx, sys, Params(eps=1e-4, precision="mixed"))
+    it.startup()
+    rng = np.random.default_rng(40)
+    checked = 0
+    for step in range(60):
+        t_next, m = ctx.select_active(sys, it.i_idx)
+        it._advance(t_next, m)
+        if step % 12 != 11:
+            continue
+        g = sys.state_numpy()
+        il = it.i_idx[:m].cpu().numpy().astype(np.int64)
+        pick = np.sort(rng.choice(m, min(m, 64), replace=False))
+        ga = it.acc.view(-1)[: 3 * m].view(3, m).T.cpu().numpy()[pick]
+        gj = it.jerk.view(-1)[: 3 * m].view(3, m).T.cpu().numpy()[pick]
+        check(orc, "mixed", ga, gj, g["xp"], g["vp"], g["m"], 1e-4, il[pick],
+              tag="N=2^20 step %d t=%.3e m=%d" % (step, t_next, m))
+        checked += 1
+    assert checked == 5
+    del sys
+    torch.cuda.empty_cache()
