@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--precision", choices=["mixed", "ds", "fp64"], default="mixed")
     ap.add_argument("--order", type=int, choices=[4, 6], default=4,
-                    help="Hermite order of the step mode (6: acc + jerk + snap, 6th-order corrector)")
+                    help="Hermite order of the step, integrate and serve modes (6: acc + jerk + snap, 6th-order corrector)")
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
@@ -467,15 +467,16 @@ def mode_serve(args):
 
     out = {"metric": "ensemble solves/s and p50/p99 latency", "mode": "serve",
            "config": {"workload": args.stream, "requests": args.requests, "slots": args.slots,
-                      "precision": args.precision, **{k: v for k, v in spec.items() if k != "base"}}}
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+                      "precision": args.precision, "order": args.order,
+                      **{k: v for k, v in spec.items() if k != "base"}}}
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
     t0 = time.perf_counter()
     res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
     closed = summarize(res, time.perf_counter() - t0)
     out["closed_batch"] = closed
     print("closed batch: %s" % closed, file=sys.stderr, flush=True)
     rate = 0.8 * closed["solves_per_s"]
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
     t0 = time.perf_counter()
     res = srv.run(stream(rate, args.requests), realtime=True, on_iteration=progress)
     poisson = summarize(res, time.perf_counter() - t0)
@@ -484,7 +485,7 @@ def mode_serve(args):
     print("poisson at %.2f/s: %s" % (rate, poisson), file=sys.stderr, flush=True)
     k = min(args.baseline_requests, args.requests)
     if k > 0:
-        srv = Server(ctx, precision="fp64", max_slots=1, energy=True)
+        srv = Server(ctx, precision="fp64", max_slots=1, energy=True, order=args.order)
         t0 = time.perf_counter()
         res = srv.run(stream(0.0, args.requests)[:k], realtime=False, on_iteration=progress)
         base = summarize(res, time.perf_counter() - t0)
@@ -492,7 +493,7 @@ def mode_serve(args):
         out["one_at_a_time_fp64"] = base
         print("one at a time fp64: %s" % base, file=sys.stderr, flush=True)
         # the same k requests through the batched server, for a like-for-like rate
-        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True)
+        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
         t0 = time.perf_counter()
         res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
         out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
@@ -500,7 +501,7 @@ def mode_serve(args):
         # the same requests in FP64 and in mixed precision: energy error per request
         per = {}
         for prec in ("fp64", "mixed"):
-            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True)
+            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, order=args.order)
             res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
             per[prec] = {r.rid: r for r in res}
         rows = []

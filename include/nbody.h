@@ -310,6 +310,18 @@ nb_status nb_step6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, int
                    double eta, double dt_max, double dt_min, double t_end, double *t_next_host,
                    int32_t *m_host, int32_t *done_host);
 
+/* nb_step_batch at 6th order (Sec. 2 item 1): one iteration of an ensemble loop
+ * in one call.  h6s[k] and snaps[k] (device, 3*n doubles) are item k's 6th-order
+ * arrays; its acc and jerk buffers hold the forces as in nb_step_batch.  A
+ * startup item takes the whole 6th-order startup in this call (the 4th-order
+ * force and startup steps, prediction to t = 0, acc + jerk + snap and
+ * nb_init_steps6's steps); the others take nb_predict6, nb_force6_active and
+ * nb_correct6 — the same kernels, plans and results as those calls on each
+ * system alone.  Host fields, errors and done as in nb_step_batch. */
+nb_status nb_step6_batch(nb_ctx *ctx, nb_batch_item *items, const nb_hermite6 *h6s,
+                         double *const *snaps, int32_t n_items, nb_precision precision,
+                         double eta, double eta_s, double dt_max, double dt_min);
+
 /* ---- tight pairs (the HiGPUs-R scheme of Sec. 3) -------------------------------------
  * Tight groups are taken out of the N-body integration and advanced apart from
  * it, on CPU threads, while the GPU kernels run.  Here a group is a bound pair:

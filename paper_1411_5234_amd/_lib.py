@@ -33,7 +33,7 @@ EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_se
            "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
            "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
-           "nb_correct6", "nb_step6", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
+           "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
            "nb_groups_advance_async", "nb_groups_wait"]
 
 
@@ -102,6 +102,8 @@ def load() -> C.CDLL:
         "nb_correct6": (C.c_int, [vp, ps, ph, vp, i32, vp, vp, vp, f64, f64, f64, f64]),
         "nb_step6": (C.c_int, [vp, ps, ph, vp, vp, vp, vp, f64, C.c_int, f64, f64, f64, f64, vp, vp,
                                vp]),
+        "nb_step6_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), ph, C.POINTER(C.c_void_p), i32,
+                                     C.c_int, f64, f64, f64, f64]),
         "nb_tidal_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, vp]),
         "nb_kepler_drift": (C.c_int, [f64, vp, vp, f64, vp, vp]),
         "nb_groups_advance": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp]),

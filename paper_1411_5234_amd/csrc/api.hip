@@ -676,6 +676,73 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
 }
 
+// The 6th-order step of the items flagged in `run` (see nb_step6_batch).  Startup
+// items take the two passes of the 6th-order startup: the 4th-order force and
+// startup steps, then prediction to t = 0 (which stores the accelerations as the
+// predicted ones), acceleration + jerk + snap and the 6th-order startup steps.
+// The other items: predict6 to t_next, force6, correct6.  The startup's first
+// pass is its own group of launches, so that the force partials of the two
+// passes never share a scratch allocation.
+nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermite6 *h6s,
+                         double *const *snaps, int32_t n_items, const std::vector<char> &run,
+                         nb_precision precision, double eta, double eta_s, double dt_max,
+                         double dt_min)
+{
+    std::vector<Item> ini4, pred6, cor6, ini6;
+    std::vector<int64_t> bi4, bp6, bc6, bi6;
+    std::vector<ForceJob> jobs4, jobs6;
+    for (int32_t k = 0; k < n_items; ++k) {
+        if (!run[k] || items[k].sys.n == 0) continue;
+        const int64_t n = items[k].sys.n;
+        const int64_t nb = (n + nbk::WG - 1) / nbk::WG;
+        Item it = batch_item(ctx, items[k]);
+        it.h6 = h6s[k];
+        if (items[k].startup) {
+            ini4.push_back(it);
+            bi4.push_back(nb);
+            jobs4.push_back(ForceJob{it, make_plan(n, (int32_t)n, precision)});
+            it.t_next = 0.0;
+        }
+        it.snap = snaps[k];
+        pred6.push_back(it);
+        bp6.push_back(nb);
+        jobs6.push_back(ForceJob{it, make_plan(n, it.m, precision)});
+        if (items[k].startup) {
+            ini6.push_back(it);
+            bi6.push_back(nb);
+        } else if (it.m > 0) {
+            cor6.push_back(it);
+            bc6.push_back((it.m + nbk::WG - 1) / nbk::WG);
+        }
+    }
+    if (!jobs4.empty()) {
+        Staging st;
+        Table t4;
+        ForcePlan fp4;
+        NB_TRY(prepare_force(ctx, jobs4, &fp4, &st));
+        NB_TRY(make_table(ctx, ini4, bi4, &t4, &st));
+        NB_TRY(flush(ctx, &st));
+        NB_TRY(launch_force(ctx, fp4, precision));
+        hipError_t e = nbk::launch_init_steps(t4, eta_s, dt_max, dt_min, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "init_steps launch");
+    }
+    Staging st;
+    Table tp, tc, ti;
+    ForcePlan fp;
+    NB_TRY(make_table(ctx, pred6, bp6, &tp, &st));
+    NB_TRY(prepare_force(ctx, jobs6, &fp, &st));
+    NB_TRY(make_table(ctx, cor6, bc6, &tc, &st));
+    NB_TRY(make_table(ctx, ini6, bi6, &ti, &st));
+    NB_TRY(flush(ctx, &st));
+    hipError_t e = nbk::launch_predict6(tp, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "predict6 launch");
+    NB_TRY(launch_force(ctx, fp, precision));
+    e = nbk::launch_correct6(tc, eta, dt_max, dt_min, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "correct6 launch");
+    e = nbk::launch_init_steps6(ti, eta_s, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps6 launch");
+}
+
 nb_status check_step_params(nb_ctx *ctx, double eta, double dt_max, double dt_min)
 {
     if (!(eta > 0.0) || !(dt_max > 0.0) || !(dt_min > 0.0) || dt_min > dt_max)
@@ -1100,6 +1167,46 @@ nb_status nb_step6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, int
                             snap));
     return nb_correct6(ctx, sys, h6, i_idx, *m_host, acc, jerk, snap, *t_next_host, eta, dt_max,
                        dt_min);
+}
+
+nb_status nb_step6_batch(nb_ctx *ctx, nb_batch_item *items, const nb_hermite6 *h6s,
+                         double *const *snaps, int32_t n_items, nb_precision precision,
+                         double eta, double eta_s, double dt_max, double dt_min)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && (!items || !h6s || !snaps)))
+        return fail(ctx, NB_EINVAL, "bad item arrays");
+    if (precision != NB_FP64 && precision != NB_MIXED && precision != NB_DS)
+        return fail(ctx, NB_EINVAL, "unknown precision");
+    NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
+    if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
+    for (int32_t k = 0; k < n_items; ++k) {
+        if (items[k].sys.n == 0) continue;
+        NB_TRY(check_h6(ctx, &items[k].sys, &h6s[k]));
+        if (!snaps[k]) return fail(ctx, NB_EINVAL, "an item's snap array is NULL");
+        if (precision != NB_FP64 && !h6s[k].axp32)
+            return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 accelerations");
+    }
+    NB_TRY(select_items(ctx, items, n_items));
+    std::vector<char> run(n_items, 0);
+    for (int32_t k = 0; k < n_items; ++k) {
+        nb_batch_item &b = items[k];
+        b.done = 0;
+        if (b.error != NB_OK || b.sys.n == 0) continue;
+        if (!b.startup && b.t_next > b.t_end) {
+            b.done = 1;
+            continue;
+        }
+        NB_TRY(check_item(ctx, b, true));
+        if (precision != NB_FP64 && !b.sys.vxp32)
+            return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 copies");
+        run[k] = 1;
+    }
+    NB_TRY(advance_items6(ctx, items, h6s, snaps, n_items, run, precision, eta, eta_s, dt_max,
+                          dt_min));
+    for (int32_t k = 0; k < n_items; ++k)
+        if (run[k]) items[k].startup = 0;
+    return NB_OK;
 }
 
 nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,

@@ -1,13 +1,15 @@
 """Continuous-batching server for ensembles of N-body simulations.
 
-Each request is an initial condition to integrate to t_end with the Hermite-4
-block-step scheme.  The server keeps every admitted system's state resident in
-HBM and advances ALL resident systems together: one iteration is one block step
-of every resident system, done by one native call (nb_step_batch: selection,
-then one ragged batched launch per phase for predict, force and correct).  Requests that arrive while others run are admitted between
-iterations as slots and device memory free up; a finished or failed system is
-retired at once and its memory is released.  A failing system (non-finite
-values, a step below dt_min) is reported alone; the others go on.
+Each request is an initial condition to integrate to t_end with the Hermite
+block-step scheme (4th order, or 6th with order=6).  The server keeps every
+admitted system's state resident in HBM and advances ALL resident systems
+together: one iteration is one block step of every resident system, done by one
+native call (nb_step_batch or nb_step6_batch: selection, then one ragged batched
+launch per phase for predict, force and correct).  Requests that arrive while
+others run are admitted between iterations as slots and device memory free up; a
+finished or failed system is retired at once and its memory is released.  A
+failing system (non-finite values, a step below dt_min) is reported alone; the
+others go on.
 
 Every system is computed with the same kernels, launch plan and arithmetic
 whether it runs alone or in a mix (the single-system calls are batches of one),
@@ -25,8 +27,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NbBatchItem, NbError, PRECISIONS
-from .nbody import Context, System
+from ._lib import NbBatchItem, NbError, NbHermite6, PRECISIONS
+from .nbody import Context, Hermite6, System
 
 
 @dataclass
@@ -55,7 +57,7 @@ class Result:
 class _Slot:
     """One resident system: device state, work buffers and its batch item."""
 
-    def __init__(self, req, device, precision, now):
+    def __init__(self, req, device, precision, now, order=4):
         snap = req.snapshot()
         self.req = req
         self.n = snap.n
@@ -75,12 +77,18 @@ class _Slot:
         self.item.eps = float(req.eps)
         self.item.t_end = float(req.t_end)
         self.item.startup = 1
+        if order == 6:
+            self.h6 = Hermite6(self.sys, fp32_copies=(precision != "fp64"))
+            self.snap6 = torch.zeros(3 * n1, dtype=torch.float64, device=device)
         self.result = Result(req.rid, self.n, req.arrival, now, float("nan"))
 
 
-def footprint_bytes(n: int, precision: str = "mixed") -> int:
-    """Device bytes one resident system of n bodies holds (state + work buffers)."""
+def footprint_bytes(n: int, precision: str = "mixed", order: int = 4) -> int:
+    """Device bytes one resident system of n bodies holds (state + work buffers;
+    at 6th order also snap, crackle, predicted acceleration and the snap output)."""
     per_body = 8 * 21 + (16 if precision != "fp64" else 0) + 4 + 48
+    if order == 6:
+        per_body += Hermite6.BYTES_PER_BODY + 24
     return per_body * max(n, 1) + 4 + 1024
 
 
@@ -127,16 +135,23 @@ class Admission:
 class Server:
     """Advance many systems together with ragged batched launches.
 
-    precision: "mixed" or "fp64"; memory_budget: device bytes for resident systems
-    (default 90% of free memory); max_slots: most systems resident at once.
+    precision: "mixed", "ds" or "fp64"; order: 4 or 6 (Hermite order; eta defaults to
+    0.02 or 0.14); memory_budget: device bytes for resident systems (default 90% of
+    free memory); max_slots: most systems resident at once.
     """
 
     def __init__(self, ctx: Context | None = None, precision: str = "mixed",
-                 memory_budget: int | None = None, max_slots: int = 256, eta: float = 0.02,
-                 eta_s: float = 0.01, dt_max: float = 2.0 ** -3, dt_min: float = 2.0 ** -40,
-                 keep_state: bool = False, energy: bool = True):
+                 memory_budget: int | None = None, max_slots: int = 256,
+                 eta: float | None = None, eta_s: float = 0.01, dt_max: float = 2.0 ** -3,
+                 dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
+                 order: int = 4):
         if precision not in PRECISIONS:
             raise ValueError(precision)
+        if order not in (4, 6):
+            raise ValueError("order must be 4 or 6")
+        self.order = order
+        if eta is None:
+            eta = 0.14 if order == 6 else 0.02
         self.ctx = ctx if ctx is not None else Context(0)
         self.L = _lib.load()
         self.precision = precision
@@ -146,7 +161,7 @@ class Server:
             free, _ = torch.cuda.mem_get_info(self.ctx.device)
             memory_budget = int(0.9 * free)
         self.adm = Admission(memory_budget, max_slots,
-                             lambda r: footprint_bytes(r.n, self.precision))
+                             lambda r: footprint_bytes(r.n, self.precision, self.order))
         self.eta, self.eta_s, self.dt_max, self.dt_min = eta, eta_s, dt_max, dt_min
         self.keep_state = keep_state
         self.energy = energy
@@ -189,7 +204,7 @@ class Server:
             req = self.adm.admit_next()
             if req is None:
                 return
-            slot = _Slot(req, self.device, self.precision, self._now())
+            slot = _Slot(req, self.device, self.precision, self._now(), self.order)
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
             self._sync_items()
@@ -234,6 +249,9 @@ class Server:
     def _build_items(self):
         k = len(self.slots)
         self._arr = (NbBatchItem * k)(*[sl.item for sl in self.slots])
+        if self.order == 6:
+            self._h6 = (NbHermite6 * k)(*[sl.h6._struct for sl in self.slots])
+            self._snaps = (C.c_void_p * k)(*[sl.snap6.data_ptr() for sl in self.slots])
         raw = (C.c_char * C.sizeof(self._arr)).from_address(C.addressof(self._arr))
         self._view = np.frombuffer(raw, dtype=self._DTYPE)
         self._n = np.array([sl.n for sl in self.slots], dtype=np.int64)
@@ -253,12 +271,19 @@ class Server:
             self._build_items()
         v = self._view
         startup = v["startup"] != 0          # before the call, which clears it
-        self._check(self.L.nb_step_batch(self.ctx.h, self._arr, len(self.slots), self.prec_code,
-                                         self.eta, self.eta_s, self.dt_max, self.dt_min))
+        if self.order == 6:
+            self._check(self.L.nb_step6_batch(self.ctx.h, self._arr, self._h6, self._snaps,
+                                              len(self.slots), self.prec_code, self.eta,
+                                              self.eta_s, self.dt_max, self.dt_min))
+        else:
+            self._check(self.L.nb_step_batch(self.ctx.h, self._arr, len(self.slots),
+                                             self.prec_code, self.eta, self.eta_s, self.dt_max,
+                                             self.dt_min))
         err, done = v["error"], v["done"]
         ran = (err == 0) & (done == 0)
         n = self._n
-        inc = np.where(startup, n * n, v["m"].astype(np.int64) * n)
+        passes = 2 if self.order == 6 else 1        # force passes of a startup step
+        inc = np.where(startup, passes * n * n, v["m"].astype(np.int64) * n)
         self._inter[ran] += inc[ran]
         self._steps[ran & ~startup] += 1
         self.iterations += 1

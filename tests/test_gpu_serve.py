@@ -116,3 +116,25 @@ def test_poisson_stream_latency_and_throughput(ctx):
     assert 0 < s["latency_p50_s"] <= s["latency_p99_s"]
     assert s["energy_error_max"] < 1e-4
     assert all(r.admitted >= r.arrival - 1e-9 for r in res)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_sixth_order_served_equals_integrator6_alone_and_in_a_mix(ctx, precision):
+    """nb_step6_batch: a system served at 6th order in a mix (admitted and retired
+    around it) gets the same bits as the single-system 6th-order integrator."""
+    from paper_1411_5234_amd.nbody import Integrator6, Params6, System
+    target = _req(0, 600, 51, t_end=0.25)
+    mix = [_req(1, 300, 52), target, _req(2, 1200, 53, t_end=0.125), _req(3, 256, 54),
+           _req(4, 800, 55, t_end=0.5)]
+    served, _ = _serve(ctx, mix, precision, max_slots=3, order=6)
+    assert all(r.error is None for r in served.values())
+    snap = target.snapshot()
+    sys_ = System.from_arrays(snap.x, snap.v, snap.m, fp32_copies=(precision != "fp64"))
+    it = Integrator6(ctx, sys_, Params6(eps=target.eps, precision=precision))
+    it.startup()
+    steps, inter = it.run(target.t_end)
+    st = sys_.state_numpy()
+    for f in FIELDS:
+        assert st[f].tobytes() == served[0].final[f].tobytes(), f
+    assert served[0].steps == steps and served[0].interactions == inter
+    assert served[0].energy_error < 1e-6
