@@ -497,12 +497,13 @@ void sel_shape(int64_t n, int32_t *blocks_out, int64_t *slice_out)
 
 // Device selection for `items` (each with s, i_idx and status set; every item
 // has n >= 1); fills res (host copy, one SelResult per item).  Waits for the stream.
-// predict: after the results are copied out, every item is also predicted to its
-// t_next unless that is past the item's t_next field (its horizon); the host
-// waits only for the copy, so the prediction runs while it reads the results
-// and prepares the next launches.
+// predict (4 or 6, 0 for none): after the results are copied out, every item is
+// also predicted (by that order's predictor; 6 needs the items' h6) to its t_next
+// unless that is past the item's t_next field (its horizon); the host waits only
+// for the copy, so the prediction runs while it reads the results and prepares
+// the next launches.
 nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResult> &res,
-                     bool predict = false)
+                     int predict = 0)
 {
     res.assign(items.size(), SelResult{INFINITY, 0, 0});
     if (items.empty()) return NB_OK;
@@ -539,7 +540,8 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
                                hipMemcpyDeviceToHost, ctx->stream));
     if (predict) {
         NB_HIP(ctx, hipEventRecord(ctx->sel_done, ctx->stream));
-        e = nbk::launch_predict(tp, dres, ctx->stream);
+        e = predict == 6 ? nbk::launch_predict6(tp, dres, ctx->stream)
+                         : nbk::launch_predict(tp, dres, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
         NB_HIP(ctx, hipEventSynchronize(ctx->sel_done));
     } else {
@@ -585,9 +587,11 @@ Item batch_item(nb_ctx *ctx, const nb_batch_item &b)
 }
 
 // a1 for every item (see nb_select_active_batch).
-// predict: non-startup items are also predicted to their t_next unless it is past
-// their t_end (see run_select).
-nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items, bool predict = false)
+// predict (4 or 6, 0 for none): non-startup items are also predicted to their
+// t_next unless it is past their t_end (see run_select); 6 takes item k's
+// 6th-order arrays from h6s[k].
+nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items, int predict = 0,
+                       const nb_hermite6 *h6s = nullptr)
 {
     std::vector<Item> dev;
     std::vector<int32_t> which;
@@ -609,6 +613,7 @@ nb_status select_items(nb_ctx *ctx, nb_batch_item *items, int32_t n_items, bool 
         if (items[k].status) it.status = items[k].status;
         it.i_idx = items[k].i_idx;
         it.t_next = items[k].startup ? -INFINITY : items[k].t_end;   // prediction horizon
+        if (h6s) it.h6 = h6s[k];
         dev.push_back(it);
         which.push_back(k);
     }
@@ -686,7 +691,7 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
 nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermite6 *h6s,
                          double *const *snaps, int32_t n_items, const std::vector<char> &run,
                          nb_precision precision, double eta, double eta_s, double dt_max,
-                         double dt_min)
+                         double dt_min, bool predicted = false)
 {
     std::vector<Item> ini4, pred6, cor6, ini6;
     std::vector<int64_t> bi4, bp6, bc6, bi6;
@@ -704,8 +709,10 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
             it.t_next = 0.0;
         }
         it.snap = snaps[k];
-        pred6.push_back(it);
-        bp6.push_back(nb);
+        if (items[k].startup || !predicted) {
+            pred6.push_back(it);
+            bp6.push_back(nb);
+        }
         jobs6.push_back(ForceJob{it, make_plan(n, it.m, precision)});
         if (items[k].startup) {
             ini6.push_back(it);
@@ -734,7 +741,7 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
     NB_TRY(make_table(ctx, cor6, bc6, &tc, &st));
     NB_TRY(make_table(ctx, ini6, bi6, &ti, &st));
     NB_TRY(flush(ctx, &st));
-    hipError_t e = nbk::launch_predict6(tp, ctx->stream);
+    hipError_t e = nbk::launch_predict6(tp, nullptr, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "predict6 launch");
     NB_TRY(launch_force(ctx, fp, precision));
     e = nbk::launch_correct6(tc, eta, dt_max, dt_min, ctx->stream);
@@ -1042,7 +1049,7 @@ nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,
         return fail(ctx, NB_EINVAL, "unknown precision");
     NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
     if (!(eta_s > 0.0)) return fail(ctx, NB_EINVAL, "eta_s must be > 0");
-    NB_TRY(select_items(ctx, items, n_items, true));
+    NB_TRY(select_items(ctx, items, n_items, 4));
     std::vector<char> run(n_items, 0);
     for (int32_t k = 0; k < n_items; ++k) {
         nb_batch_item &b = items[k];
@@ -1075,7 +1082,7 @@ nb_status nb_predict6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, 
     std::vector<int64_t> blocks{(sys->n + nbk::WG - 1) / nbk::WG};
     Table t;
     NB_TRY(make_table(ctx, items, blocks, &t));
-    hipError_t e = nbk::launch_predict6(t, ctx->stream);
+    hipError_t e = nbk::launch_predict6(t, nullptr, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "predict6 launch");
 }
 
@@ -1155,14 +1162,31 @@ nb_status nb_step6(nb_ctx *ctx, const nb_system *sys, const nb_hermite6 *h6, int
     if (!ctx) return NB_EINVAL;
     if (!done_host) return fail(ctx, NB_EINVAL, "done is NULL");
     *done_host = 0;
+    NB_TRY(check_system(ctx, sys, true));
     NB_TRY(check_h6(ctx, sys, h6));
     NB_TRY(check_step_params(ctx, eta, dt_max, dt_min));
-    NB_TRY(nb_select_active(ctx, sys, t_next_host, i_idx, m_host));
+    if (!t_next_host || !m_host) return fail(ctx, NB_EINVAL, "host outputs are NULL");
+    if (sys->n == 0) {
+        *t_next_host = INFINITY;
+        *m_host = 0;
+        *done_host = 1;
+        return NB_OK;
+    }
+    if (!i_idx) return fail(ctx, NB_EINVAL, "i_idx is NULL");
+    // the selection, with the 6th-order prediction enqueued behind its results
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].i_idx = i_idx;
+    items[0].h6 = *h6;
+    items[0].t_next = t_end;
+    std::vector<SelResult> res;
+    NB_TRY(run_select(ctx, items, res, 6));
+    *t_next_host = res[0].t_next;
+    *m_host = res[0].m;
+    NB_TRY(take_status(ctx, res[0].status));
     if (!(*t_next_host <= t_end)) {
         *done_host = 1;
         return NB_OK;
     }
-    NB_TRY(nb_predict6(ctx, sys, h6, *t_next_host));
     NB_TRY(nb_force6_active(ctx, sys, h6, i_idx, *m_host, 0, sys->n, eps, precision, acc, jerk,
                             snap));
     return nb_correct6(ctx, sys, h6, i_idx, *m_host, acc, jerk, snap, *t_next_host, eta, dt_max,
@@ -1187,7 +1211,7 @@ nb_status nb_step6_batch(nb_ctx *ctx, nb_batch_item *items, const nb_hermite6 *h
         if (precision != NB_FP64 && !h6s[k].axp32)
             return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 accelerations");
     }
-    NB_TRY(select_items(ctx, items, n_items));
+    NB_TRY(select_items(ctx, items, n_items, 6, h6s));
     std::vector<char> run(n_items, 0);
     for (int32_t k = 0; k < n_items; ++k) {
         nb_batch_item &b = items[k];
@@ -1203,7 +1227,7 @@ nb_status nb_step6_batch(nb_ctx *ctx, nb_batch_item *items, const nb_hermite6 *h
         run[k] = 1;
     }
     NB_TRY(advance_items6(ctx, items, h6s, snaps, n_items, run, precision, eta, eta_s, dt_max,
-                          dt_min));
+                          dt_min, true));
     for (int32_t k = 0; k < n_items; ++k)
         if (run[k]) items[k].startup = 0;
     return NB_OK;

@@ -116,7 +116,7 @@ hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_m
                           hipStream_t st);
 hipError_t launch_init_steps(const Table &t, double eta_s, double dt_max, double dt_min,
                              hipStream_t st);
-hipError_t launch_predict6(const Table &t, hipStream_t st);
+hipError_t launch_predict6(const Table &t, const SelResult *sel, hipStream_t st);
 hipError_t launch_correct6(const Table &t, double eta, double dt_max, double dt_min,
                            hipStream_t st);
 hipError_t launch_init_steps6(const Table &t, double eta_s, double dt_max, double dt_min,

@@ -7,18 +7,27 @@
 namespace nbk {
 
 // Every body to the block time: position to the crackle term, velocity and
-// acceleration (the acceleration is what the snap of the pair sum needs).
+// acceleration (the acceleration is what the snap of the pair sum needs).  The
+// block time is the item's t_next, or, with sel (the device selection results of
+// the same items), sel[k].t_next when that is not past the item's t_next field
+// (then its horizon), as in the 4th-order predictor.
 __global__ __launch_bounds__(WG) void predict6_kernel(const Item *items, const int64_t *starts,
-                                                      int n_items)
+                                                      int n_items, const SelResult *sel)
 {
     const int k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[k];
     const int64_t i = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
     const nb_system &s = p.s;
     const nb_hermite6 &h = p.h6;
+    double tn = p.t_next;
+    if (sel) {
+        tn = sel[k].t_next;
+        if (!(tn <= p.t_next))
+            return;
+    }
     if (i >= s.n)
         return;
-    const double d = p.t_next - s.t[i];
+    const double d = tn - s.t[i];
     // Taylor coefficients d^n / n!
     const double c2 = d * d * 0.5, c3 = c2 * d * (1.0 / 3.0), c4 = c3 * d * 0.25,
                  c5 = c4 * d * 0.2;
@@ -43,11 +52,11 @@ __global__ __launch_bounds__(WG) void predict6_kernel(const Item *items, const i
         s.m32[i] = (float)s.m[i];
 }
 
-hipError_t launch_predict6(const Table &t, hipStream_t st)
+hipError_t launch_predict6(const Table &t, const SelResult *sel, hipStream_t st)
 {
     if (t.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(predict6_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items,
-                       t.starts, t.n);
+                       t.starts, t.n, sel);
     return hipGetLastError();
 }
 
