@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "launch.h"
 
 #define NB_VERSION "0.5.0"
 

@@ -19,6 +19,7 @@
 // FP32 with the hardware reciprocal square root, accumulates short runs of
 // FP32 terms and folds them into FP64 totals.
 #include "pair.h"
+#include "launch.h"
 
 namespace nbk {
 

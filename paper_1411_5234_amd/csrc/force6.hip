@@ -16,6 +16,7 @@
 //   A = mu r,   J = mu u with u = w - 3 alpha r,
 //   S = mu (b - 6 alpha u - 3 beta r).
 #include "pair.h"
+#include "launch.h"
 
 namespace nbk {
 

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "launch.h"
 
 namespace nbk {
 

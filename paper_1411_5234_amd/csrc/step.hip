@@ -5,6 +5,7 @@
 // table of systems (items): a workgroup finds its item by binary search over
 // the table's workgroup offsets and then works inside that one system.
 #include "nb_internal.h"
+#include "launch.h"
 
 namespace nbk {
 

@@ -3,6 +3,7 @@
 // 4th-order kernels.  All FP64; one thread per body (predictor, startup) or per
 // active body (corrector).
 #include "nb_internal.h"
+#include "launch.h"
 
 namespace nbk {
 
