@@ -256,18 +256,21 @@ struct Plan {
 //  - splits j into B chunks while the grid has fewer than about 2^21 lanes --
 //    eight times the lanes the force kernels keep resident on 256 CUs, so the
 //    last round of workgroups is a small part of the run -- keeping at least
-//    2048 j-bodies per chunk, so the FP64 partial sums (48 B per body and
-//    chunk) stay a few per cent of the pair work;
+//    1024 j-bodies per chunk, so the FP64 partial sums (48 B per body and
+//    chunk) stay a small part of the pair work;
 //  - then raises S while the grid has fewer than about 2^20 lanes and every
-//    lane keeps at least 128 j-bodies (S > 1 turns LDS broadcasts into per-lane
+//    lane keeps at least 32 j-bodies (S > 1 turns LDS broadcasts into per-lane
 //    reads, so it is used less eagerly than the j-split).
+// The two floors were chosen on measured times over N = 2048 ... 2^20 and active
+// blocks of 16 ... N: against floors of 2048 and 128 they cut small blocks of
+// systems up to N = 2^18 by 10-25% and cost nowhere more than about 1%.
 // Large mixed-precision blocks hold two i-bodies per lane (half the LDS reads
 // per interaction).  Pure function of (nj, m, precision): a system's results
 // never depend on what else runs.
 Plan make_plan(int64_t nj, int32_t m, int precision)
 {
     const int64_t target_lanes = (int64_t)1 << 21;
-    const int64_t min_j_lane = 128, min_j_chunk = 2048;
+    const int64_t min_j_lane = 32, min_j_chunk = 1024;
     Plan p{(precision != NB_FP64 && m >= (1 << 16)) ? 2 : 1, 1, 1};
     if (m <= 0 || nj <= 0) return p;
     const int64_t groups = (m + p.il - 1) / p.il;   // lane groups holding distinct i-bodies
