@@ -395,18 +395,21 @@ nb_status launch_force(nb_ctx *ctx, const ForcePlan &fp, int prec)
         for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q)
             NB_HIP(ctx, hipStreamWaitEvent(ctx->side[q], ctx->fork, 0));
     }
-    for (int k = 0; k < nl; ++k) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nl && e == hipSuccess; ++k) {
         const ForceLaunch &l = fp.launches[k];
         hipStream_t st = k == 0 ? ctx->stream : ctx->side[(k - 1) % nb_ctx::NSIDE];
-        hipError_t e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
-                            : nbk::launch_force(prec, l.il, l.s, l.t, st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
+        e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
+                 : nbk::launch_force(prec, l.il, l.s, l.t, st);
     }
+    // Joined even after a failed launch: the staging ring's reuse waits on
+    // `stream` alone, so every side stream's work must sit behind it.
     for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q) {
         NB_HIP(ctx, hipEventRecord(ctx->join[q], ctx->side[q]));
         NB_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join[q], 0));
     }
-    hipError_t e = nbk::launch_reduce(fp.red, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
+    e = nbk::launch_reduce(fp.red, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "partial reduction launch");
 }
 
