@@ -497,6 +497,18 @@ def mode_serve(args):
         t0 = time.perf_counter()
         res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
         out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
+    worst = closed.get("energy_error_worst_request")
+    if worst is not None:
+        # the request with the largest energy error, served alone in FP64 and in the
+        # run's precision: tells the integrator's error from the pair arithmetic's
+        req = [q for q in stream(0.0, args.requests) if q.rid == worst["rid"]]
+        row = dict(worst)
+        for prec in dict.fromkeys(("fp64", args.precision)):
+            srv = Server(ctx, precision=prec, max_slots=1, energy=True, order=args.order)
+            r = srv.run(req, realtime=False)[0]
+            row["energy_error_" + prec] = r.energy_error if r.error is None else r.error
+        out["worst_request_alone"] = row
+        print("worst request alone: %s" % row, file=sys.stderr, flush=True)
     if args.stream == "c5":
         # the same requests in FP64 and in mixed precision: energy error per request
         per = {}

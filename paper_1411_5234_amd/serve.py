@@ -329,8 +329,11 @@ def summarize(results, wall: float) -> dict:
            "wall_s": wall, "solves_per_s": len(ok) / wall if wall > 0 else float("nan"),
            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
            "interactions": int(inter), "interactions_per_s": inter / wall if wall > 0 else float("nan")}
-    errs = [r.energy_error for r in ok if not math.isnan(r.energy1)]
-    if errs:
+    with_e = [r for r in ok if not math.isnan(r.energy1)]
+    if with_e:
+        errs = [r.energy_error for r in with_e]
+        worst = with_e[int(np.argmax(errs))]
         out["energy_error_median"] = float(np.median(errs))
         out["energy_error_max"] = float(np.max(errs))
+        out["energy_error_worst_request"] = {"rid": worst.rid, "n": worst.n}
     return out

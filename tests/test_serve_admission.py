@@ -101,3 +101,19 @@ def test_footprint_covers_the_device_arrays():
     # state rows + FP32 copies + i_idx + acc/jerk (3n doubles each)
     need = 8 * len(FIELDS64) * n + 4 * len(FIELDS32) * n + 4 * n + 2 * 8 * 3 * n
     assert footprint_bytes(n, "mixed") >= need
+
+
+def test_summary_names_the_request_with_the_largest_energy_error():
+    from paper_1411_5234_amd.serve import Result, summarize
+
+    def res(rid, n, e0, e1, t, err=None):
+        return Result(rid=rid, n=n, arrival=0.0, admitted=0.0, finished=t, energy0=e0,
+                      energy1=e1, error=err)
+
+    rs = [res(0, 300, -0.25, -0.25000001, 1.0), res(1, 900, -0.25, -0.2501, 2.0),
+          res(2, 500, -0.25, -0.3, 3.0, err="failed"), res(3, 700, -0.25, -0.25001, 4.0)]
+    s = summarize(rs, wall=4.0)
+    assert s["completed"] == 3 and s["failed"] == 1
+    assert s["energy_error_worst_request"] == {"rid": 1, "n": 900}
+    assert s["energy_error_max"] == pytest.approx(0.0001 / 0.25)
+    assert s["solves_per_s"] == pytest.approx(0.75)
