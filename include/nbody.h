@@ -209,8 +209,8 @@ nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_it
  * the stream), then, for every item without an error whose next block time is
  * not past its t_end, a2 + a3 + a4 + a5 as in the four calls above (startup
  * items: force + startup steps, after which their startup flag is cleared).
- * Here a2 is enqueued right after the selection results' copy and runs while
- * the host reads them, with the same arithmetic as nb_predict_batch.
+ * Here a2 is enqueued right after the selection and runs while the host reads
+ * its results, with the same arithmetic as nb_predict_batch.
  * Items past t_end get done = 1 and no work; items with an error get no work.
  * Host fields t_next, m, error, done and startup are updated in place. */
 nb_status nb_step_batch(nb_ctx *ctx, nb_batch_item *items, int32_t n_items,

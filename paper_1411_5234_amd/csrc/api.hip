@@ -114,10 +114,23 @@ nb_status ensure_res(nb_ctx *ctx, size_t bytes)
     NB_TRY(grow(ctx, &ctx->res, &have, bytes, "selection results"));
     if (ctx->res_host) (void)hipHostFree(ctx->res_host);
     ctx->res_host = nullptr;
-    if (hipHostMalloc(&ctx->res_host, have, hipHostMallocDefault) != hipSuccess) {
+    ctx->res_host_dev = nullptr;
+    ctx->res_bytes = 0;
+    // Coherent and mapped: the status kernel writes the results here directly,
+    // and the host reads them once that kernel has completed (no copy).
+    if (hipHostMalloc(&ctx->res_host, have, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
         (void)hipGetLastError();
-        ctx->res_bytes = 0;
+        ctx->res_host = nullptr;
         return fail(ctx, NB_ENOMEM, "pinned selection results");
+    }
+    if (hipHostGetDevicePointer(&ctx->res_host_dev, ctx->res_host, 0) != hipSuccess ||
+        !ctx->res_host_dev) {
+        (void)hipGetLastError();
+        (void)hipHostFree(ctx->res_host);
+        ctx->res_host = nullptr;
+        ctx->res_host_dev = nullptr;
+        return fail(ctx, NB_EDEVICE, "device address of the pinned selection results");
     }
     ctx->res_bytes = have;
     return NB_OK;
@@ -503,12 +516,13 @@ void sel_shape(int64_t n, int32_t *blocks_out, int64_t *slice_out)
 }
 
 // Device selection for `items` (each with s, i_idx and status set; every item
-// has n >= 1); fills res (host copy, one SelResult per item).  Waits for the stream.
-// predict (4 or 6, 0 for none): after the results are copied out, every item is
-// also predicted (by that order's predictor; 6 needs the items' h6) to its t_next
+// has n >= 1); fills res (one SelResult per item, which the status kernel writes
+// into the mapped pinned buffer).  Waits for the stream.
+// predict (4 or 6, 0 for none): after the status kernel, every item is also
+// predicted (by that order's predictor; 6 needs the items' h6) to its t_next
 // unless that is past the item's t_next field (its horizon); the host waits only
-// for the copy, so the prediction runs while it reads the results and prepares
-// the next launches.
+// for the status kernel, so the prediction runs while it reads the results and
+// prepares the next launches.
 nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResult> &res,
                      int predict = 0)
 {
@@ -541,10 +555,9 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
     if (t.n != (int)items.size()) return fail(ctx, NB_EINVAL, "selection of an empty system");
     hipError_t e = nbk::launch_select(t, blockval, blockcnt, dres, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "selection launch");
-    e = nbk::launch_collect_status(t.items, t.n, dres, ctx->stream);
+    e = nbk::launch_collect_status(t.items, t.n, dres, (SelResult *)ctx->res_host_dev,
+                                   ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "status collection launch");
-    NB_HIP(ctx, hipMemcpyAsync(ctx->res_host, dres, items.size() * sizeof(SelResult),
-                               hipMemcpyDeviceToHost, ctx->stream));
     if (predict) {
         NB_HIP(ctx, hipEventRecord(ctx->sel_done, ctx->stream));
         e = predict == 6 ? nbk::launch_predict6(tp, dres, ctx->stream)

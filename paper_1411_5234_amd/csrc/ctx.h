@@ -22,7 +22,8 @@ struct nb_ctx {
     void *selbuf = nullptr;           // device: selection per-workgroup temporaries (grows)
     size_t selbuf_bytes = 0;
     void *res = nullptr;              // device: per-item selection results (grows)
-    void *res_host = nullptr;         // pinned mirror of res
+    void *res_host = nullptr;         // pinned, mapped: the results as the host reads them
+    void *res_host_dev = nullptr;     // device address of res_host
     size_t res_bytes = 0;
     char *stage_host = nullptr;       // pinned ring for item tables
     char *stage_dev = nullptr;        // device ring mirrored by stage_host
@@ -35,7 +36,7 @@ struct nb_ctx {
     hipStream_t side[NSIDE] = {};
     hipEvent_t fork = nullptr, join[NSIDE] = {};
     bool side_ready = false;
-    // Recorded after the selection results' copy when a prediction follows it.
+    // Recorded after the selection's status kernel when a prediction follows it.
     hipEvent_t sel_done = nullptr;
     // Host thread for pair advances (started on first use): a FIFO of jobs run in
     // call order; result is the first failure since the last wait.

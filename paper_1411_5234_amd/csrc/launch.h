@@ -20,11 +20,13 @@ hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *
 
 // Tidal tensors of the listed bodies, one workgroup per body, rows (3a+b)*m + k.
 hipError_t launch_tidal(const Table &t, double *T, hipStream_t st);
-// Selection: three passes over per-item workgroup slices, then per-item results.
+// Selection: two passes over per-item workgroup slices, then per-item results.
 hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
                          hipStream_t st);
-// Copy each item's status word into res[k].status, then clear the words.
-hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipStream_t st);
+// Copy each item's status word into res[k].status, then clear the words; host
+// (mapped pinned memory, or null) also receives every item's whole result.
+hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,
+                                 hipStream_t st);
 // sel: null, or the device selection results of the same items (see predict_kernel).
 hipError_t launch_predict(const Table &t, const SelResult *sel, hipStream_t st);
 hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_min,

@@ -33,14 +33,29 @@ __device__ __forceinline__ void predict_body(const nb_system &s, int64_t i, doub
 
 // ---- selection ---------------------------------------------------------------
 // Per item, the bodies are cut into sel_blocks contiguous slices of sel_slice.
-// Pass 1: each workgroup takes the minimum of t + dt over its slice.
+// Pass 1: each workgroup takes the minimum of t + dt over its slice and counts
+//         the slice's bodies at that minimum.
 // Pass 2: each workgroup reduces its item's slice minima to t_next (the same
-//         arithmetic in every workgroup of the item) and counts its bodies due
-//         at t_next; the item's first workgroup stores t_next.
-// Pass 3: each workgroup adds the counts of the item's earlier slices and writes
-//         its due bodies' indices in ascending order (ordered compaction with a
-//         wave ballot and an LDS prefix over the four waves); the item's last
-//         workgroup stores m.
+//         arithmetic in every workgroup of the item), adds the counts of the
+//         item's earlier slices whose minimum is t_next, and writes its due
+//         bodies' indices in ascending order (ordered compaction with a wave
+//         ballot and an LDS prefix over the four waves); the item's first
+//         workgroup stores t_next, its last stores m.
+// A slice whose minimum is above t_next holds no due body, and one whose minimum
+// is t_next holds exactly its counted ones, so the offsets are those of the full
+// ordered list.
+
+// (minimum, count at the minimum) of two partial results.  A NaN never becomes
+// the minimum and is never counted, as with fmin and ==.
+__device__ __forceinline__ void min_count(double &v, int &c, double v2, int c2)
+{
+    if (v2 < v) {
+        v = v2;
+        c = c2;
+    } else if (v2 == v) {
+        c += c2;
+    }
+}
 
 __device__ double wg_min(double v, double *lds)
 {
@@ -69,28 +84,49 @@ __device__ int wg_sum_int(int v, int *lds)
 }
 
 __global__ __launch_bounds__(WG) void select_min_kernel(const Item *items, const int64_t *starts,
-                                                        int n_items, double *blockval)
+                                                        int n_items, double *blockval,
+                                                        int32_t *blockcnt)
 {
-    __shared__ double lds[WG / 64];
+    __shared__ double ldv[WG / 64];
+    __shared__ int ldc[WG / 64];
     const int k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[k];
     const int64_t lb = (int64_t)blockIdx.x - starts[k];
     const int64_t b0 = lb * p.sel_slice;
     const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
     double v = INFINITY;
+    int c = 0;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += WG)
-        v = fmin(v, p.s.t[i] + p.s.dt[i]);
-    v = wg_min(v, lds);
-    if (threadIdx.x == 0)
+        min_count(v, c, p.s.t[i] + p.s.dt[i], 1);
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double v2 = __shfl_xor(v, off, 64);
+        const int c2 = __shfl_xor(c, off, 64);
+        min_count(v, c, v2, c2);
+    }
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) {
+        ldv[w] = v;
+        ldc[w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = ldv[0];
+        c = ldc[0];
+        for (int q = 1; q < WG / 64; ++q) min_count(v, c, ldv[q], ldc[q]);
         blockval[p.sel_off + lb] = v;
+        blockcnt[p.sel_off + lb] = c;
+    }
 }
 
-__global__ __launch_bounds__(WG) void select_count_kernel(const Item *items, const int64_t *starts,
-                                                          int n_items, const double *blockval,
-                                                          int32_t *blockcnt, SelResult *res)
+__global__ __launch_bounds__(WG) void select_scatter_kernel(const Item *items,
+                                                            const int64_t *starts, int n_items,
+                                                            const double *blockval,
+                                                            const int32_t *blockcnt,
+                                                            SelResult *res)
 {
     __shared__ double lds[WG / 64];
     __shared__ int ldi[WG / 64];
+    __shared__ int wave_off[WG / 64];
     const int k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[k];
     const int64_t lb = (int64_t)blockIdx.x - starts[k];
@@ -98,34 +134,12 @@ __global__ __launch_bounds__(WG) void select_count_kernel(const Item *items, con
     for (int q = threadIdx.x; q < p.sel_blocks; q += WG)
         v = fmin(v, blockval[p.sel_off + q]);
     const double tn = wg_min(v, lds);
-    const int64_t b0 = lb * p.sel_slice;
-    const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
-    int c = 0;
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += WG)
-        c += (p.s.t[i] + p.s.dt[i] == tn) ? 1 : 0;
-    c = wg_sum_int(c, ldi);
-    if (threadIdx.x == 0) {
-        blockcnt[p.sel_off + lb] = c;
-        if (lb == 0)
-            res[k].t_next = tn;
-    }
-}
-
-__global__ __launch_bounds__(WG) void select_scatter_kernel(const Item *items,
-                                                            const int64_t *starts, int n_items,
-                                                            const int32_t *blockcnt,
-                                                            SelResult *res)
-{
-    __shared__ int ldi[WG / 64];
-    __shared__ int wave_off[WG / 64];
-    const int k = find_item(starts, n_items, blockIdx.x);
-    const Item &p = items[k];
-    const int64_t lb = (int64_t)blockIdx.x - starts[k];
-    const double tn = res[k].t_next;
     int before = 0;
     for (int q = threadIdx.x; q < (int)lb; q += WG)
-        before += blockcnt[p.sel_off + q];
+        before += blockval[p.sel_off + q] == tn ? blockcnt[p.sel_off + q] : 0;
     int base = wg_sum_int(before, ldi);
+    if (lb == 0 && threadIdx.x == 0)
+        res[k].t_next = tn;
     const int64_t b0 = lb * p.sel_slice;
     const int64_t b1 = min(b0 + p.sel_slice, p.s.n);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
@@ -155,33 +169,38 @@ hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, Se
 {
     if (t.blocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)t.blocks);
-    hipLaunchKernelGGL(select_min_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n, blockval);
+    hipLaunchKernelGGL(select_min_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n, blockval,
+                       blockcnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(select_count_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n,
-                       (const double *)blockval, blockcnt, res);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(select_scatter_kernel, grid, dim3(WG), 0, st, t.items, t.starts, t.n,
-                       (const int32_t *)blockcnt, res);
+                       (const double *)blockval, (const int32_t *)blockcnt, res);
     return hipGetLastError();
 }
 
-// One workgroup: read every item's status word, then clear the words (several
+// One workgroup: read every item's status word into res[k].status and, when
+// `host` is set, write each item's whole result there (mapped pinned memory that
+// the host reads once this kernel has completed); then clear the words (several
 // items may share one word, so all reads finish before any clear).
-__global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, int n, SelResult *res)
+__global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, int n, SelResult *res,
+                                                            SelResult *host)
 {
-    for (int k = threadIdx.x; k < n; k += WG)
-        res[k].status = *items[k].status;
+    for (int k = threadIdx.x; k < n; k += WG) {
+        SelResult r = res[k];
+        r.status = *items[k].status;
+        res[k].status = r.status;
+        if (host) host[k] = r;
+    }
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += WG)
         *items[k].status = 0;
 }
 
-hipError_t launch_collect_status(const Item *items, int n, SelResult *res, hipStream_t st)
+hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,
+                                 hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(collect_status_kernel, dim3(1), dim3(WG), 0, st, items, n, res);
+    hipLaunchKernelGGL(collect_status_kernel, dim3(1), dim3(WG), 0, st, items, n, res, host);
     return hipGetLastError();
 }
 
