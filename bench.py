@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--baseline-requests", type=int, default=32)
+    ap.add_argument("--closed-only", action="store_true",
+                    help="serve mode: the closed batch alone (no Poisson replay, baselines "
+                         "or reruns), e.g. for a kernel trace")
     return ap.parse_args()
 
 
@@ -475,6 +478,12 @@ def mode_serve(args):
     closed = summarize(res, time.perf_counter() - t0)
     out["closed_batch"] = closed
     print("closed batch: %s" % closed, file=sys.stderr, flush=True)
+    if args.closed_only:
+        ctx.close()
+        out["value"] = closed["solves_per_s"]
+        out["unit"] = "solves/s"
+        print(json.dumps(out), flush=True)
+        return
     rate = 0.8 * closed["solves_per_s"]
     srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
     t0 = time.perf_counter()
