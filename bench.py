@@ -85,6 +85,10 @@ def parse():
     ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--baseline-requests", type=int, default=32)
+    ap.add_argument("--lanes", type=int, default=1 << 18,
+                    help="serve mode: force-plan lane target of every batched system "
+                         "(0: the library default, sized for one system alone; 2^18 was "
+                         "the fastest of 2^17 ... 2^21 on the C4 stream)")
     ap.add_argument("--closed-only", action="store_true",
                     help="serve mode: the closed batch alone (no Poisson replay, baselines "
                          "or reruns), e.g. for a kernel trace")
@@ -470,9 +474,10 @@ def mode_serve(args):
 
     out = {"metric": "ensemble solves/s and p50/p99 latency", "mode": "serve",
            "config": {"workload": args.stream, "requests": args.requests, "slots": args.slots,
-                      "precision": args.precision, "order": args.order,
+                      "precision": args.precision, "order": args.order, "lanes": args.lanes,
                       **{k: v for k, v in spec.items() if k != "base"}}}
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
+                     lanes=args.lanes)
     t0 = time.perf_counter()
     res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
     closed = summarize(res, time.perf_counter() - t0)
@@ -485,7 +490,8 @@ def mode_serve(args):
         print(json.dumps(out), flush=True)
         return
     rate = 0.8 * closed["solves_per_s"]
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
+    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
+                     lanes=args.lanes)
     t0 = time.perf_counter()
     res = srv.run(stream(rate, args.requests), realtime=True, on_iteration=progress)
     poisson = summarize(res, time.perf_counter() - t0)
@@ -502,7 +508,8 @@ def mode_serve(args):
         out["one_at_a_time_fp64"] = base
         print("one at a time fp64: %s" % base, file=sys.stderr, flush=True)
         # the same k requests through the batched server, for a like-for-like rate
-        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order)
+        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
+                     lanes=args.lanes)
         t0 = time.perf_counter()
         res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
         out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
@@ -513,7 +520,8 @@ def mode_serve(args):
         req = [q for q in stream(0.0, args.requests) if q.rid == worst["rid"]]
         row = dict(worst)
         for prec in dict.fromkeys(("fp64", args.precision)):
-            srv = Server(ctx, precision=prec, max_slots=1, energy=True, order=args.order)
+            srv = Server(ctx, precision=prec, max_slots=1, energy=True, order=args.order,
+                         lanes=args.lanes)
             r = srv.run(req, realtime=False)[0]
             row["energy_error_" + prec] = r.energy_error if r.error is None else r.error
         out["worst_request_alone"] = row
@@ -522,7 +530,8 @@ def mode_serve(args):
         # the same requests in FP64 and in mixed precision: energy error per request
         per = {}
         for prec in ("fp64", "mixed"):
-            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, order=args.order)
+            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, order=args.order,
+                         lanes=args.lanes)
             res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
             per[prec] = {r.rid: r for r in res}
         rows = []

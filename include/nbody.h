@@ -157,6 +157,17 @@ nb_status nb_energy(nb_ctx *ctx, const nb_system *sys, double eps,
 void nb_force_plan(int64_t nj, int32_t m, nb_precision precision,
                    int32_t *i_per_lane, int32_t *lanes_per_i, int32_t *j_chunks);
 
+/* The same plan for a given lane target: the plan splits the work until about
+ * `lanes` lanes are busy (0 = the default, NB_PLAN_LANES, which lets one system
+ * fill the GPU).  Batch items carry their own target (nb_batch_item.lanes).
+ * Returns NB_EINVAL (and leaves the outputs alone) unless lanes is 0 or in
+ * [NB_PLAN_LANES_MIN, NB_PLAN_LANES_MAX]. */
+#define NB_PLAN_LANES ((int64_t)1 << 21)
+#define NB_PLAN_LANES_MIN ((int64_t)1 << 10)
+#define NB_PLAN_LANES_MAX ((int64_t)1 << 24)
+nb_status nb_force_plan_lanes(int64_t nj, int32_t m, nb_precision precision, int64_t lanes,
+                              int32_t *i_per_lane, int32_t *lanes_per_i, int32_t *j_chunks);
+
 /* Same as nb_force_active but with an explicit plan (for tests and tuning);
  * i_per_lane in {1, 2, 4}, lanes_per_i in {1, 4, 16, 64}, j_chunks >= 1. */
 nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
@@ -169,10 +180,10 @@ nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t 
  * Ensemble serving advances many systems of different n together.  Each batch
  * call runs ONE launch per phase (per plan shape for the force) over all items,
  * with every workgroup working for exactly one item.  Each item is computed
- * with the same kernels, the same launch plan (a pure function of its own n and
- * m) and the same arithmetic as the single-system calls above, which are
- * themselves batches of one, so a system's results are bitwise the same alone
- * and in any mix.  The block-step parameters (eta, eta_s, dt_max, dt_min) are
+ * with the same kernels, the same launch plan (a pure function of its own n, m
+ * and lane target) and the same arithmetic as the single-system calls above,
+ * which are themselves batches of one, so a system's results are bitwise the
+ * same alone and in any mix.  The block-step parameters (eta, eta_s, dt_max, dt_min) are
  * shared by the items of a call.  An item whose status word is non-NULL gets its
  * own kernel error bits there (device int, owned by the caller); otherwise the
  * context's word is used. */
@@ -189,6 +200,9 @@ typedef struct {
     int32_t error;       /* host: nb_status of this item's latched errors, set by
                             nb_select_active_batch (the item's word is then cleared) */
     int32_t done;        /* host: set to 1 by nb_step_batch when t_next > t_end      */
+    int64_t lanes;       /* force plan lane target (see nb_force_plan_lanes); 0 = the
+                            default.  A server whose systems fill the GPU together can
+                            give each fewer lanes than one system alone would take. */
 } nb_batch_item;
 
 /* a1 for every item (Sec. 2 item 2).  Startup items get m = n, t_next = 0 and no

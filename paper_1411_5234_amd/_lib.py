@@ -30,7 +30,7 @@ STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
 # Every symbol include/nbody.h declares.
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
-           "nb_force_plan", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
+           "nb_force_plan", "nb_force_plan_lanes", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
            "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
            "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
@@ -49,7 +49,8 @@ class NbBatchItem(C.Structure):
     _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("acc", C.c_void_p),
                 ("jerk", C.c_void_p), ("status", C.c_void_p), ("eps", C.c_double),
                 ("t_next", C.c_double), ("t_end", C.c_double), ("m", C.c_int32),
-                ("startup", C.c_int32), ("error", C.c_int32), ("done", C.c_int32)]
+                ("startup", C.c_int32), ("error", C.c_int32), ("done", C.c_int32),
+                ("lanes", C.c_int64)]
 
 
 class NbError(RuntimeError):
@@ -85,6 +86,8 @@ def load() -> C.CDLL:
         "nb_force_active_plan": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, i32, i32, i32,
                                            vp, vp]),
         "nb_force_plan": (None, [i64, i32, C.c_int, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "nb_force_plan_lanes": (C.c_int, [i64, i32, C.c_int, i64, C.POINTER(i32), C.POINTER(i32),
+                                          C.POINTER(i32)]),
         "nb_init_steps": (C.c_int, [vp, ps, vp, vp, f64, f64, f64]),
         "nb_correct": (C.c_int, [vp, ps, vp, i32, vp, vp, f64, f64, f64, f64]),
         "nb_energy": (C.c_int, [vp, ps, f64, C.POINTER(f64), C.POINTER(f64)]),
@@ -118,8 +121,17 @@ def load() -> C.CDLL:
     return L
 
 
-def force_plan(nj: int, m: int, precision: str = "mixed"):
+def force_plan(nj: int, m: int, precision: str = "mixed", lanes: int | None = None):
+    """(i-bodies per lane, lanes per i-body, j-chunks) of the force launch; lanes:
+    the plan's lane target (None: nb_force_plan; 0: the default target)."""
     L = load()
     a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-    L.nb_force_plan(int(nj), int(m), PRECISIONS[precision], C.byref(a), C.byref(b), C.byref(c))
+    if lanes is None:
+        L.nb_force_plan(int(nj), int(m), PRECISIONS[precision], C.byref(a), C.byref(b),
+                        C.byref(c))
+    else:
+        rc = L.nb_force_plan_lanes(int(nj), int(m), PRECISIONS[precision], int(lanes),
+                                   C.byref(a), C.byref(b), C.byref(c))
+        if rc != 0:
+            raise NbError(rc, "lane target %d out of range" % lanes)
     return a.value, b.value, c.value

@@ -278,11 +278,13 @@ struct Plan {
 // blocks of 16 ... N: against floors of 2048 and 128 they cut small blocks of
 // systems up to N = 2^18 by 10-25% and cost nowhere more than about 1%.
 // Large mixed-precision blocks hold two i-bodies per lane (half the LDS reads
-// per interaction).  Pure function of (nj, m, precision): a system's results
-// never depend on what else runs.
-Plan make_plan(int64_t nj, int32_t m, int precision)
+// per interaction).  Pure function of (nj, m, precision, lane target): a
+// system's results never depend on what else runs.  The default target lets
+// one system fill the GPU; a batch of many systems fills it together and may
+// give each a smaller target (fewer, longer lanes).
+Plan make_plan(int64_t nj, int32_t m, int precision, int64_t lanes = 0)
 {
-    const int64_t target_lanes = (int64_t)1 << 21;
+    const int64_t target_lanes = lanes > 0 ? lanes : NB_PLAN_LANES;
     const int64_t min_j_lane = 32, min_j_chunk = 1024;
     Plan p{(precision != NB_FP64 && m >= (1 << 16)) ? 2 : 1, 1, 1};
     if (m <= 0 || nj <= 0) return p;
@@ -583,6 +585,8 @@ nb_status check_item(nb_ctx *ctx, const nb_batch_item &b, bool need_m)
         return fail(ctx, NB_EINVAL, "item m out of range");
     if (need_m && !b.startup && !isfinite(b.t_next))
         return fail(ctx, NB_EINVAL, "item t_next must be finite");
+    if (b.lanes != 0 && (b.lanes < NB_PLAN_LANES_MIN || b.lanes > NB_PLAN_LANES_MAX))
+        return fail(ctx, NB_EINVAL, "item lane target out of range");
     return NB_OK;
 }
 
@@ -680,7 +684,7 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
         }
         ForceJob job;
         job.it = it;
-        job.plan = make_plan(items[k].sys.n, it.m, precision);
+        job.plan = make_plan(items[k].sys.n, it.m, precision, items[k].lanes);
         jobs.push_back(job);
     }
     // every table of the iteration in one upload
@@ -725,7 +729,7 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
         if (items[k].startup) {
             ini4.push_back(it);
             bi4.push_back(nb);
-            jobs4.push_back(ForceJob{it, make_plan(n, (int32_t)n, precision)});
+            jobs4.push_back(ForceJob{it, make_plan(n, (int32_t)n, precision, items[k].lanes)});
             it.t_next = 0.0;
         }
         it.snap = snaps[k];
@@ -733,7 +737,7 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
             pred6.push_back(it);
             bp6.push_back(nb);
         }
-        jobs6.push_back(ForceJob{it, make_plan(n, it.m, precision)});
+        jobs6.push_back(ForceJob{it, make_plan(n, it.m, precision, items[k].lanes)});
         if (items[k].startup) {
             ini6.push_back(it);
             bi6.push_back(nb);
@@ -917,6 +921,17 @@ void nb_force_plan(int64_t nj, int32_t m, nb_precision precision, int32_t *i_per
     if (j_chunks) *j_chunks = p.b;
 }
 
+nb_status nb_force_plan_lanes(int64_t nj, int32_t m, nb_precision precision, int64_t lanes,
+                              int32_t *i_per_lane, int32_t *lanes_per_i, int32_t *j_chunks)
+{
+    if (lanes != 0 && (lanes < NB_PLAN_LANES_MIN || lanes > NB_PLAN_LANES_MAX)) return NB_EINVAL;
+    Plan p = make_plan(nj, m, precision, lanes);
+    if (i_per_lane) *i_per_lane = p.il;
+    if (lanes_per_i) *lanes_per_i = p.s;
+    if (j_chunks) *j_chunks = p.b;
+    return NB_OK;
+}
+
 nb_status nb_init_steps(nb_ctx *ctx, const nb_system *sys, const double *acc,
                         const double *jerk, double eta_s, double dt_max, double dt_min)
 {
@@ -1023,7 +1038,7 @@ nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t
             return fail(ctx, NB_EINVAL, "mixed and DS precision need the FP32 copies");
         ForceJob job;
         job.it = batch_item(ctx, items[k]);
-        job.plan = make_plan(items[k].sys.n, job.it.m, precision);
+        job.plan = make_plan(items[k].sys.n, job.it.m, precision, items[k].lanes);
         jobs.push_back(job);
     }
     return run_force(ctx, jobs, precision);

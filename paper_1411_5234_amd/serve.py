@@ -137,19 +137,25 @@ class Server:
 
     precision: "mixed", "ds" or "fp64"; order: 4 or 6 (Hermite order; eta defaults to
     0.02 or 0.14); memory_budget: device bytes for resident systems (default 90% of
-    free memory); max_slots: most systems resident at once.
+    free memory); max_slots: most systems resident at once; lanes: the force plan's
+    lane target for every served system (0: the default, with which one system alone
+    fills the GPU; a batch fills it together, so a smaller target trades the
+    splitting of each system's work for longer lanes).  A system's results depend
+    on its own sizes and this setting only, never on the other systems.
     """
 
     def __init__(self, ctx: Context | None = None, precision: str = "mixed",
                  memory_budget: int | None = None, max_slots: int = 256,
                  eta: float | None = None, eta_s: float = 0.01, dt_max: float = 2.0 ** -3,
                  dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
-                 order: int = 4):
+                 order: int = 4, lanes: int = 0):
         if precision not in PRECISIONS:
             raise ValueError(precision)
         if order not in (4, 6):
             raise ValueError("order must be 4 or 6")
         self.order = order
+        _lib.force_plan(1, 1, "mixed", lanes)     # raises on a target out of range
+        self.lanes = int(lanes)
         if eta is None:
             eta = 0.14 if order == 6 else 0.02
         self.ctx = ctx if ctx is not None else Context(0)
@@ -205,6 +211,7 @@ class Server:
             if req is None:
                 return
             slot = _Slot(req, self.device, self.precision, self._now(), self.order)
+            slot.item.lanes = self.lanes
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
             self._sync_items()

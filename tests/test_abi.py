@@ -62,6 +62,38 @@ def test_force_plan_is_pure_and_valid():
     assert s * b > 1
 
 
+def test_force_plan_lane_target():
+    """The plan's lane target: 0 and the default give nb_force_plan's plan; a smaller
+    target never takes more lanes (i-groups x lanes per i-body x j-chunks); targets
+    outside the documented range are refused."""
+    from paper_1411_5234_amd import _lib
+    default = 1 << 21
+    for prec in ("fp64", "mixed"):
+        for nj in (1, 300, 4096, 32768, 1 << 20):
+            for m in (1, 5, 20, 100, 1000, 4096, 1 << 20):
+                if m > nj:
+                    continue
+                base = _lib.force_plan(nj, m, prec)
+                assert _lib.force_plan(nj, m, prec, 0) == base
+                assert _lib.force_plan(nj, m, prec, default) == base
+                prev = None
+                for lanes in (1 << 24, default, 1 << 18, 1 << 14, 1 << 10):
+                    il, s, b = _lib.force_plan(nj, m, prec, lanes)
+                    assert il in (1, 2, 4) and s in (1, 4, 16, 64) and 1 <= b <= 1024
+                    used = -(-m // il) * s * b
+                    if prev is not None:
+                        assert used <= prev
+                    prev = used
+    # a small block of a mid-sized system: the default splits it far more than a
+    # target sized for a batch of systems does
+    il, s, b = _lib.force_plan(32768, 100, "mixed")
+    il2, s2, b2 = _lib.force_plan(32768, 100, "mixed", 1 << 14)
+    assert s * b > s2 * b2
+    for bad in (-1, 1, (1 << 10) - 1, (1 << 24) + 1):
+        with pytest.raises(_lib.NbError):
+            _lib.force_plan(1024, 10, "mixed", bad)
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     """ctypes mirrors of nb_system / nb_batch_item / nb_hermite6 have the C sizes and offsets."""
     import ctypes

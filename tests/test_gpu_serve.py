@@ -53,6 +53,33 @@ def test_same_result_alone_and_in_a_mix(ctx, precision):
     assert np.all(b["t"] == 0.25)
 
 
+@pytest.mark.parametrize("order", [4, 6])
+def test_lane_target_alone_and_in_a_mix(ctx, order):
+    """A server with a smaller force-plan lane target: plans change (so the test
+    exercises other launch shapes) and a system's result is still bitwise the same
+    alone and in a mix."""
+    from paper_1411_5234_amd import _lib
+    from paper_1411_5234_amd.serve import Server
+    lanes = 1 << 14
+    # the startup step and blocks of 1024 bodies or more get other plans at N = 2048
+    assert _lib.force_plan(2048, 2048, "mixed", lanes) != _lib.force_plan(2048, 2048, "mixed")
+    assert _lib.force_plan(2048, 1024, "mixed", lanes) != _lib.force_plan(2048, 1024, "mixed")
+    target = _req(0, 2048, 11, t_end=0.125)
+    alone, _ = _serve(ctx, [target], "mixed", lanes=lanes, order=order)
+    mix = [_req(1, 300, 12, t_end=0.125), target, _req(2, 1500, 13, t_end=0.125),
+           _req(3, 256, 14, t_end=0.125)]
+    mixed, _ = _serve(ctx, mix, "mixed", max_slots=2, lanes=lanes, order=order)
+    assert all(r.error is None for r in mixed.values())
+    a, b = alone[0].final, mixed[0].final
+    for f in FIELDS:
+        assert a[f].tobytes() == b[f].tobytes(), f
+    assert alone[0].steps == mixed[0].steps
+    assert np.all(b["t"] == 0.125)
+    assert alone[0].energy_error < 1e-5
+    with pytest.raises(_lib.NbError):
+        Server(ctx, lanes=3)
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_served_equals_single_system_integrator(ctx, precision):
     from paper_1411_5234_amd.nbody import Integrator, Params, System
