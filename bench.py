@@ -85,10 +85,11 @@ def parse():
     ap.add_argument("--stream", choices=["c4", "c5"], default="c4")
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--baseline-requests", type=int, default=32)
-    ap.add_argument("--lanes", type=int, default=1 << 18,
+    ap.add_argument("--lanes", type=int, default=None,
                     help="serve mode: force-plan lane target of every batched system "
-                         "(0: the library default, sized for one system alone; 2^18 was "
-                         "the fastest of 2^17 ... 2^21 on the C4 stream)")
+                         "(0: the library default, sized for one system alone; default "
+                         "2^18 at 4th order and 2^16 at 6th, the fastest targets tried on "
+                         "the C4 stream)")
     ap.add_argument("--closed-only", action="store_true",
                     help="serve mode: the closed batch alone (no Poisson replay, baselines "
                          "or reruns), e.g. for a kernel trace")
@@ -450,6 +451,8 @@ def mode_serve(args):
     from paper_1411_5234_amd import inputs
     from paper_1411_5234_amd.nbody import Context
     from paper_1411_5234_amd.serve import Server, summarize
+    if args.lanes is None:
+        args.lanes = 1 << 16 if args.order == 6 else 1 << 18
     if args.stream == "c4":
         spec = dict(n_lo=256, n_hi=32768, eps=1e-3, t_end=1.0, kind="plummer", seed=4, base=4000)
     else:
