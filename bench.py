@@ -88,8 +88,8 @@ def parse():
     ap.add_argument("--lanes", type=int, default=None,
                     help="serve mode: force-plan lane target of every batched system "
                          "(0: the library default, sized for one system alone; default "
-                         "2^18 at 4th order and 2^16 at 6th, the fastest targets tried on "
-                         "the C4 stream)")
+                         "for the C4 stream 2^18 at 4th order and 2^16 at 6th, the fastest "
+                         "targets tried there; 0 for C5)")
     ap.add_argument("--closed-only", action="store_true",
                     help="serve mode: the closed batch alone (no Poisson replay, baselines "
                          "or reruns), e.g. for a kernel trace")
@@ -452,7 +452,10 @@ def mode_serve(args):
     from paper_1411_5234_amd.nbody import Context
     from paper_1411_5234_amd.serve import Server, summarize
     if args.lanes is None:
-        args.lanes = 1 << 16 if args.order == 6 else 1 << 18
+        # measured: with up to 256 C4 systems resident the batch fills the GPU and
+        # shorter splits win; the C5 runs keep few systems resident, where the
+        # default split (one system fills the GPU) was faster
+        args.lanes = 0 if args.stream == "c5" else (1 << 16 if args.order == 6 else 1 << 18)
     if args.stream == "c4":
         spec = dict(n_lo=256, n_hi=32768, eps=1e-3, t_end=1.0, kind="plummer", seed=4, base=4000)
     else:
