@@ -13,7 +13,9 @@ others go on.
 
 Every system is computed with the same kernels, launch plan and arithmetic
 whether it runs alone or in a mix (the single-system calls are batches of one),
-so its result is bitwise the same in both cases.
+so its result is bitwise the same in both cases.  The launch plan depends on the
+system's own sizes and on the server's lane target (the `lanes` argument), never
+on the other systems.
 """
 from __future__ import annotations
 
