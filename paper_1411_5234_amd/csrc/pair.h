@@ -21,13 +21,39 @@ __device__ __forceinline__ double rsqrt64(double s)
     return y;
 }
 
+// v plus the value that DPP control CTRL moves into this lane (within a row of 16
+// lanes; every lane of the wave must be active).  Both 32-bit halves move alike.
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    const unsigned long long q = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    return v + __longlong_as_double((long long)q);
+}
+
+// Sum over the S consecutive lanes of a group (S = 1, 4, 16 or 64), the same value
+// in every lane of the group.  Inside a row the partners come from DPP lane moves
+// (register to register): lanes 2 apart and 1 apart within a quad, then the
+// half-row mirror (the other quad of each 8 lanes) and the row mirror (the other
+// half of each 16); rows are then combined with cross-row shuffles.
 template <int S>
 __device__ __forceinline__ double group_sum(double v)
 {
-    // butterfly over the S consecutive lanes of a group (S divides 64)
-#pragma unroll
-    for (int off = S / 2; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, S);
+    static_assert(S == 1 || S == 4 || S == 16 || S == 64, "group size");
+    if constexpr (S >= 4) {
+        v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
+        v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+    }
+    if constexpr (S >= 16) {
+        v = dpp_add<0x141>(v);   // row_half_mirror
+        v = dpp_add<0x140>(v);   // row_mirror
+    }
+    if constexpr (S == 64) {
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+    }
     return v;
 }
 
