@@ -43,7 +43,9 @@ typedef enum {
     NB_ERANGE = -4,   /* a new time step fell below dt_min                      */
     NB_ENAN = -5,     /* non-finite acceleration, jerk or time step            */
     NB_EINDEX = -6,   /* an active index was outside [0, n)                     */
-    NB_EUNBOUND = -7  /* a pair handed to the two-body drift is not bound        */
+    NB_EUNBOUND = -7, /* a pair handed to the two-body drift is not bound        */
+    NB_ESCRATCH = -8  /* nb_force_active_noalloc: the call needs more scratch than
+                         the static area holds                                  */
 } nb_status;
 
 typedef enum {
@@ -175,6 +177,22 @@ nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t 
                                nb_precision precision, int32_t i_per_lane,
                                int32_t lanes_per_i, int32_t j_chunks,
                                double *acc, double *jerk);
+
+/* Allocation-free form of nb_force_active, for callers that cannot allocate
+ * memory during the call: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, launch plan, kernels and
+ * results (bitwise) as nb_force_active; it allocates nothing, device or host.
+ * Its launch table and j-chunk partial sums live in a static device area of
+ * NB_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process ends and
+ * located by nb_ctx_create.  A call whose partial sums (6 doubles per active
+ * body and j-chunk when the plan has more than one chunk) would not fit returns
+ * NB_ESCRATCH before anything is enqueued.  Every call on one GPU uses that
+ * GPU's single area, which keeps the last call's contents: calls that overlap
+ * on one GPU (several streams or contexts) race, so serialise them. */
+#define NB_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+nb_status nb_force_active_noalloc(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                                  int32_t m, int64_t j0, int64_t j1, double eps,
+                                  nb_precision precision, double *acc, double *jerk);
 
 /* ---- ragged batches: many independent systems in one launch per phase -------
  * Ensemble serving advances many systems of different n together.  Each batch

@@ -25,12 +25,14 @@ NB_DS = 2
 PRECISIONS = {"fp64": NB_FP64, "mixed": NB_MIXED, "ds": NB_DS}
 
 STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
-          -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX", -7: "NB_EUNBOUND"}
+          -4: "NB_ERANGE", -5: "NB_ENAN", -6: "NB_EINDEX", -7: "NB_EUNBOUND",
+          -8: "NB_ESCRATCH"}
 
 # Every symbol include/nbody.h declares.
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
-           "nb_force_plan", "nb_force_plan_lanes", "nb_force_active_plan", "nb_version", "nb_select_active_batch",
+           "nb_force_plan", "nb_force_plan_lanes", "nb_force_active_plan", "nb_force_active_noalloc",
+           "nb_version", "nb_select_active_batch",
            "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
            "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
@@ -85,6 +87,7 @@ def load() -> C.CDLL:
         "nb_force_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, vp, vp]),
         "nb_force_active_plan": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, i32, i32, i32,
                                            vp, vp]),
+        "nb_force_active_noalloc": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, C.c_int, vp, vp]),
         "nb_force_plan": (None, [i64, i32, C.c_int, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "nb_force_plan_lanes": (C.c_int, [i64, i32, C.c_int, i64, C.POINTER(i32), C.POINTER(i32),
                                           C.POINTER(i32)]),

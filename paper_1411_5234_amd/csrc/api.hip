@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -337,33 +338,62 @@ struct ForcePlan {
     Table red{};
 };
 
+// The j-chunks of an item under its plan: B chunks of ceil(nj / B) bodies rounded
+// up to the LDS tile (the last chunk shorter or empty).
+void set_chunks(Item &it, const Plan &plan)
+{
+    const int64_t nj = it.j1 - it.j0;
+    int64_t chunk = (nj + plan.b - 1) / plan.b;
+    chunk = (chunk + nbk::TILE - 1) / nbk::TILE * nbk::TILE;
+    if (chunk < nbk::TILE) chunk = nbk::TILE;
+    it.chunk = chunk;
+    it.b = plan.b;
+}
+
+// FP64 partial sums an item with more than one j-chunk writes (0 otherwise).
+size_t part_doubles(const Item &it)
+{
+    return it.b > 1 ? nbk::force_outputs(it) * (size_t)it.m * (size_t)it.b : 0;
+}
+
+// Lanes per output value of the partial reduction: about 16 chunks per lane, 1 to 64.
+void set_red_lanes(Item &it)
+{
+    int lanes = 1;
+    while (lanes < 64 && lanes * 16 <= it.b) lanes *= 2;
+    it.red_lanes = lanes;
+}
+
+// Workgroups of an item's force launch and of its partial reduction.
+int64_t force_blocks(const Item &it, const Plan &plan)
+{
+    const int iwg = (nbk::WG / plan.s) * plan.il;
+    return (int64_t)((it.m + iwg - 1) / iwg) * it.b;
+}
+int64_t reduce_blocks(const Item &it)
+{
+    const int64_t per = nbk::WG / it.red_lanes;
+    return (nbk::force_outputs(it) * (int64_t)it.m + per - 1) / per;
+}
+
 nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, ForcePlan *fp, Staging *st)
 {
-    size_t part_doubles = 0;
+    size_t total = 0;
     for (ForceJob &j : jobs) {
-        Item &it = j.it;
-        const int64_t nj = it.j1 - it.j0;
-        int64_t chunk = (nj + j.plan.b - 1) / j.plan.b;
-        chunk = (chunk + nbk::TILE - 1) / nbk::TILE * nbk::TILE;
-        if (chunk < nbk::TILE) chunk = nbk::TILE;
-        it.chunk = chunk;
-        it.b = j.plan.b;
-        if (it.b > 1) part_doubles += nbk::force_outputs(it) * (size_t)it.m * (size_t)it.b;
+        set_chunks(j.it, j.plan);
+        total += part_doubles(j.it);
     }
-    if (part_doubles) {
+    if (total) {
         size_t have = ctx->scratch_bytes;
-        NB_TRY(grow(ctx, &ctx->scratch, &have, part_doubles * sizeof(double), "force partials"));
+        NB_TRY(grow(ctx, &ctx->scratch, &have, total * sizeof(double), "force partials"));
         ctx->scratch_bytes = have;
     }
     size_t off = 0;
     for (ForceJob &j : jobs) {
         if (j.it.b > 1) {
             j.it.part = (double *)ctx->scratch + off;
-            off += nbk::force_outputs(j.it) * (size_t)j.it.m * (size_t)j.it.b;
-            // lanes per output value of the reduction: about 16 chunks per lane, 1 to 64
-            int lanes = 1;
-            while (lanes < 64 && lanes * 16 <= j.it.b) lanes *= 2;
-            j.it.red_lanes = lanes;
+            off += part_doubles(j.it);
+            set_red_lanes(j.it);
         }
     }
     std::map<std::tuple<int, int, bool>, std::vector<size_t>> shapes;
@@ -374,12 +404,11 @@ nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, ForcePlan *fp,
     fp->launches.reserve(shapes.size());
     for (auto &kv : shapes) {
         const int il = std::get<0>(kv.first), s = std::get<1>(kv.first);
-        const int iwg = (nbk::WG / s) * il;
         std::vector<Item> items;
         std::vector<int64_t> blocks;
         for (size_t k : kv.second) {
             items.push_back(jobs[k].it);
-            blocks.push_back((int64_t)((jobs[k].it.m + iwg - 1) / iwg) * jobs[k].it.b);
+            blocks.push_back(force_blocks(jobs[k].it, jobs[k].plan));
         }
         fp->launches.push_back(ForceLaunch{il, s, std::get<2>(kv.first), Table{}});
         NB_TRY(make_table(ctx, items, blocks, &fp->launches.back().t, st));
@@ -389,8 +418,7 @@ nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, ForcePlan *fp,
     for (ForceJob &j : jobs) {
         if (j.it.b > 1 && j.it.m > 0) {
             red.push_back(j.it);
-            const int64_t per = nbk::WG / j.it.red_lanes;
-            rblocks.push_back((nbk::force_outputs(j.it) * (int64_t)j.it.m + per - 1) / per);
+            rblocks.push_back(reduce_blocks(j.it));
         }
     }
     return make_table(ctx, red, rblocks, &fp->red, st);
@@ -783,6 +811,107 @@ nb_status check_step_params(nb_ctx *ctx, double eta, double dt_max, double dt_mi
 
 }  // namespace
 
+// ---- allocation-free force ---------------------------------------------------------
+
+// Static device area of nb_force_active_noalloc: its launch table (one item and
+// the workgroup offsets of the force launch and of the partial reduction) and
+// its j-chunk partial sums.  Every GPU the library runs on holds one copy until
+// the process ends.  Host code never uses this name as an address: it uses the
+// device address hipGetSymbolAddress gives for it on each device
+// (locate_noalloc_area, called by nb_ctx_create with that device current).
+static __device__ __align__(256) unsigned char scratch[NB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t NOALLOC_TABLE_BYTES = 1024;   // item + 4 offsets, rounded up
+static_assert(sizeof(Item) + 4 * sizeof(int64_t) <= NOALLOC_TABLE_BYTES, "table area");
+
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_area;   // device -> address of `scratch` there
+
+nb_status locate_noalloc_area(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto f = g_noalloc_area.find(device);
+    if (f != g_noalloc_area.end()) {
+        *out = f->second;
+        return NB_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return NB_EDEVICE;
+    }
+    g_noalloc_area[device] = p;
+    *out = p;
+    return NB_OK;
+}
+
+// Writes the launch table of one item into the static area: items[0] = it,
+// starts[0..1] = {0, force_blocks}, starts[2..3] = {0, reduce_blocks}.  The item
+// travels as a kernel argument, so nothing is staged in host memory.
+__global__ void put_noalloc_table_kernel(Item it, int64_t fblocks, int64_t rblocks, Item *items,
+                                         int64_t *starts)
+{
+    if (threadIdx.x == 0) {
+        items[0] = it;
+        starts[0] = 0;
+        starts[1] = fblocks;
+        starts[2] = 0;
+        starts[3] = rblocks;
+    }
+}
+
+nb_status force_noalloc(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx, int32_t m,
+                        int64_t j0, int64_t j1, double eps, nb_precision prec, double *acc,
+                        double *jerk)
+{
+    NB_TRY(check_force_args(ctx, sys, m, j0, j1, eps, prec, acc, jerk));
+    if (!ctx->noalloc_area)
+        return fail(ctx, NB_EDEVICE, "the static scratch area was not located on device %d",
+                    ctx->device);
+    if (m == 0) return NB_OK;
+    // The item and plan of nb_force_active, so the kernels and the results are the same.
+    const Plan plan = make_plan(j1 - j0, m, prec);
+    Item it = base_item(ctx, *sys);
+    it.i_idx = i_idx;
+    it.m = m;
+    it.j0 = j0;
+    it.j1 = j1;
+    it.eps2 = eps * eps;
+    it.acc = acc;
+    it.jerk = jerk;
+    set_chunks(it, plan);
+    char *area = (char *)ctx->noalloc_area;
+    const size_t need = NOALLOC_TABLE_BYTES + part_doubles(it) * sizeof(double);
+    if (need > (size_t)NB_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, NB_ESCRATCH,
+                    "m = %d with %d j-chunks needs %zu bytes of static scratch; it holds %lld",
+                    (int)m, it.b, need, (long long)NB_NOALLOC_SCRATCH_BYTES);
+    if (it.b > 1) {
+        it.part = (double *)(area + NOALLOC_TABLE_BYTES);
+        set_red_lanes(it);
+    }
+    const int64_t fb = force_blocks(it, plan), rb = it.b > 1 ? reduce_blocks(it) : 0;
+    if (fb > (int64_t)INT32_MAX) return fail(ctx, NB_EINVAL, "launch too large");
+    Item *items = (Item *)area;
+    int64_t *starts = (int64_t *)(area + sizeof(Item));
+    hipLaunchKernelGGL(put_noalloc_table_kernel, dim3(1), dim3(64), 0, ctx->stream, it, fb, rb,
+                       items, starts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "table launch");
+    e = nbk::launch_force(prec, plan.il, plan.s, Table{items, starts, 1, fb}, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "force kernel launch");
+    if (rb > 0) {
+        e = nbk::launch_reduce(Table{items, starts + 2, 1, rb}, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "partial reduction launch");
+    }
+    return NB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *nb_version(void) { return NB_VERSION; }
@@ -810,6 +939,12 @@ nb_status nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
         return NB_ENOMEM;
     }
     memset(ctx->small_host, 0, sizeof(nb_small));
+    if (locate_noalloc_area(device, &ctx->noalloc_area) != NB_OK) {
+        (void)hipFree(ctx->small);
+        (void)hipHostFree(ctx->small_host);
+        delete ctx;
+        return NB_EDEVICE;
+    }
     *out = ctx;
     return NB_OK;
 }
@@ -910,6 +1045,13 @@ nb_status nb_force_active_plan(nb_ctx *ctx, const nb_system *sys, const int32_t 
 {
     return force_one(ctx, sys, i_idx, m, j0, j1, eps, precision,
                      Plan{i_per_lane, lanes_per_i, j_chunks}, acc, jerk);
+}
+
+nb_status nb_force_active_noalloc(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                                  int32_t m, int64_t j0, int64_t j1, double eps,
+                                  nb_precision precision, double *acc, double *jerk)
+{
+    return force_noalloc(ctx, sys, i_idx, m, j0, j1, eps, precision, acc, jerk);
 }
 
 void nb_force_plan(int64_t nj, int32_t m, nb_precision precision, int32_t *i_per_lane,

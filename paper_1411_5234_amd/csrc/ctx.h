@@ -18,6 +18,7 @@ struct nb_ctx {
     nb_small *small = nullptr;        // device
     nb_small *small_host = nullptr;   // pinned host mirror
     void *scratch = nullptr;          // device: force partials, energy rows (grows)
+    void *noalloc_area = nullptr;     // device address of the static area on this device
     size_t scratch_bytes = 0;
     void *selbuf = nullptr;           // device: selection per-workgroup temporaries (grows)
     size_t selbuf_bytes = 0;

@@ -175,6 +175,16 @@ class Context:
                                              _ptr(acc), _ptr(jerk))
         self._check(rc)
 
+    def force_active_noalloc(self, sys: System, i_idx: torch.Tensor | None, m: int, j0: int,
+                             j1: int, eps: float, precision: str, acc: torch.Tensor,
+                             jerk: torch.Tensor):
+        """nb_force_active_noalloc: the same forces with the library's static scratch."""
+        if acc.numel() < 3 * m or jerk.numel() < 3 * m:
+            raise ValueError("acc/jerk need 3*m elements")
+        self._check(self.L.nb_force_active_noalloc(self.h, sys.ref, _ptr(i_idx), int(m), int(j0),
+                                                   int(j1), float(eps), PRECISIONS[precision],
+                                                   _ptr(acc), _ptr(jerk)))
+
     def init_steps(self, sys: System, acc, jerk, eta_s, dt_max, dt_min):
         self._check(self.L.nb_init_steps(self.h, sys.ref, _ptr(acc), _ptr(jerk), float(eta_s),
                                          float(dt_max), float(dt_min)))
