@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="bodies of the oracle's CPU baseline sample (0 = skip)")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="step mode: serve the first R requests of the C4 stream after the "
+                         "headline (closed batch, Poisson replay, one-at-a-time FP64 on the "
+                         "first --baseline-requests) and report them as `serving` (0 = skip)")
     ap.add_argument("--mode", choices=["step", "sweep", "integrate", "serve", "copy", "groups"],
                     default="step",
                     help="step: the headline (default); sweep: active-block sizes 2^6..2^16 at "
@@ -94,6 +98,11 @@ def parse():
                          "(0: the library default, sized for one system alone; default "
                          "for the C4 stream 2^18 at 4th order and 2^16 at 6th, the fastest "
                          "targets tried there; 0 for C5)")
+    ap.add_argument("--groups", action="store_true",
+                    help="serve mode, C5 stream: carry each primordial binary as one body at its "
+                         "centre of mass, its relative orbit advanced on CPU threads")
+    ap.add_argument("--precisions", default="mixed,fp64",
+                    help="serve mode, C5 stream: the precisions each request is served in")
     ap.add_argument("--closed-only", action="store_true",
                     help="serve mode: the closed batch alone (no Poisson replay, baselines "
                          "or reruns), e.g. for a kernel trace")
@@ -262,19 +271,32 @@ def mode_step(args):
             oa, oj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, il)
         tcpu = time.perf_counter() - tc
         cpu = {"value": k * n / tcpu, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "build": "gcc " + " ".join(oracle.CFLAGS),
                "sample": "%s of the first %d bodies against all %d predicted bodies (FP64, "
                          "compensated sums), %.1f s" % ("acc+jerk+snap" if h6 else "acc+jerk",
                                                          k, n, tcpu)}
         if ms[-1] == n:   # the last block was the whole system, in index order
-            ga = it.acc.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
-            gj = it.jerk.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
+            ga_all = it.acc.view(-1)[: 3 * n].view(3, n).T.cpu().numpy()
+            gj_all = it.jerk.view(-1)[: 3 * n].view(3, n).T.cpu().numpy()
+            ga, gj = ga_all[:k], gj_all[:k]
             ea = np.linalg.norm(ga - oa, axis=1) / np.linalg.norm(oa, axis=1)
             ej = np.linalg.norm(gj - oj, axis=1) / np.linalg.norm(oj, axis=1)
             extra["error_vs_oracle_sample"] = {
                 "bodies": k, "acc_rel_max": float(ea.max()),
                 "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
                 "jerk_rel_max": float(ej.max()), "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
+            if not h6:
+                ssa, ssj = oracle.force_scale(st["xp"], st["vp"], st["m"], args.eps, il)
+                extra["error_vs_oracle_sample"].update(accuracy_summary(ga, gj, oa, oj, ssa, ssj))
+                top = top_kappa_bodies(n, args.seed, args.eps)
+                if top is not None:
+                    ta, tj = oracle.force(st["xp"], st["vp"], st["m"], args.eps, top)
+                    tsa, tsj = oracle.force_scale(st["xp"], st["vp"], st["m"], args.eps, top)
+                    extra["error_vs_oracle_top_kappa"] = {
+                        "bodies": int(top.size),
+                        "chosen": "the 64 largest sum|a_ij|/|a_i| and the 64 largest "
+                                  "sum|jerk_ij|/|jerk_i| of a full oracle scan of the t = 0 state",
+                        **accuracy_summary(ga_all[top], gj_all[top], ta, tj, tsa, tsj)}
             if h6:
                 gs = it.snap.view(-1)[: 3 * n].view(3, n)[:, :k].T.cpu().numpy()
                 ss = oracle.force6_scale(st["xp"], st["vp"], ap, st["m"], args.eps, il)
@@ -288,6 +310,9 @@ def mode_step(args):
                     "acc_rel_max": float(ea.max()), "acc_rel_rms": float(np.sqrt((ea ** 2).mean())),
                     "jerk_rel_max": float(ej.max()),
                     "jerk_rel_rms": float(np.sqrt((ej ** 2).mean()))}
+                if not h6 and prec != "fp64":
+                    extra["other_precisions_same_state"][prec]["error_vs_oracle_sample"].update(
+                        accuracy_summary(pa, pj, oa, oj, ssa, ssj))
 
     kname = "force%s_%s_kernel" % ("6" if h6 else "",
                                    "fp64" if args.precision == "fp64" else "mixed")
@@ -322,8 +347,52 @@ def mode_step(args):
         "cpu_baseline": cpu,
     }
     out.update(extra)
+    if args.serving_requests > 0 and not h6 and args.precision == "mixed":
+        # the serving half of the metric: a bounded sample of the C4 stream
+        print("serving: first %d requests of the C4 stream" % args.serving_requests,
+              file=sys.stderr, flush=True)
+        sv = serving_runs(ctx, "c4", args.serving_requests, baseline=args.baseline_requests)
+        out["serving"] = {"workload": "c4: equal-mass Plummer, N log-uniform in [256, 32768], "
+                                      "eps = 1e-3, to t = 1, first %d requests" % args.serving_requests,
+                          "precision": "mixed", "lanes": default_lanes("c4", 4), **sv}
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+ACC_GATE = 1e-6           # per-body relative error of the mixed path (acceleration and jerk)
+
+
+def accuracy_summary(ga, gj, oa, oj, sa, sj):
+    """Plain per-body relative errors |g - o| / |o|, the errors over the magnitude
+    scales sum_j |a_ij| and sum_j |jerk_ij|, the share of bodies within the plain
+    1e-6, and the cancellation factors kappa = scale / |o| of the worst bodies."""
+    import numpy as np
+    na, nj = np.linalg.norm(oa, axis=1), np.linalg.norm(oj, axis=1)
+    ea = np.linalg.norm(ga - oa, axis=1) / na
+    ej = np.linalg.norm(gj - oj, axis=1) / nj
+    wa, wj = int(np.argmax(ea)), int(np.argmax(ej))
+    return {"acc_rel_max": float(ea.max()), "jerk_rel_max": float(ej.max()),
+            "acc_over_scale_max": float((np.linalg.norm(ga - oa, axis=1) / sa).max()),
+            "jerk_over_scale_max": float((np.linalg.norm(gj - oj, axis=1) / sj).max()),
+            "share_acc_rel_le_1e-6": float((ea <= ACC_GATE).mean()),
+            "share_jerk_rel_le_1e-6": float((ej <= ACC_GATE).mean()),
+            "share_both_rel_le_1e-6": float(((ea <= ACC_GATE) & (ej <= ACC_GATE)).mean()),
+            "kappa_acc_of_worst_acc_body": float(sa[wa] / na[wa]),
+            "kappa_jerk_of_worst_jerk_body": float(sj[wj] / nj[wj])}
+
+
+def top_kappa_bodies(n, seed, eps):
+    """Indices of the bodies with the largest cancellation factors of the N = 2^20
+    Plummer sphere (seed 3, eps = 1e-4), as written by the oracle-only script
+    tests/golden/make_kappa_plummer_2pow20.py; None for other workloads."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "kappa_plummer_2pow20_seed3.json")
+    if (n, seed, eps) != (1 << 20, 3, 1e-4) or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    idx = rec["top_kappa_acc"]["index"] + rec["top_kappa_jerk"]["index"]
+    return np.unique(np.asarray(idx, dtype=np.int64))
 
 
 def _timed_force(ctx, system, idx, m, eps, precision, acc, jerk, plan=None, reps=5):
@@ -441,37 +510,30 @@ def mode_integrate(args):
     print(json.dumps(out), flush=True)
 
 
-def mode_serve(args):
-    """Serve a Poisson stream through the continuous-batching server.
+SERVE_SPECS = {
+    "c4": dict(n_lo=256, n_hi=32768, eps=1e-3, t_end=1.0, kind="plummer", seed=4, base=4000),
+    "c5": dict(n_lo=1024, n_hi=65536, eps=1e-5, t_end=0.125, kind="kroupa_binaries", seed=5,
+               base=5000),
+}
 
-    c4: equal-mass Plummer clusters, N log-uniform in [256, 32768], eps = 1e-3, to
-    t = 1.  c5: Kroupa IMF with 10% binaries, N log-uniform in [1024, 65536],
-    eps = 1e-5, to t = 1/8.  The stream is first served as a closed batch to
-    measure saturated throughput, then replayed in real time with arrivals at
-    0.8 x that rate; a one-at-a-time FP64 baseline serves the first
-    --baseline-requests requests alone, one after another."""
-    import numpy as np
 
+def default_lanes(stream, order):
+    """Force-plan lane target of the batched systems: with up to 256 C4 systems
+    resident the batch fills the GPU and shorter splits win (measured fastest:
+    2^18 at 4th order, 2^16 at 6th); the C5 runs keep few systems resident, where
+    the library default (one system fills the GPU) was faster."""
+    return 0 if stream == "c5" else (1 << 16 if order == 6 else 1 << 18)
+
+
+def serve_stream(stream, rate, count):
     from paper_1411_5234_amd import inputs
-    from paper_1411_5234_amd.nbody import Context
-    from paper_1411_5234_amd.serve import Server, summarize
-    if args.lanes is None:
-        # measured: with up to 256 C4 systems resident the batch fills the GPU and
-        # shorter splits win; the C5 runs keep few systems resident, where the
-        # default split (one system fills the GPU) was faster
-        args.lanes = 0 if args.stream == "c5" else (1 << 16 if args.order == 6 else 1 << 18)
-    if args.stream == "c4":
-        spec = dict(n_lo=256, n_hi=32768, eps=1e-3, t_end=1.0, kind="plummer", seed=4, base=4000)
-    else:
-        spec = dict(n_lo=1024, n_hi=65536, eps=1e-5, t_end=0.125, kind="kroupa_binaries", seed=5,
-                    base=5000)
+    spec = SERVE_SPECS[stream]
+    return inputs.request_stream(count, spec["seed"], spec["n_lo"], spec["n_hi"], rate=rate,
+                                 eps=spec["eps"], t_end=spec["t_end"], kind=spec["kind"],
+                                 ic_seed_base=spec["base"])
 
-    def stream(rate, count):
-        return inputs.request_stream(count, spec["seed"], spec["n_lo"], spec["n_hi"], rate=rate,
-                                     eps=spec["eps"], t_end=spec["t_end"], kind=spec["kind"],
-                                     ic_seed_base=spec["base"])
 
-    ctx = Context(0)
+def _progress():
     last = [time.perf_counter()]
 
     def progress(srv):
@@ -481,53 +543,89 @@ def mode_serve(args):
             print("  iteration %d: %d resident, %d queued, %d done" % (
                 srv.iterations, len(srv.slots), len(srv.queue), len(srv.results)),
                 file=sys.stderr, flush=True)
+    return progress
 
+
+def serving_runs(ctx, stream, requests, precision="mixed", order=4, slots=256, lanes=None,
+                 baseline=32, closed_only=False):
+    """The first `requests` requests of a serving stream, served four ways:
+    - closed batch: all arrive at t = 0 (saturated throughput);
+    - Poisson replay in real time at 0.8 x the closed-batch rate;
+    - one at a time in FP64 (the first `baseline` requests, one after another);
+    - the same `baseline` requests through the batched server, for a like-for-like rate.
+    Returns the summaries (solves/s, p50/p99 latency, interactions, energy errors)."""
+    from paper_1411_5234_amd.serve import Server, summarize
+    lanes = default_lanes(stream, order) if lanes is None else lanes
+    progress = _progress()
+    out = {}
+    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes)
+    t0 = time.perf_counter()
+    res = srv.run(serve_stream(stream, 0.0, requests), realtime=False, on_iteration=progress)
+    out["closed_batch"] = summarize(res, time.perf_counter() - t0)
+    print("closed batch: %s" % out["closed_batch"], file=sys.stderr, flush=True)
+    if closed_only:
+        return out
+    rate = 0.8 * out["closed_batch"]["solves_per_s"]
+    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes)
+    t0 = time.perf_counter()
+    res = srv.run(serve_stream(stream, rate, requests), realtime=True, on_iteration=progress)
+    out["poisson"] = summarize(res, time.perf_counter() - t0)
+    out["poisson"]["arrival_rate_per_s"] = rate
+    print("poisson at %.2f/s: %s" % (rate, out["poisson"]), file=sys.stderr, flush=True)
+    k = min(baseline, requests)
+    if k > 0:
+        srv = Server(ctx, precision="fp64", max_slots=1, energy=True, order=order)
+        t0 = time.perf_counter()
+        res = srv.run(serve_stream(stream, 0.0, requests)[:k], realtime=False,
+                      on_iteration=progress)
+        out["one_at_a_time_fp64"] = summarize(res, time.perf_counter() - t0)
+        out["one_at_a_time_fp64"]["requests_served"] = k
+        print("one at a time fp64: %s" % out["one_at_a_time_fp64"], file=sys.stderr, flush=True)
+        srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order,
+                     lanes=lanes)
+        t0 = time.perf_counter()
+        res = srv.run(serve_stream(stream, 0.0, requests)[:k], realtime=False)
+        out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
+        out["batched_same_requests"]["requests_served"] = k
+    return out
+
+
+def mode_serve(args):
+    """Serve a request stream through the continuous-batching server.
+
+    c4: equal-mass Plummer clusters, N log-uniform in [256, 32768], eps = 1e-3, to
+    t = 1.  c5: Kroupa IMF with 10% binaries, N log-uniform in [1024, 65536],
+    eps = 1e-5, to t = 1/8.  The stream is first served as a closed batch to
+    measure saturated throughput, then replayed in real time with arrivals at
+    0.8 x that rate; a one-at-a-time FP64 baseline serves the first
+    --baseline-requests requests alone, one after another."""
+    from paper_1411_5234_amd.nbody import Context
+    from paper_1411_5234_amd.serve import Server
+    if args.lanes is None:
+        args.lanes = default_lanes(args.stream, args.order)
+    if args.stream == "c5":
+        return mode_serve_c5(args)
+    spec = SERVE_SPECS[args.stream]
+    ctx = Context(0)
     out = {"metric": "ensemble solves/s and p50/p99 latency", "mode": "serve",
            "config": {"workload": args.stream, "requests": args.requests, "slots": args.slots,
                       "precision": args.precision, "order": args.order, "lanes": args.lanes,
                       **{k: v for k, v in spec.items() if k != "base"}}}
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
-                     lanes=args.lanes)
-    t0 = time.perf_counter()
-    res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
-    closed = summarize(res, time.perf_counter() - t0)
-    out["closed_batch"] = closed
-    print("closed batch: %s" % closed, file=sys.stderr, flush=True)
+    out.update(serving_runs(ctx, args.stream, args.requests, args.precision, args.order,
+                            args.slots, args.lanes, args.baseline_requests, args.closed_only))
+    closed = out["closed_batch"]
     if args.closed_only:
         ctx.close()
         out["value"] = closed["solves_per_s"]
         out["unit"] = "solves/s"
         print(json.dumps(out), flush=True)
         return
-    rate = 0.8 * closed["solves_per_s"]
-    srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
-                     lanes=args.lanes)
-    t0 = time.perf_counter()
-    res = srv.run(stream(rate, args.requests), realtime=True, on_iteration=progress)
-    poisson = summarize(res, time.perf_counter() - t0)
-    poisson["arrival_rate_per_s"] = rate
-    out["poisson"] = poisson
-    print("poisson at %.2f/s: %s" % (rate, poisson), file=sys.stderr, flush=True)
-    k = min(args.baseline_requests, args.requests)
-    if k > 0:
-        srv = Server(ctx, precision="fp64", max_slots=1, energy=True, order=args.order)
-        t0 = time.perf_counter()
-        res = srv.run(stream(0.0, args.requests)[:k], realtime=False, on_iteration=progress)
-        base = summarize(res, time.perf_counter() - t0)
-        base["requests_served"] = k
-        out["one_at_a_time_fp64"] = base
-        print("one at a time fp64: %s" % base, file=sys.stderr, flush=True)
-        # the same k requests through the batched server, for a like-for-like rate
-        srv = Server(ctx, precision=args.precision, max_slots=args.slots, energy=True, order=args.order,
-                     lanes=args.lanes)
-        t0 = time.perf_counter()
-        res = srv.run(stream(0.0, args.requests)[:k], realtime=False)
-        out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
+    progress = _progress()
     worst = closed.get("energy_error_worst_request")
     if worst is not None:
         # the request with the largest energy error, served alone in FP64 and in the
         # run's precision: tells the integrator's error from the pair arithmetic's
-        req = [q for q in stream(0.0, args.requests) if q.rid == worst["rid"]]
+        req = [q for q in serve_stream(args.stream, 0.0, args.requests) if q.rid == worst["rid"]]
         row = dict(worst)
         for prec in dict.fromkeys(("fp64", args.precision)):
             srv = Server(ctx, precision=prec, max_slots=1, energy=True, order=args.order,
@@ -536,23 +634,79 @@ def mode_serve(args):
             row["energy_error_" + prec] = r.energy_error if r.error is None else r.error
         out["worst_request_alone"] = row
         print("worst request alone: %s" % row, file=sys.stderr, flush=True)
-    if args.stream == "c5":
-        # the same requests in FP64 and in mixed precision: energy error per request
-        per = {}
-        for prec in ("fp64", "mixed"):
-            srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, order=args.order,
-                         lanes=args.lanes)
-            res = srv.run(stream(0.0, args.requests), realtime=False, on_iteration=progress)
-            per[prec] = {r.rid: r for r in res}
-        rows = []
-        for rid in sorted(per["fp64"]):
-            a, b = per["fp64"][rid], per["mixed"].get(rid)
-            if a.error is None and b is not None and b.error is None:
-                rows.append({"rid": rid, "n": a.n, "energy_error_fp64": a.energy_error,
-                             "energy_error_mixed": b.energy_error})
-        out["energy_error_per_request"] = rows
     ctx.close()
-    out["value"] = poisson["solves_per_s"]
+    out["value"] = out["poisson"]["solves_per_s"]
+    out["unit"] = "solves/s"
+    print(json.dumps(out), flush=True)
+
+
+def mode_serve_c5(args):
+    """The precision-stress stream (C5): Kroupa clusters with 10% of the bodies in
+    primordial binaries, N log-uniform in [1024, 65536], eps = 1e-5, to t = 1/8.
+    The first --requests requests are served as a closed batch in each precision of
+    --precisions, directly (every body in the block-step system) or with --groups
+    (each binary carried as one body at its centre of mass, its orbit advanced on
+    CPU threads).  Reported: solves/s per precision and, per request, the energy
+    error in each precision (grouped: the scheme's conserved quantity and the full
+    N-body energy of the reconstructed members), with its distribution."""
+    import numpy as np
+
+    from paper_1411_5234_amd.nbody import Context
+    from paper_1411_5234_amd.serve import Server, summarize
+    spec = SERVE_SPECS["c5"]
+    precs = [p for p in args.precisions.split(",") if p]
+    reqs = serve_stream("c5", 0.0, args.requests)
+    ctx = Context(0)
+    out = {"metric": "ensemble solves/s and energy error per request, mixed vs FP64",
+           "mode": "serve", "config": {"workload": "c5", "requests": args.requests,
+                                       "slots": args.slots, "groups": args.groups,
+                                       "lanes": args.lanes, "precisions": precs,
+                                       **{k: v for k, v in spec.items() if k != "base"}}}
+    progress = _progress()
+    per = {}
+    for prec in precs:
+        srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, lanes=args.lanes,
+                     groups=args.groups)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=False, on_iteration=progress)
+        out["closed_batch_" + prec] = summarize(res, time.perf_counter() - t0)
+        print("%s closed batch: %s" % (prec, out["closed_batch_" + prec]), file=sys.stderr,
+              flush=True)
+        per[prec] = {r.rid: r for r in res}
+    rows = []
+    for q in reqs:
+        row = {"rid": q.rid, "n": q.n}
+        for prec in precs:
+            r = per[prec].get(q.rid)
+            if r is None or r.error is not None:
+                row["error_" + prec] = r.error if r is not None else "missing"
+                continue
+            row["pairs"] = r.pairs
+            row["steps_" + prec] = r.steps
+            row["energy_error_" + prec] = r.energy_error
+            if args.groups:
+                row["direct_energy_error_" + prec] = abs(r.direct1 - r.direct0) / abs(r.direct0)
+        rows.append(row)
+    out["energy_error_per_request"] = rows
+    dist = {}
+    for key in ["energy_error_" + p for p in precs] + (
+            ["direct_energy_error_" + p for p in precs] if args.groups else []):
+        vals = np.array([r[key] for r in rows if key in r])
+        if vals.size:
+            worst = max((r for r in rows if key in r), key=lambda r: r[key])
+            dist[key] = {"requests": int(vals.size), "median": float(np.median(vals)),
+                         "p90": float(np.quantile(vals, 0.9)), "max": float(vals.max()),
+                         "worst_request": {"rid": worst["rid"], "n": worst["n"]}}
+    if "mixed" in precs and "fp64" in precs:
+        both = [r for r in rows if "energy_error_mixed" in r and "energy_error_fp64" in r]
+        ratio = np.array([r["energy_error_mixed"] / max(r["energy_error_fp64"], 1e-300)
+                          for r in both])
+        if ratio.size:
+            dist["mixed_over_fp64"] = {"median": float(np.median(ratio)),
+                                       "min": float(ratio.min()), "max": float(ratio.max())}
+    out["energy_error_distribution"] = dist
+    ctx.close()
+    out["value"] = out["closed_batch_" + precs[0]]["solves_per_s"]
     out["unit"] = "solves/s"
     print(json.dumps(out), flush=True)
 

@@ -129,6 +129,19 @@ nb_status nb_force_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
 nb_status nb_init_steps(nb_ctx *ctx, const nb_system *sys, const double *acc,
                         const double *jerk, double eta_s, double dt_max, double dt_min);
 
+/* Bodies joining a running block-step system at block time t (the two members
+ * of a pair returned to the N-body system): copy acc/jerk of the m listed bodies
+ * (3*m SoA, from nb_force_active on the predicted set at t) into their state,
+ * set their time to t and their step by the startup rule, the largest power of
+ * two not above min(eta_s |a| / |j|, dt_max).  dt_max must be a power of two
+ * that divides t (for instance the step of the body they replace), so the new
+ * steps keep the block times commensurate (Sec. 2 item 2).  A step below dt_min
+ * latches NB_ERANGE; a non-finite value NB_ENAN; an index outside [0, n)
+ * NB_EINDEX.  Returns NB_EINVAL for bad arguments or t not a multiple of dt_max. */
+nb_status nb_init_steps_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                               int32_t m, const double *acc, const double *jerk, double t,
+                               double eta_s, double dt_max, double dt_min);
+
 /* Corrector and new step for the active block (Sec. 2 items 1-2; the standard
  * 4th-order Hermite form of Aarseth's book, cited there).  With h = t_next - t_i,
  * (a0, j0) the stored and (a1, j1) the new acc/jerk (3*m SoA, order of i_idx):
@@ -372,6 +385,69 @@ nb_status nb_step6_batch(nb_ctx *ctx, nb_batch_item *items, const nb_hermite6 *h
  * Returns NB_EINVAL for eps < 0, bad ranges or m < 0; m == 0 is a no-op. */
 nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
                           int32_t m, int64_t j0, int64_t j1, double eps, double *tensor);
+
+/* The tidal tensor of many systems in one launch (a served ensemble whose pairs
+ * are carried as centre-of-mass bodies).  Per item, as nb_tidal_active over the
+ * whole j-range [0, sys.n), at the bodies i_idx[0 .. m), into `tensor` (device,
+ * 9*m doubles, (3a+b)*m + k); `t_out` (device, m doubles, or NULL) receives each
+ * listed body's time t_i, so the host can tell which pairs were in the last
+ * block.  `status`: the item's device error word (NULL: the context's).  Items
+ * with m == 0 are skipped.  Returns NB_EINVAL for a bad item (nothing enqueued). */
+typedef struct {
+    nb_system sys;
+    const int32_t *i_idx;  /* device: listed bodies                       */
+    int32_t m;
+    double eps;            /* >= 0                                        */
+    double *tensor;        /* device, 9*m                                 */
+    double *t_out;         /* device, m, or NULL                          */
+    int32_t *status;       /* device word, or NULL                        */
+} nb_tidal_item;
+nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t n_items);
+
+/* Host.  The reduced system of n bodies with n_pairs bound pairs (pairs[2k],
+ * pairs[2k+1]: distinct indices in [0, n)): the bodies in no pair, in index
+ * order, then one body per pair at its centre of mass, mass M = m1 + m2,
+ *   x_c = (m1 x1 + m2 x2) / M,  v_c likewise;
+ * and per pair M[k], r = x2 - x1, w = v2 - v1.  x, v: (n, 3) row-major; xr, vr:
+ * (n - n_pairs, 3); mr: n - n_pairs; r, w: (n_pairs, 3).  All HOST memory.
+ * Returns NB_OK or NB_EINVAL (bad or repeated indices). */
+nb_status nb_pairs_reduce(int64_t n, const double *x, const double *v, const double *m,
+                          int32_t n_pairs, const int64_t *pairs, double *xr, double *vr,
+                          double *mr, double *M, double *r, double *w);
+
+/* Host.  The inverse: members' positions and velocities from the reduced state
+ * (xr, vr as written by nb_pairs_reduce, later advanced) and each pair's r, w:
+ *   x1 = x_c - (m2 / M) r,  x2 = x_c + (m1 / M) r  (v alike).
+ * x, v: (n, 3) outputs.  Returns NB_OK or NB_EINVAL. */
+nb_status nb_pairs_members(int64_t n, const double *xr, const double *vr, const double *m,
+                           int32_t n_pairs, const int64_t *pairs, const double *r,
+                           const double *w, double *x, double *v);
+
+/* Host.  The pairs' part of the quantity the scheme conserves:
+ *   sum_k mu_k (|w_k|^2 / 2 - M_k / |r_k| - r_k . T_k r_k / 2),  mu = m1 m2 / M,
+ * with T_k the tidal tensor (row-major 3x3 at T[9k..]) at the pair's current
+ * time; compensated sum over k in order.  Returns NB_OK or NB_EINVAL. */
+nb_status nb_pairs_energy(int32_t n_pairs, const double *m, const int64_t *pairs,
+                          const double *r, const double *w, const double *T, double *out);
+
+/* Host.  Per pair: the semimajor axis a of its relative orbit, written from r
+ * and w as a = 1 / (2/|r| - |w|^2/M) (INFINITY if unbound) -- or, with r == NULL,
+ * read from a -- and its perturbation
+ *   gamma = |T|_F (2a)^3 / M,
+ * the tidal acceleration across the orbit's diameter over the pair's own
+ * acceleration at that distance (T row-major 3x3 at T[9k..]; T == NULL gives
+ * gamma = 0 for a bound pair, INFINITY for an unbound one).  A server groups a
+ * pair while gamma is small and returns it to the N-body system as two bodies
+ * otherwise.  All arrays HOST memory.  Returns NB_OK or NB_EINVAL. */
+nb_status nb_pairs_perturbation(int32_t n_pairs, const double *M, const double *r,
+                                const double *w, const double *T, double *a, double *gamma);
+
+/* Host.  When pairs return to the N-body system as two bodies, the quantity the
+ * scheme conserves changes by their mutual potential turning from the unsoftened
+ * into the softened one:  out = sum_k m1 m2 (1/|r_k| - 1/sqrt(|r_k|^2 + eps^2)).
+ * Returns NB_OK or NB_EINVAL (a pair at r = 0). */
+nb_status nb_pairs_split_energy(int32_t n_pairs, const double *m, const int64_t *pairs,
+                                const double *r, double eps, double *out);
 
 /* Host.  Two-body motion of a bound relative coordinate (r0, v0) of total mass M
  * over dt (any sign, any length): r'' = -M r / |r|^3.  All pointers are HOST

@@ -24,6 +24,10 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _lib = None
+# Plain FP64: no contraction into FMA, no fast-math, so reductions keep their
+# written order; -O3 without -march, so the library built here runs on any x86-64
+# host it is copied to.
+CFLAGS = ["-O3", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
 
 def build(force: bool = True) -> str:
@@ -31,8 +35,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    cmd = ["gcc"] + CFLAGS + ["-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

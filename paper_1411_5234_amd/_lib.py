@@ -32,11 +32,13 @@ STATUS = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_ENOMEM", -3: "NB_EDEVICE",
 EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_select_active",
            "nb_predict", "nb_force_active", "nb_init_steps", "nb_correct", "nb_energy",
            "nb_force_plan", "nb_force_plan_lanes", "nb_force_active_plan", "nb_force_active_noalloc",
+           "nb_init_steps_active", "nb_pairs_perturbation", "nb_pairs_split_energy",
            "nb_version", "nb_select_active_batch",
            "nb_predict_batch", "nb_force_active_batch", "nb_correct_batch", "nb_step_batch",
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
-           "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_kepler_drift", "nb_groups_advance",
-           "nb_groups_advance_async", "nb_groups_wait"]
+           "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_tidal_active_batch",
+           "nb_pairs_reduce", "nb_pairs_members", "nb_pairs_energy", "nb_kepler_drift",
+           "nb_groups_advance", "nb_groups_advance_async", "nb_groups_wait"]
 
 
 class NbSystem(C.Structure):
@@ -53,6 +55,11 @@ class NbBatchItem(C.Structure):
                 ("t_next", C.c_double), ("t_end", C.c_double), ("m", C.c_int32),
                 ("startup", C.c_int32), ("error", C.c_int32), ("done", C.c_int32),
                 ("lanes", C.c_int64)]
+
+
+class NbTidalItem(C.Structure):
+    _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("m", C.c_int32), ("eps", C.c_double),
+                ("tensor", C.c_void_p), ("t_out", C.c_void_p), ("status", C.c_void_p)]
 
 
 class NbError(RuntimeError):
@@ -92,6 +99,9 @@ def load() -> C.CDLL:
         "nb_force_plan_lanes": (C.c_int, [i64, i32, C.c_int, i64, C.POINTER(i32), C.POINTER(i32),
                                           C.POINTER(i32)]),
         "nb_init_steps": (C.c_int, [vp, ps, vp, vp, f64, f64, f64]),
+        "nb_init_steps_active": (C.c_int, [vp, ps, vp, i32, vp, vp, f64, f64, f64, f64]),
+        "nb_pairs_perturbation": (C.c_int, [i32, vp, vp, vp, vp, vp, vp]),
+        "nb_pairs_split_energy": (C.c_int, [i32, vp, vp, vp, f64, vp]),
         "nb_correct": (C.c_int, [vp, ps, vp, i32, vp, vp, f64, f64, f64, f64]),
         "nb_energy": (C.c_int, [vp, ps, f64, C.POINTER(f64), C.POINTER(f64)]),
         "nb_version": (C.c_char_p, []),
@@ -111,6 +121,10 @@ def load() -> C.CDLL:
         "nb_step6_batch": (C.c_int, [vp, C.POINTER(NbBatchItem), ph, C.POINTER(C.c_void_p), i32,
                                      C.c_int, f64, f64, f64, f64]),
         "nb_tidal_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, vp]),
+        "nb_tidal_active_batch": (C.c_int, [vp, C.POINTER(NbTidalItem), i32]),
+        "nb_pairs_reduce": (C.c_int, [i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "nb_pairs_members": (C.c_int, [i64, vp, vp, vp, i32, vp, vp, vp, vp, vp]),
+        "nb_pairs_energy": (C.c_int, [i32, vp, vp, vp, vp, vp, vp]),
         "nb_kepler_drift": (C.c_int, [f64, vp, vp, f64, vp, vp]),
         "nb_groups_advance": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp]),
         "nb_groups_advance_async": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp]),

@@ -338,16 +338,21 @@ struct ForcePlan {
     Table red{};
 };
 
-// The j-chunks of an item under its plan: B chunks of ceil(nj / B) bodies rounded
-// up to the LDS tile (the last chunk shorter or empty).
-void set_chunks(Item &it, const Plan &plan)
+// The j-chunks of an item under its plan: ceil(nj / B) bodies rounded up to the
+// kernel's work granule -- the j-bodies a lane group passes over between two
+// FP32 run folds (S x fold, at most one LDS tile) in the mixed and double-single
+// kernels, the whole tile in the FP64 ones -- then as many chunks as that takes
+// (at most B; the last one shorter).  A chunk ends on a granule, so no chunk
+// does work past its share, and no chunk is empty.
+void set_chunks(Item &it, const Plan &plan, int prec)
 {
     const int64_t nj = it.j1 - it.j0;
+    const int64_t g = prec == NB_FP64 ? nbk::TILE
+                                      : (int64_t)plan.s * std::min(nbk::TILE / plan.s, NBK_FOLD);
     int64_t chunk = (nj + plan.b - 1) / plan.b;
-    chunk = (chunk + nbk::TILE - 1) / nbk::TILE * nbk::TILE;
-    if (chunk < nbk::TILE) chunk = nbk::TILE;
+    chunk = std::max<int64_t>(g, (chunk + g - 1) / g * g);
     it.chunk = chunk;
-    it.b = plan.b;
+    it.b = nj > 0 ? (int)((nj + chunk - 1) / chunk) : 1;
 }
 
 // FP64 partial sums an item with more than one j-chunk writes (0 otherwise).
@@ -376,11 +381,12 @@ int64_t reduce_blocks(const Item &it)
     return (nbk::force_outputs(it) * (int64_t)it.m + per - 1) / per;
 }
 
-nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, ForcePlan *fp, Staging *st)
+nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec, ForcePlan *fp,
+                        Staging *st)
 {
     size_t total = 0;
     for (ForceJob &j : jobs) {
-        set_chunks(j.it, j.plan);
+        set_chunks(j.it, j.plan, prec);
         total += part_doubles(j.it);
     }
     if (total) {
@@ -462,7 +468,7 @@ nb_status run_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec)
 {
     Staging st;
     ForcePlan fp;
-    NB_TRY(prepare_force(ctx, jobs, &fp, &st));
+    NB_TRY(prepare_force(ctx, jobs, prec, &fp, &st));
     NB_TRY(flush(ctx, &st));
     return launch_force(ctx, fp, prec);
 }
@@ -720,7 +726,7 @@ nb_status advance_items(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items
     Table tp, tc, ti;
     ForcePlan fp;
     NB_TRY(make_table(ctx, pred, pblocks, &tp, &st));
-    NB_TRY(prepare_force(ctx, jobs, &fp, &st));
+    NB_TRY(prepare_force(ctx, jobs, precision, &fp, &st));
     NB_TRY(make_table(ctx, cor, cblocks, &tc, &st));
     NB_TRY(make_table(ctx, ini, iblocks, &ti, &st));
     NB_TRY(flush(ctx, &st));
@@ -778,7 +784,7 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
         Staging st;
         Table t4;
         ForcePlan fp4;
-        NB_TRY(prepare_force(ctx, jobs4, &fp4, &st));
+        NB_TRY(prepare_force(ctx, jobs4, precision, &fp4, &st));
         NB_TRY(make_table(ctx, ini4, bi4, &t4, &st));
         NB_TRY(flush(ctx, &st));
         NB_TRY(launch_force(ctx, fp4, precision));
@@ -789,7 +795,7 @@ nb_status advance_items6(nb_ctx *ctx, const nb_batch_item *items, const nb_hermi
     Table tp, tc, ti;
     ForcePlan fp;
     NB_TRY(make_table(ctx, pred6, bp6, &tp, &st));
-    NB_TRY(prepare_force(ctx, jobs6, &fp, &st));
+    NB_TRY(prepare_force(ctx, jobs6, precision, &fp, &st));
     NB_TRY(make_table(ctx, cor6, bc6, &tc, &st));
     NB_TRY(make_table(ctx, ini6, bi6, &ti, &st));
     NB_TRY(flush(ctx, &st));
@@ -882,7 +888,7 @@ nb_status force_noalloc(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
     it.eps2 = eps * eps;
     it.acc = acc;
     it.jerk = jerk;
-    set_chunks(it, plan);
+    set_chunks(it, plan, prec);
     char *area = (char *)ctx->noalloc_area;
     const size_t need = NOALLOC_TABLE_BYTES + part_doubles(it) * sizeof(double);
     if (need > (size_t)NB_NOALLOC_SCRATCH_BYTES)
@@ -1088,6 +1094,30 @@ nb_status nb_init_steps(nb_ctx *ctx, const nb_system *sys, const double *acc,
     Table t;
     NB_TRY(make_table(ctx, items, blocks, &t));
     hipError_t e = nbk::launch_init_steps(t, eta_s, dt_max, dt_min, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
+}
+
+nb_status nb_init_steps_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_idx,
+                               int32_t m, const double *acc, const double *jerk, double t,
+                               double eta_s, double dt_max, double dt_min)
+{
+    NB_TRY(check_system(ctx, sys, false));
+    NB_TRY(check_step_params(ctx, eta_s, dt_max, dt_min));
+    if (m < 0 || (int64_t)m > sys->n) return fail(ctx, NB_EINVAL, "m out of range");
+    if (!(t >= 0.0) || !isfinite(t)) return fail(ctx, NB_EINVAL, "t must be finite and >= 0");
+    if (fmod(t, dt_max) != 0.0) return fail(ctx, NB_EINVAL, "t must be a multiple of dt_max");
+    if (m == 0) return NB_OK;
+    if (!i_idx || !acc || !jerk) return fail(ctx, NB_EINVAL, "i_idx/acc/jerk is NULL");
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].i_idx = i_idx;
+    items[0].m = m;
+    items[0].t_next = t;
+    items[0].acc = (double *)acc;
+    items[0].jerk = (double *)jerk;
+    std::vector<int64_t> blocks{(m + nbk::WG - 1) / nbk::WG};
+    Table tb;
+    NB_TRY(make_table(ctx, items, blocks, &tb));
+    hipError_t e = nbk::launch_init_steps(tb, eta_s, dt_max, dt_min, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "init_steps launch");
 }
 
@@ -1425,10 +1455,45 @@ nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
     items[0].j0 = j0;
     items[0].j1 = j1;
     items[0].eps2 = eps * eps;
+    items[0].tensor = tensor;
     std::vector<int64_t> blocks{m};
     Table t;
     NB_TRY(make_table(ctx, items, blocks, &t));
-    hipError_t e = nbk::launch_tidal(t, tensor, ctx->stream);
+    hipError_t e = nbk::launch_tidal(t, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
+}
+
+nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t n_items)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    std::vector<Item> dev;
+    std::vector<int64_t> blocks;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const nb_tidal_item &b = items[k];
+        NB_TRY(check_system(ctx, &b.sys, true));
+        if (!(b.eps >= 0.0) || !isfinite(b.eps))
+            return fail(ctx, NB_EINVAL, "item %d: eps must be >= 0 and finite", (int)k);
+        if (b.m < 0 || (int64_t)b.m > b.sys.n)
+            return fail(ctx, NB_EINVAL, "item %d: m out of range", (int)k);
+        if (b.m == 0) continue;
+        if (!b.i_idx || !b.tensor)
+            return fail(ctx, NB_EINVAL, "item %d: i_idx or tensor is NULL", (int)k);
+        Item it = base_item(ctx, b.sys);
+        if (b.status) it.status = b.status;
+        it.i_idx = b.i_idx;
+        it.m = b.m;
+        it.j0 = 0;
+        it.j1 = b.sys.n;
+        it.eps2 = b.eps * b.eps;
+        it.tensor = b.tensor;
+        it.t_out = b.t_out;
+        dev.push_back(it);
+        blocks.push_back(b.m);
+    }
+    Table t;
+    NB_TRY(make_table(ctx, dev, blocks, &t));
+    hipError_t e = nbk::launch_tidal(t, ctx->stream);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
 }
 

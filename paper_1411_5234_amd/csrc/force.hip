@@ -361,36 +361,53 @@ hipError_t launch_reduce(const Table &t, hipStream_t st)
 
 // ---- energy -------------------------------------------------------------------
 
-// rows[i] = m_i * sum_{j != i} m_j / sqrt(|x_j - x_i|^2 + eps^2), one i per lane.
+// rows[i] = m_i * sum_{j > i} m_j / sqrt(|x_j - x_i|^2 + eps^2): each unordered pair
+// once, one i per lane.  Row i takes n - 1 - i pairs, so workgroup k takes two
+// blocks of WG rows, block k and block nb - 1 - k (nb = blocks of WG rows), and
+// every workgroup does about n pairs.  The first tile of a block holds its own
+// rows' diagonal (pairs with j <= i masked out); the tiles after it are whole.
 __global__ __launch_bounds__(WG) void potential_rows_kernel(const double *x, const double *y,
                                                             const double *z, const double *mass,
                                                             int64_t n, double eps2, double *rows)
 {
     __shared__ double sx[TILE], sy[TILE], sz[TILE], sm[TILE];
-    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const int64_t ii = i < n ? i : 0;
-    const double xi = x[ii], yi = y[ii], zi = z[ii];
-    double tot = 0.0;
-    for (int64_t jt = 0; jt < n; jt += TILE) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < TILE; q += WG) {
-            const int64_t j = jt + q;
-            if (j < n) { sx[q] = x[j]; sy[q] = y[j]; sz[q] = z[j]; sm[q] = mass[j]; }
-            else { sx[q] = 0.0; sy[q] = 0.0; sz[q] = 0.0; sm[q] = 0.0; }
+    const int64_t nb = (n + WG - 1) / WG;
+    const int64_t blk[2] = {(int64_t)blockIdx.x, nb - 1 - (int64_t)blockIdx.x};
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1 && blk[1] == blk[0]) break;
+        const int64_t i0 = blk[h] * WG;
+        const int64_t i = i0 + threadIdx.x;
+        const int64_t ii = i < n ? i : n - 1;
+        const double xi = x[ii], yi = y[ii], zi = z[ii];
+        double tot = 0.0;
+        for (int64_t jt = i0; jt < n; jt += TILE) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < TILE; q += WG) {
+                const int64_t j = jt + q;
+                if (j < n) { sx[q] = x[j]; sy[q] = y[j]; sz[q] = z[j]; sm[q] = mass[j]; }
+            }
+            __syncthreads();
+            const int lim = (int)min<int64_t>(TILE, n - jt);
+            double part = 0.0;
+            if (jt == i0) {
+                for (int q = 0; q < lim; ++q) {
+                    const double dx = sx[q] - xi, dy = sy[q] - yi, dz = sz[q] - zi;
+                    const bool upper = jt + q > i;
+                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                    part = fma(upper ? sm[q] : 0.0, rsqrt64(upper ? r2 : 1.0), part);
+                }
+            } else {
+                for (int q = 0; q < lim; ++q) {
+                    const double dx = sx[q] - xi, dy = sy[q] - yi, dz = sz[q] - zi;
+                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                    part = fma(sm[q], rsqrt64(r2), part);
+                }
+            }
+            tot += part;
         }
-        __syncthreads();
-        double part = 0.0;
-        for (int q = 0; q < TILE; ++q) {
-            const double dx = sx[q] - xi, dy = sy[q] - yi, dz = sz[q] - zi;
-            const bool self = (jt + q == i);
-            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-            const double w = self ? 0.0 : sm[q];
-            part = fma(w, rsqrt64(self ? 1.0 : r2), part);
-        }
-        tot += part;
+        if (i < n)
+            rows[i] = mass[i] * tot;
     }
-    if (i < n)
-        rows[i] = mass[i] * tot;
 }
 
 // Neumaier compensated accumulation.
@@ -405,7 +422,7 @@ struct CSum {
     }
 };
 
-// One workgroup: out[0] = sum_i m_i |v_i|^2 / 2, out[1] = -sum_i rows[i] / 2, each
+// One workgroup: out[0] = sum_i m_i |v_i|^2 / 2, out[1] = -sum_i rows[i], each
 // lane summing a strided slice in order, then lane 0 combining lanes in order.
 __global__ __launch_bounds__(WG) void energy_total_kernel(const double *vx, const double *vy,
                                                           const double *vz, const double *mass,
@@ -428,7 +445,7 @@ __global__ __launch_bounds__(WG) void energy_total_kernel(const double *vx, cons
             p2.add(ps[t]); p2.add(pc[t]);
         }
         out[0] = k2.s + k2.c;
-        out[1] = -0.5 * (p2.s + p2.c);
+        out[1] = -(p2.s + p2.c);
     }
 }
 
@@ -436,7 +453,7 @@ hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *
                          hipStream_t st)
 {
     const int64_t n = s.n;
-    const unsigned blocks = (unsigned)((n + WG - 1) / WG);
+    const unsigned blocks = (unsigned)(((n + WG - 1) / WG + 1) / 2);
     hipLaunchKernelGGL(potential_rows_kernel, dim3(blocks), dim3(WG), 0, st, s.x, s.y, s.z, s.m,
                        n, eps2, rows);
     hipError_t e = hipGetLastError();

@@ -24,11 +24,12 @@
 namespace nbk {
 
 // T[(3a+b) m + k] = sum_{j != i} m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),
-// r = xp_j - xp_i, s = |r|^2 + eps^2, for the k-th listed body i.  Each thread
-// sums a strided slice of j in order; the 256 partial sums are combined in a
-// fixed tree order.
+// r = xp_j - xp_i, s = |r|^2 + eps^2, for the k-th listed body i of an item, into
+// the item's `tensor` (and the body's time t_i into its `t_out`, when set).
+// Each thread sums a strided slice of j in order; the 256 partial sums are
+// combined in a fixed tree order.
 __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int64_t *starts,
-                                                   int n_items, double *T)
+                                                   int n_items)
 {
     __shared__ double part[9][WG];
     const int it_k = find_item(starts, n_items, blockIdx.x);
@@ -73,14 +74,16 @@ __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int6
         __syncthreads();
     }
     if (threadIdx.x < 9)
-        T[threadIdx.x * m + k] = part[threadIdx.x][0];
+        p.tensor[threadIdx.x * m + k] = part[threadIdx.x][0];
+    if (threadIdx.x == 9 && p.t_out)
+        p.t_out[k] = p.s.t[i];
 }
 
-hipError_t launch_tidal(const Table &t, double *T, hipStream_t st)
+hipError_t launch_tidal(const Table &t, hipStream_t st)
 {
     if (t.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(tidal_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
-                       t.n, T);
+                       t.n);
     return hipGetLastError();
 }
 
@@ -290,7 +293,151 @@ nb_status nb_groups_run(nb_ctx *ctx, int32_t n, const int32_t *idx, const double
     return NB_OK;
 }
 
+namespace {
+
+// Pair indices valid: in [0, n), no index twice.  `seen` has n entries.
+bool pairs_valid(int64_t n, int32_t n_pairs, const int64_t *pairs, std::vector<char> &seen)
+{
+    if (n < 0 || n_pairs < 0 || (n_pairs > 0 && !pairs) || 2 * (int64_t)n_pairs > n) return false;
+    seen.assign((size_t)n, 0);
+    for (int64_t q = 0; q < 2 * (int64_t)n_pairs; ++q) {
+        const int64_t i = pairs[q];
+        if (i < 0 || i >= n || seen[(size_t)i]) return false;
+        seen[(size_t)i] = 1;
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
+
+nb_status nb_pairs_reduce(int64_t n, const double *x, const double *v, const double *m,
+                          int32_t n_pairs, const int64_t *pairs, double *xr, double *vr,
+                          double *mr, double *M, double *r, double *w)
+{
+    std::vector<char> in_pair;
+    if (!pairs_valid(n, n_pairs, pairs, in_pair)) return NB_EINVAL;
+    if (n > 0 && (!x || !v || !m || !xr || !vr || !mr)) return NB_EINVAL;
+    if (n_pairs > 0 && (!M || !r || !w)) return NB_EINVAL;
+    int64_t q = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (in_pair[(size_t)i]) continue;
+        for (int d = 0; d < 3; ++d) {
+            xr[3 * q + d] = x[3 * i + d];
+            vr[3 * q + d] = v[3 * i + d];
+        }
+        mr[q++] = m[i];
+    }
+    for (int32_t k = 0; k < n_pairs; ++k, ++q) {
+        const int64_t a = pairs[2 * k], b = pairs[2 * k + 1];
+        const double mt = m[a] + m[b];
+        for (int d = 0; d < 3; ++d) {
+            xr[3 * q + d] = (m[a] * x[3 * a + d] + m[b] * x[3 * b + d]) / mt;
+            vr[3 * q + d] = (m[a] * v[3 * a + d] + m[b] * v[3 * b + d]) / mt;
+            r[3 * k + d] = x[3 * b + d] - x[3 * a + d];
+            w[3 * k + d] = v[3 * b + d] - v[3 * a + d];
+        }
+        mr[q] = mt;
+        M[k] = mt;
+    }
+    return NB_OK;
+}
+
+nb_status nb_pairs_members(int64_t n, const double *xr, const double *vr, const double *m,
+                           int32_t n_pairs, const int64_t *pairs, const double *r,
+                           const double *w, double *x, double *v)
+{
+    std::vector<char> in_pair;
+    if (!pairs_valid(n, n_pairs, pairs, in_pair)) return NB_EINVAL;
+    if (n > 0 && (!x || !v || !m || !xr || !vr)) return NB_EINVAL;
+    if (n_pairs > 0 && (!r || !w)) return NB_EINVAL;
+    int64_t q = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (in_pair[(size_t)i]) continue;
+        for (int d = 0; d < 3; ++d) {
+            x[3 * i + d] = xr[3 * q + d];
+            v[3 * i + d] = vr[3 * q + d];
+        }
+        ++q;
+    }
+    for (int32_t k = 0; k < n_pairs; ++k, ++q) {
+        const int64_t a = pairs[2 * k], b = pairs[2 * k + 1];
+        const double mt = m[a] + m[b], fa = m[b] / mt, fb = m[a] / mt;
+        for (int d = 0; d < 3; ++d) {
+            x[3 * a + d] = xr[3 * q + d] - fa * r[3 * k + d];
+            x[3 * b + d] = xr[3 * q + d] + fb * r[3 * k + d];
+            v[3 * a + d] = vr[3 * q + d] - fa * w[3 * k + d];
+            v[3 * b + d] = vr[3 * q + d] + fb * w[3 * k + d];
+        }
+    }
+    return NB_OK;
+}
+
+nb_status nb_pairs_energy(int32_t n_pairs, const double *m, const int64_t *pairs,
+                          const double *r, const double *w, const double *T, double *out)
+{
+    if (!out || n_pairs < 0 || (n_pairs > 0 && (!m || !pairs || !r || !w || !T)))
+        return NB_EINVAL;
+    double s = 0.0, c = 0.0;     // Neumaier sum over the pairs in order
+    for (int32_t k = 0; k < n_pairs; ++k) {
+        const double ma = m[pairs[2 * k]], mb = m[pairs[2 * k + 1]];
+        const double mt = ma + mb, mu = ma * mb / mt;
+        const double *rk = r + 3 * k, *wk = w + 3 * k, *Tk = T + 9 * k;
+        double w2 = 0.0, r2 = 0.0, rTr = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            w2 += wk[a] * wk[a];
+            r2 += rk[a] * rk[a];
+            for (int b = 0; b < 3; ++b)
+                rTr += rk[a] * Tk[3 * a + b] * rk[b];
+        }
+        if (!(r2 > 0.0)) return NB_EINVAL;
+        const double e = mu * (0.5 * w2 - mt / sqrt(r2) - 0.5 * rTr);
+        const double t = s + e;
+        c += fabs(s) >= fabs(e) ? (s - t) + e : (e - t) + s;
+        s = t;
+    }
+    *out = s + c;
+    return NB_OK;
+}
+
+nb_status nb_pairs_perturbation(int32_t n_pairs, const double *M, const double *r,
+                                const double *w, const double *T, double *a, double *gamma)
+{
+    if (n_pairs < 0 || (n_pairs > 0 && (!M || !a || !gamma || (r && !w)))) return NB_EINVAL;
+    for (int32_t k = 0; k < n_pairs; ++k) {
+        if (r) {
+            const double *rk = r + 3 * k, *wk = w + 3 * k;
+            const double rn = sqrt(rk[0] * rk[0] + rk[1] * rk[1] + rk[2] * rk[2]);
+            const double w2 = wk[0] * wk[0] + wk[1] * wk[1] + wk[2] * wk[2];
+            const double inv_a = 2.0 / rn - w2 / M[k];
+            a[k] = inv_a > 0.0 ? 1.0 / inv_a : INFINITY;
+        }
+        double t2 = 0.0;
+        if (T)
+            for (int q = 0; q < 9; ++q)
+                t2 += T[9 * k + q] * T[9 * k + q];
+        const double d = 2.0 * a[k];
+        gamma[k] = a[k] > 0.0 && isfinite(a[k]) ? sqrt(t2) * d * d * d / M[k] : INFINITY;
+    }
+    return NB_OK;
+}
+
+nb_status nb_pairs_split_energy(int32_t n_pairs, const double *m, const int64_t *pairs,
+                                const double *r, double eps, double *out)
+{
+    if (!out || n_pairs < 0 || !(eps >= 0.0) || (n_pairs > 0 && (!m || !pairs || !r)))
+        return NB_EINVAL;
+    double s = 0.0;
+    for (int32_t k = 0; k < n_pairs; ++k) {
+        const double *rk = r + 3 * k;
+        const double r2 = rk[0] * rk[0] + rk[1] * rk[1] + rk[2] * rk[2];
+        if (!(r2 > 0.0)) return NB_EINVAL;
+        s += m[pairs[2 * k]] * m[pairs[2 * k + 1]] * (1.0 / sqrt(r2) - 1.0 / sqrt(r2 + eps * eps));
+    }
+    *out = s;
+    return NB_OK;
+}
 
 nb_status nb_kepler_drift(double M, const double *r0, const double *v0, double dt, double *r1,
                           double *v1)

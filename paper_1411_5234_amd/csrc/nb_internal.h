@@ -54,13 +54,15 @@ struct Item {
     double eps2;                 // softening squared
     double t_next;               // block time
     int64_t j0, j1;              // force j-range
-    int64_t chunk;               // j per chunk (multiple of TILE)
+    int64_t chunk;               // j per chunk (a multiple of the kernel's work granule)
     int32_t m;                   // active block size
     int32_t b;                   // j-chunks (Bfactor)
     int64_t sel_slice;           // selection: bodies per workgroup
     int64_t sel_off;             // selection: first slot of this item's temporaries
     int32_t sel_blocks;          // selection: workgroups
     int32_t red_lanes;           // partial reduction: lanes per output value
+    double *tensor;              // tidal tensor output, rows (3a+b)*m + k
+    double *t_out;               // tidal: time of each listed body (or null)
 };
 
 // Per-item selection results written by the selection kernels.

@@ -109,30 +109,15 @@ __device__ __forceinline__ void diff(const JBody<true> &j, const IPos<true> &i, 
     dz = (j.zh - i.zh) + (j.zl - i.zl);
 }
 
-#ifndef NBK_KAHAN
-#define NBK_KAHAN 0
-#endif
 #ifndef NBK_MIXED_WAVES
 #define NBK_MIXED_WAVES 1
 #endif
 
-// Running total of the FP32 run sums: FP64, or (NBK_KAHAN) an FP32 Kahan pair.
+// Running FP64 total of a lane's FP32 run sums.
 struct Total {
-#if NBK_KAHAN
-    float s = 0.f, c = 0.f;
-    __device__ __forceinline__ void add(float v)
-    {
-        const float y = v - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-#else
     double s = 0.0;
     __device__ __forceinline__ void add(float v) { s += (double)v; }
     __device__ __forceinline__ double value() const { return s; }
-#endif
 };
 
 // LDS tile of a mixed or DS kernel: 40 bytes per j-body either way.

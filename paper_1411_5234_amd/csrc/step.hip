@@ -325,13 +325,20 @@ __global__ __launch_bounds__(WG) void init_steps_kernel(const Item *items, const
 {
     const int k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[k];
-    const int64_t i = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
+    const int64_t q = ((int64_t)blockIdx.x - starts[k]) * WG + threadIdx.x;
     const nb_system &s = p.s;
-    const int64_t n = s.n;
-    if (i >= n)
+    // every body (t = 0), or the listed bodies at the item's time t_next; the
+    // acc/jerk rows hold one entry per body or per listed body
+    const int64_t cnt = p.i_idx ? (int64_t)p.m : s.n;
+    if (q >= cnt)
         return;
-    const double ax = p.acc[i], ay = p.acc[n + i], az = p.acc[2 * n + i];
-    const double jx = p.jerk[i], jy = p.jerk[n + i], jz = p.jerk[2 * n + i];
+    int64_t i = p.i_idx ? (int64_t)p.i_idx[q] : q;
+    if (i < 0 || i >= s.n) {
+        atomicOr(p.status, (int)NBK_EINDEX);
+        return;
+    }
+    const double ax = p.acc[q], ay = p.acc[cnt + q], az = p.acc[2 * cnt + q];
+    const double jx = p.jerk[q], jy = p.jerk[cnt + q], jz = p.jerk[2 * cnt + q];
     s.ax[i] = ax; s.ay[i] = ay; s.az[i] = az;
     s.jx[i] = jx; s.jy[i] = jy; s.jz[i] = jz;
     const double an = norm3(ax, ay, az), jn = norm3(jx, jy, jz);
@@ -346,7 +353,7 @@ __global__ __launch_bounds__(WG) void init_steps_kernel(const Item *items, const
         step *= 0.5;
     if (step < dt_min)
         err |= NBK_ERANGE;
-    s.t[i] = 0.0;
+    s.t[i] = p.i_idx ? p.t_next : 0.0;
     s.dt[i] = step;
     if (err)
         atomicOr(p.status, err);

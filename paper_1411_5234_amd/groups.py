@@ -33,6 +33,114 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+class PairSet:
+    """Host state of the bound pairs of one system: per pair its total mass M, the
+    relative coordinate r = x2 - x1 and velocity w = v2 - v1 (host arrays the CPU
+    threads advance in place), the tidal tensor T at the pair's own time tpair, and
+    a status word.  The arithmetic (reduction to centre-of-mass bodies, members,
+    pair energy, pair advance) is the library's (nb_pairs_*, nb_groups_advance*);
+    this class holds the arrays and the queue of pending advances."""
+
+    MAX_QUEUED = 4096
+
+    def __init__(self, L, x, v, m, pairs):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        self.m = np.ascontiguousarray(m, dtype=np.float64)
+        self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+        self.L = L
+        self.n = self.m.shape[0]
+        self.np = self.pairs.shape[0]
+        nr = self.n - self.np
+        self.xr, self.vr = np.empty((nr, 3)), np.empty((nr, 3))
+        self.mr = np.empty(nr)
+        k = max(self.np, 1)
+        self.M = np.zeros(k)
+        self.r, self.w = np.zeros((k, 3)), np.zeros((k, 3))
+        rc = L.nb_pairs_reduce(self.n, _p(x), _p(v), _p(self.m), self.np, _p(self.pairs),
+                               _p(self.xr), _p(self.vr), _p(self.mr), _p(self.M), _p(self.r),
+                               _p(self.w))
+        if rc != 0:
+            raise ValueError("pairs must be distinct indices in [0, n)")
+        self.cm0 = nr - self.np                  # first centre-of-mass body of the reduced system
+        self.T = np.zeros((k, 9))
+        self.tpair = np.zeros(k)
+        self.status = np.zeros(k, dtype=np.int32)
+        self._pending = []
+        self.advanced = 0
+
+    def due(self, tcm, t_block):
+        """Pairs whose centre of mass was in the block at t_block (tcm: the
+        centre-of-mass bodies' times after that block) and are not yet there."""
+        idx = np.nonzero(tcm[: self.np] == t_block)[0]
+        return idx[self.tpair[idx] < t_block]
+
+    def advance(self, ctx, idx, t_block, Tn, per_period, max_sub, queue=True):
+        """Advance pairs idx from their own times to t_block, the tidal tensor linear
+        from T (at tpair) to Tn (at t_block); queued on the context's CPU thread
+        (queue=True) or run here.  Returns the seconds spent here."""
+        if idx.size == 0:
+            return 0.0
+        rows = np.ascontiguousarray(idx, dtype=np.int32)
+        H = np.ascontiguousarray(t_block - self.tpair[idx])
+        T0 = np.ascontiguousarray(self.T[idx])
+        T1 = np.ascontiguousarray(Tn)
+        self.T[idx] = Tn
+        self.tpair[idx] = t_block
+        self.advanced += idx.size
+        args = (int(idx.size), _p(rows), _p(self.M), _p(self.r), _p(self.w), _p(H), _p(T0),
+                _p(T1), int(per_period), int(max_sub), _p(self.status))
+        if queue:
+            if len(self._pending) >= self.MAX_QUEUED:
+                self.drain(ctx)
+            self._pending.append((rows, H, T0, T1))
+            ctx._check(ctx.L.nb_groups_advance_async(ctx.h, *args))
+            return 0.0
+        t0 = time.perf_counter()
+        rc = ctx.L.nb_groups_advance(*args)
+        dt = time.perf_counter() - t0
+        if rc != 0:
+            self.fail(rc)
+        return dt
+
+    def drain(self, ctx):
+        """Wait until every queued advance has run (r, w current); raises if a pair
+        of this set became unbound."""
+        if not self._pending:
+            return 0.0
+        t0 = time.perf_counter()
+        ctx.L.nb_groups_wait(ctx.h)
+        self._pending.clear()
+        if np.any(self.status[: self.np] != 0):
+            self.fail(-7)
+        return time.perf_counter() - t0
+
+    def fail(self, rc):
+        bad = np.nonzero(self.status[: self.np] != 0)[0]
+        raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
+
+    def members(self, xr, vr):
+        """(x, v) of all n original bodies from the reduced state and r, w."""
+        x, v = np.empty((self.n, 3)), np.empty((self.n, 3))
+        xr = np.ascontiguousarray(xr, dtype=np.float64)
+        vr = np.ascontiguousarray(vr, dtype=np.float64)
+        rc = self.L.nb_pairs_members(self.n, _p(xr), _p(vr), _p(self.m), self.np, _p(self.pairs),
+                                     _p(self.r), _p(self.w), _p(x), _p(v))
+        if rc != 0:
+            raise ValueError("bad reduced state")
+        return x, v
+
+    def energy(self):
+        """The pairs' two-body and tidal energy (the pair part of the conserved
+        quantity)."""
+        out = C.c_double()
+        rc = self.L.nb_pairs_energy(self.np, _p(self.m), _p(self.pairs), _p(self.r), _p(self.w),
+                                    _p(self.T), C.byref(out))
+        if rc != 0:
+            raise ValueError("degenerate pair")
+        return out.value
+
+
 class GroupedIntegrator:
     """Block-step integration of x, v, m (numpy, n bodies) with the given bound pairs
     (index pairs into x) carried as centre-of-mass bodies.
@@ -43,33 +151,12 @@ class GroupedIntegrator:
 
     def __init__(self, ctx: Context, x, v, m, pairs, p: Params, per_period: int = 32,
                  max_sub: int = 1 << 20, overlap: bool = True, device="cuda"):
-        x = np.asarray(x, dtype=np.float64)
-        v = np.asarray(v, dtype=np.float64)
-        m = np.asarray(m, dtype=np.float64)
-        pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
-        n = m.shape[0]
-        if pairs.size and (pairs.min() < 0 or pairs.max() >= n or
-                           np.unique(pairs.ravel()).size != pairs.size):
-            raise ValueError("pairs must be distinct indices in [0, n)")
-        self.ctx, self.p, self.n = ctx, p, n
+        self.ctx, self.p = ctx, p
+        self.ps = PairSet(ctx.L, x, v, m, pairs)
+        self.n, self.np, self.cm0 = self.ps.n, self.ps.np, self.ps.cm0
+        self.pairs = self.ps.pairs
         self.per_period, self.max_sub, self.overlap = int(per_period), int(max_sub), overlap
-        self.m = m
-        self.pairs = pairs
-        in_pair = np.zeros(n, dtype=bool)
-        in_pair[pairs.ravel()] = True
-        self.singles = np.nonzero(~in_pair)[0]
-        i, j = pairs[:, 0], pairs[:, 1]
-        self.M = np.ascontiguousarray(m[i] + m[j])
-        xc = (m[i, None] * x[i] + m[j, None] * x[j]) / self.M[:, None]
-        vc = (m[i, None] * v[i] + m[j, None] * v[j]) / self.M[:, None]
-        self.r = np.ascontiguousarray(x[j] - x[i])
-        self.w = np.ascontiguousarray(v[j] - v[i])
-        self.np = pairs.shape[0]
-        self.cm0 = self.singles.size
-        xr = np.concatenate([x[self.singles], xc])
-        vr = np.concatenate([v[self.singles], vc])
-        mr = np.concatenate([m[self.singles], self.M])
-        self.sys = System.from_arrays(xr, vr, mr, device=device,
+        self.sys = System.from_arrays(self.ps.xr, self.ps.vr, self.ps.mr, device=device,
                                       fp32_copies=(p.precision != "fp64"))
         self.it = Integrator(ctx, self.sys, p)
         k = max(self.np, 1)
@@ -77,19 +164,30 @@ class GroupedIntegrator:
         self.T_dev = torch.zeros(9 * k, dtype=torch.float64, device=device)
         self.T_host = torch.zeros(9 * k, dtype=torch.float64).pin_memory()
         self.tcm_host = torch.zeros(k, dtype=torch.float64).pin_memory()
-        self.T = np.zeros((k, 9))                 # tensor at each pair's own time
-        self.tpair = np.zeros(k)
-        self.status = np.zeros(k, dtype=np.int32)
-        self._pending = []                        # buffers of the queued advances
         self._prev_t = None                       # block time of the last GPU step
-        self.cpu_pairs_advanced = 0
         self.cpu_seconds = 0.0                    # pair advance run on this thread
         self.wait_seconds = 0.0                   # time blocked waiting for the queue
+
+    @property
+    def M(self):
+        return self.ps.M[: self.np]
+
+    @property
+    def r(self):
+        return self.ps.r[: self.np]
+
+    @property
+    def w(self):
+        return self.ps.w[: self.np]
+
+    @property
+    def cpu_pairs_advanced(self):
+        return self.ps.advanced
 
     def __del__(self):
         # the CPU thread writes into this object's arrays: never free them under it
         try:
-            if self._pending:
+            if self.ps._pending:
                 self.ctx.L.nb_groups_wait(self.ctx.h)
         except Exception:
             pass
@@ -114,58 +212,24 @@ class GroupedIntegrator:
         self.it.startup()
         self._tidal_to_host()
         self.ctx.sync()
-        self.T[: self.np] = self._host_tensor()
-        self.tpair[:] = 0.0
+        self.ps.T[: self.np] = self._host_tensor()
+        self.ps.tpair[:] = 0.0
 
     # ---- CPU side --------------------------------------------------------------------
-    MAX_QUEUED = 4096
-
-    def _fail(self, rc):
-        bad = np.nonzero(self.status[: self.np] != 0)[0]
-        raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
-
     def _drain(self):
-        """Wait until every queued pair advance has run (self.r, self.w current)."""
-        if not self._pending:
-            return
-        t0 = time.perf_counter()
-        rc = self.ctx.L.nb_groups_wait(self.ctx.h)
-        self.wait_seconds += time.perf_counter() - t0
-        self._pending.clear()
-        if rc != 0:
-            self._fail(rc)
+        """Wait until every queued pair advance has run (r, w current)."""
+        self.wait_seconds += self.ps.drain(self.ctx)
 
     def _launch(self):
         """Queue the advance of the pairs whose centre of mass was in the previous
         block (their tensors and times are on the host after the selection's sync)."""
         if self._prev_t is None or self.np == 0:
             return
-        tcm = self.tcm_host.numpy()[: self.np]
-        idx = np.nonzero(tcm == self._prev_t)[0]
-        idx = idx[self.tpair[idx] < self._prev_t]
-        if idx.size == 0:
-            return
-        Tn = self._host_tensor()[idx]
-        rows = np.ascontiguousarray(idx, dtype=np.int32)
-        H = np.ascontiguousarray(self._prev_t - self.tpair[idx])
-        T0 = np.ascontiguousarray(self.T[idx])
-        T1 = np.ascontiguousarray(Tn)
-        self.T[idx] = Tn
-        self.tpair[idx] = self._prev_t
-        self.cpu_pairs_advanced += idx.size
-        args = (int(idx.size), _p(rows), _p(self.M), _p(self.r), _p(self.w), _p(H), _p(T0),
-                _p(T1), self.per_period, self.max_sub, _p(self.status))
-        if self.overlap:
-            if len(self._pending) >= self.MAX_QUEUED:
-                self._drain()
-            self._pending.append((rows, H, T0, T1))
-            self.ctx._check(self.ctx.L.nb_groups_advance_async(self.ctx.h, *args))
-        else:
-            t0 = time.perf_counter()
-            rc = self.ctx.L.nb_groups_advance(*args)
-            self.cpu_seconds += time.perf_counter() - t0
-            if rc != 0:
-                self._fail(rc)
+        idx = self.ps.due(self.tcm_host.numpy(), self._prev_t)
+        if idx.size:
+            self.cpu_seconds += self.ps.advance(self.ctx, idx, self._prev_t,
+                                                self._host_tensor()[idx], self.per_period,
+                                                self.max_sub, queue=self.overlap)
 
     # ---- block steps -----------------------------------------------------------------
     def step(self):
@@ -201,28 +265,10 @@ class GroupedIntegrator:
         same time (after run)."""
         self._drain()
         st = self.sys.state_numpy()
-        x, v = np.empty((self.n, 3)), np.empty((self.n, 3))
-        ns = self.cm0
-        x[self.singles], v[self.singles] = st["x"][:ns], st["v"][:ns]
-        i, j = self.pairs[:, 0], self.pairs[:, 1]
-        fi = (self.m[j] / self.M)[:, None]
-        fj = (self.m[i] / self.M)[:, None]
-        x[i] = st["x"][ns:] - fi * self.r
-        x[j] = st["x"][ns:] + fj * self.r
-        v[i] = st["v"][ns:] - fi * self.w
-        v[j] = st["v"][ns:] + fj * self.w
-        return x, v
+        return self.ps.members(st["x"], st["v"])
 
     def energy(self):
         """Reduced system's energy (softened) + each pair's two-body energy and tidal
         energy -mu r.T.r / 2 (the quantity the scheme conserves)."""
         self._drain()
-        er = self.ctx.energy(self.sys, self.p.eps)[2]
-        if self.np == 0:
-            return er
-        i, j = self.pairs[:, 0], self.pairs[:, 1]
-        mu = self.m[i] * self.m[j] / self.M
-        T = self.T[: self.np].reshape(-1, 3, 3)
-        tid = np.einsum("ka,kab,kb->k", self.r, T, self.r)
-        rr = np.linalg.norm(self.r, axis=1)
-        return er + float((mu * (0.5 * (self.w ** 2).sum(1) - self.M / rr - 0.5 * tid)).sum())
+        return self.ctx.energy(self.sys, self.p.eps)[2] + self.ps.energy()

@@ -211,7 +211,9 @@ def with_binaries(n: int, seed: int, frac_members: float = 0.10, a_lo: float = 1
     v[2 * n_pairs:] = cm.v[n_pairs:]
     m[2 * n_pairs:] = singles
     meta = {"kind": "plummer+binaries", "seed": int(seed), "n": n, "n_pairs": n_pairs,
-            "a": a, "e": e}
+            "a": a, "e": e,
+            # the members of pair k are bodies 2k and 2k + 1
+            "pairs": np.arange(2 * n_pairs, dtype=np.int64).reshape(-1, 2)}
     return Snapshot(x, v, m, meta)
 
 

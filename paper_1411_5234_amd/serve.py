@@ -29,7 +29,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NbBatchItem, NbError, NbHermite6, PRECISIONS
+from ._lib import NbBatchItem, NbError, NbHermite6, NbTidalItem, PRECISIONS
+from .groups import PairSet
 from .nbody import Context, Hermite6, System
 
 
@@ -46,6 +47,12 @@ class Result:
     energy1: float = float("nan")
     error: str | None = None
     final: dict | None = None    # final state (when keep_state is set)
+    # grouped systems: energy0/1 are the scheme's conserved quantity (reduced system
+    # plus the pairs' two-body and tidal energies); these are the full N-body
+    # energies of the reconstructed members
+    direct0: float = float("nan")
+    direct1: float = float("nan")
+    pairs: int = 0
 
     @property
     def latency(self) -> float:
@@ -59,12 +66,24 @@ class Result:
 class _Slot:
     """One resident system: device state, work buffers and its batch item."""
 
-    def __init__(self, req, device, precision, now, order=4):
+    def __init__(self, req, device, precision, now, order=4, L=None, groups=False):
         snap = req.snapshot()
         self.req = req
-        self.n = snap.n
-        self.sys = System.from_arrays(snap.x, snap.v, snap.m, device=device,
-                                      fp32_copies=(precision != "fp64"))
+        self.snap = snap
+        self.ps = None                     # PairSet of a grouped system
+        self.prev_t = None                 # grouped: block time of its last block step
+        self.tid_off = 0                   # grouped: offset of its tidal rows
+        pairs = snap.meta.get("pairs") if groups else None
+        if pairs is not None and len(pairs):
+            self.ps = PairSet(L, snap.x, snap.v, snap.m, pairs)
+            self.n = self.ps.n - self.ps.np
+            self.sys = System.from_arrays(self.ps.xr, self.ps.vr, self.ps.mr, device=device,
+                                          fp32_copies=(precision != "fp64"))
+            self.cm_idx = torch.arange(self.ps.cm0, self.n, dtype=torch.int32, device=device)
+        else:
+            self.n = snap.n
+            self.sys = System.from_arrays(snap.x, snap.v, snap.m, device=device,
+                                          fp32_copies=(precision != "fp64"))
         n1 = max(self.n, 1)
         self.i_idx = torch.zeros(n1, dtype=torch.int32, device=device)
         self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=device)
@@ -82,7 +101,9 @@ class _Slot:
         if order == 6:
             self.h6 = Hermite6(self.sys, fp32_copies=(precision != "fp64"))
             self.snap6 = torch.zeros(3 * n1, dtype=torch.float64, device=device)
-        self.result = Result(req.rid, self.n, req.arrival, now, float("nan"))
+        self.result = Result(req.rid, snap.n, req.arrival, now, float("nan"))
+        if self.ps is not None:
+            self.result.pairs = self.ps.np
 
 
 def footprint_bytes(n: int, precision: str = "mixed", order: int = 4) -> int:
@@ -150,11 +171,25 @@ class Server:
                  memory_budget: int | None = None, max_slots: int = 256,
                  eta: float | None = None, eta_s: float = 0.01, dt_max: float = 2.0 ** -3,
                  dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
-                 order: int = 4, lanes: int = 0):
+                 order: int = 4, lanes: int = 0, groups: bool = False, per_period: int = 32,
+                 max_sub: int = 1 << 20):
         if precision not in PRECISIONS:
             raise ValueError(precision)
         if order not in (4, 6):
             raise ValueError("order must be 4 or 6")
+        if groups and order != 4:
+            raise ValueError("grouped pairs are served at 4th order")
+        # groups: requests whose initial condition lists bound pairs carry each pair
+        # as one body at its centre of mass; its relative orbit advances on the
+        # context's CPU thread (tidal kicks and exact two-body drifts) while the
+        # GPU runs the block steps of every resident system
+        self.groups = bool(groups)
+        self.per_period, self.max_sub = int(per_period), int(max_sub)
+        self._tid_stale = True
+        self._tid_items = None
+        self._tid_dev = None
+        self._tid_host = None
+        self._tid_slots = []
         self.order = order
         _lib.force_plan(1, 1, "mixed", lanes)     # raises on a target out of range
         self.lanes = int(lanes)
@@ -212,28 +247,128 @@ class Server:
             req = self.adm.admit_next()
             if req is None:
                 return
-            slot = _Slot(req, self.device, self.precision, self._now(), self.order)
+            slot = _Slot(req, self.device, self.precision, self._now(), self.order, self.L,
+                         self.groups)
             slot.item.lanes = self.lanes
+            if slot.ps is not None:
+                self._pairs_startup(slot)
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
+                if slot.ps is not None:
+                    slot.result.energy0 += slot.ps.energy()
+                    slot.result.direct0 = self._direct_energy(slot, slot.snap.x, slot.snap.v)
             self._sync_items()
             self.slots.append(slot)
             self._arr = None
+            self._tid_stale = True
+
+    # ---- grouped pairs -----------------------------------------------------------
+    def _pairs_startup(self, slot):
+        """The tidal tensor at every pair's centre of mass at t = 0 (the predicted set
+        of a new system is its initial state)."""
+        ps = slot.ps
+        T = torch.zeros(9 * ps.np, dtype=torch.float64, device=self.device)
+        self._check(self.L.nb_tidal_active(self.ctx.h, slot.sys.ref, slot.cm_idx.data_ptr(), ps.np,
+                                           0, slot.n, float(slot.req.eps), T.data_ptr()))
+        self.ctx.sync()
+        ps.T[: ps.np] = T.cpu().numpy().reshape(9, ps.np).T
+        ps.tpair[:] = 0.0
+
+    def _direct_energy(self, slot, x, v):
+        """Full N-body energy of the members (a temporary system on the device)."""
+        full = System.from_arrays(x, v, slot.snap.m, device=self.device, fp32_copies=False)
+        return self.ctx.energy(full, slot.req.eps)[2]
+
+    def _grouped(self):
+        return [sl for sl in self.slots if sl.ps is not None]
+
+    def _queue_pairs(self):
+        """Queue the advance of every grouped system's pairs that were in its last
+        block; their tensors and times reached the pinned host buffer before the
+        selection's host sync of this iteration."""
+        if self._tid_host is None:
+            return
+        host = self._tid_host.numpy()
+        for sl in self._tid_slots:
+            if sl.prev_t is None or sl not in self.slots:
+                continue
+            k, o = sl.ps.np, sl.tid_off
+            tcm = host[o + 9 * k: o + 10 * k]
+            idx = sl.ps.due(tcm, sl.prev_t)
+            if idx.size:
+                Tn = host[o: o + 9 * k].reshape(9, k).T[idx]
+                sl.ps.advance(self.ctx, idx, sl.prev_t, Tn, self.per_period, self.max_sub)
+
+    def _tidal_layout(self):
+        """One device buffer and one pinned host buffer for the tidal outputs of every
+        resident grouped system (10 doubles per pair: the tensor, then the centre of
+        mass's time), rebuilt when the resident set changes."""
+        gs = self._grouped()
+        off = 0
+        for sl in gs:
+            sl.tid_off = off
+            off += 10 * sl.ps.np
+        self._tid_slots = gs
+        self._tid_dev = torch.zeros(max(off, 1), dtype=torch.float64, device=self.device)
+        self._tid_host = torch.zeros(max(off, 1), dtype=torch.float64).pin_memory()
+        items = (NbTidalItem * max(len(gs), 1))()
+        base = self._tid_dev.data_ptr()
+        for q, sl in enumerate(gs):
+            it = items[q]
+            it.sys = sl.sys._struct
+            it.i_idx = sl.cm_idx.data_ptr()
+            it.m = sl.ps.np
+            it.eps = float(sl.req.eps)
+            it.tensor = base + 8 * sl.tid_off
+            it.t_out = base + 8 * (sl.tid_off + 9 * sl.ps.np)
+            it.status = sl.status.data_ptr()
+        self._tid_items = items
+        self._tid_stale = False
+
+    def _tidal(self, ran_slots):
+        """Tidal tensors of the grouped systems that ran a block step this iteration,
+        from the predicted set of that step, copied to the pinned host buffer."""
+        if self._tid_stale:
+            self._tidal_layout()
+        if not self._tid_slots:
+            return
+        items = self._tid_items
+        for q, sl in enumerate(self._tid_slots):
+            items[q].m = sl.ps.np if sl in ran_slots else 0
+        self._check(self.L.nb_tidal_active_batch(self.ctx.h, items, len(self._tid_slots)))
+        with torch.cuda.stream(self.ctx.stream):
+            self._tid_host.copy_(self._tid_dev, non_blocking=True)
 
     def _retire(self, slot: _Slot, error: str | None):
         self._sync_items()
         r = slot.result
+        if slot.ps is not None:
+            try:
+                slot.ps.drain(self.ctx)        # its pairs' queued advances, before reading them
+            except NbError as e:
+                error = error or "NB_EUNBOUND: %s" % e
         r.error = error
         if error is None:
             if self.energy:
                 r.energy1 = self.ctx.energy(slot.sys, slot.req.eps)[2]
-            if self.keep_state:
+            if slot.ps is not None:
+                st = slot.sys.state_numpy()
+                x, v = slot.ps.members(st["x"], st["v"])
+                if self.energy:
+                    r.energy1 += slot.ps.energy()
+                    r.direct1 = self._direct_energy(slot, x, v)
+                if self.keep_state:
+                    r.final = dict(st, members_x=x, members_v=v,
+                                   pair_r=slot.ps.r[: slot.ps.np].copy(),
+                                   pair_w=slot.ps.w[: slot.ps.np].copy())
+            elif self.keep_state:
                 r.final = slot.sys.state_numpy()
         r.finished = self._now()
         self.results.append(r)
         self.adm.release(slot.req)
         self.slots.remove(slot)
         self._arr = None
+        self._tid_stale = True
 
     # ---- one iteration: one block step of every resident system ---------------
     def _check(self, rc):
@@ -296,11 +431,23 @@ class Server:
         self._inter[ran] += inc[ran]
         self._steps[ran & ~startup] += 1
         self.iterations += 1
+        if self.groups:
+            # the previous block's pairs go to the CPU thread; this block's
+            # systems get their tidal tensors after the retirements below
+            self._queue_pairs()
+            stepped = set()
+            for k in np.flatnonzero(ran & ~startup):
+                sl = self.slots[k]
+                if sl.ps is not None:
+                    sl.prev_t = float(v["t_next"][k])
+                    stepped.add(sl)
         leave = np.flatnonzero((err != 0) | (done != 0))
         if leave.size:
             gone = [(self.slots[k], int(err[k])) for k in leave]
             for sl, e in gone:
                 self._retire(sl, _lib.STATUS.get(e, str(e)) if e != 0 else None)
+        if self.groups:
+            self._tidal(stepped)
 
     # ---- driving a request stream ------------------------------------------------
     def run(self, requests, realtime: bool = True, on_iteration=None):

@@ -3,11 +3,21 @@ import numpy as np
 import torch
 
 # Per-body gates.  FP64 path: |g - o| / |o| <= 1e-12 for acceleration and jerk.
-# Mixed and DS paths: acceleration |g - o| / S_a <= 1e-6 and jerk |g - o| / S_j <= 1e-6
-# with S_a = sum_j |a_ij| and S_j = sum_j |jerk_ij|: FP32 pair terms carry a few ulp
-# of error each, and a body's acceleration (near the centre of a cluster, where it
-# vanishes) or jerk can be a sum of terms much larger than the result.  The plain
-# relative errors are printed beside them.
+# Mixed and DS paths, two gates:
+#  - every body: |g - o| / S <= 1e-6, with S_a = sum_j |a_ij| and S_j = sum_j |jerk_ij|
+#    the magnitude scales of the pair sums;
+#  - every body whose cancellation factor kappa = S / |o| is at most KAPPA_PLAIN:
+#    the plain |g - o| / |o| <= 1e-6.
+# Why both: each FP32 pair term carries a few units of FP32 rounding (2^-24 =
+# 6e-8), so |g - o| is a few 1e-8 of the largest terms, and the plain relative
+# error grows with kappa.  An FP32 emulation of the kernel's arithmetic on 4800
+# bodies of the N = 2^20 Plummer sphere found |g - o| / S up to 4.8e-7 (jerk) and
+# 2.9e-7 (acceleration), and plain errors up to 4.5e-6 on bodies with kappa_j ~ 160;
+# with only the mandated FP32 rounding of r_j - r_i (and every later operation in
+# FP64) the worst of them still reaches 1.4e-6.  Every emulated body with
+# kappa_a <= 10 kept the plain acceleration error <= 3.4e-7, and every one with
+# kappa_j <= 5 the plain jerk error <= 6.9e-7.
+KAPPA_PLAIN = {"acc": 10.0, "jerk": 5.0}
 TOL = {"fp64": 1e-12, "mixed": 1e-6, "ds": 1e-6}
 # Snap (6th order): |g - o| / S_s with S_s = sum_j |snap_ij|.  A pair's snap term
 # passes through about a dozen FP32 roundings (the hardware reciprocal square root,
@@ -52,6 +62,22 @@ def report(tag, g_a, g_j, o_a, o_j):
     return ea, ej
 
 
+def plain_gate(tag, g, o, scale, kmax, tol=1e-6):
+    """Assert |g - o| / |o| <= tol for every body with scale / |o| <= kmax, and
+    |g - o| / scale <= tol for every body; print both and the share of all bodies
+    within the plain tol."""
+    no = np.linalg.norm(o, axis=1)
+    err = np.linalg.norm(g - o, axis=1)
+    plain, over = err / no, err / scale
+    kappa = scale / no
+    low = kappa <= kmax
+    print("   %s: plain max %.3e (kappa %.1f), within 1e-6: %d/%d | kappa<=%g: plain max %.3e "
+          "| /scale max %.3e" % (tag, plain.max(), kappa[np.argmax(plain)], int((plain <= tol).sum()),
+                                 plain.size, kmax, plain[low].max(initial=0), over.max()), flush=True)
+    assert over.max(initial=0) <= tol, (tag, over.max())
+    assert plain[low].max(initial=0) <= tol, (tag, plain[low].max())
+
+
 def check(orc, precision, ga, gj, x, v, m, eps, ilist=None, j0=0, j1=None, tag=""):
     """Compare GPU acc/jerk of bodies `ilist` with the oracle under the gates above."""
     oa, oj = orc.force(x, v, m, eps, ilist, j0, j1)
@@ -61,16 +87,8 @@ def check(orc, precision, ga, gj, x, v, m, eps, ilist=None, j0=0, j1=None, tag="
         assert ea.max(initial=0) <= TOL["fp64"] and ej.max(initial=0) <= TOL["fp64"], (ea.max(), ej.max())
     else:
         sa, sj = orc.force_scale(x, v, m, eps, ilist, j0, j1)
-        na = np.linalg.norm(ga[keep] - oa[keep], axis=1) / sa[keep]
-        nj = np.linalg.norm(gj[keep] - oj[keep], axis=1) / sj[keep]
-        if ea.size:
-            w = int(np.argmax(ea))
-            kappa = sa[keep][w] / np.linalg.norm(oa[keep][w])
-            print("   %s acc error / sum|a_ij|: max %.3e (worst relative body: %.3e, "
-                  "sum|a_ij| / |a| = %.1f) | jerk error / sum|jerk_ij|: max %.3e"
-                  % (precision, na.max(), ea[w], kappa, nj.max()), flush=True)
-        assert na.max(initial=0) <= TOL[precision], na.max()
-        assert nj.max(initial=0) <= TOL[precision], nj.max()
+        plain_gate("acc", ga[keep], oa[keep], sa[keep], KAPPA_PLAIN["acc"], TOL[precision])
+        plain_gate("jerk", gj[keep], oj[keep], sj[keep], KAPPA_PLAIN["jerk"], TOL[precision])
     return oa, oj
 
 
@@ -121,6 +139,9 @@ def check6(orc, precision, g, x, v, ap, m, eps, ilist=None, j0=0, j1=None, tag="
     tol = TOL[precision]
     assert (ea if precision == "fp64" else na).max(initial=0) <= tol
     assert nj.max(initial=0) <= tol, nj.max()
+    if precision != "fp64":
+        plain_gate("acc", ga[keep], oa[keep], sa[keep], KAPPA_PLAIN["acc"], tol)
+        plain_gate("jerk", gj[keep], oj[keep], sj[keep], KAPPA_PLAIN["jerk"], tol)
     assert ns.max(initial=0) <= TOL_SNAP[precision], ns.max()
     if precision == "fp64":
         ej = rel_err(gj[keep], oj[keep])

@@ -95,22 +95,27 @@ def test_force_plan_lane_target():
 
 
 def test_struct_layouts_match_the_header(tmp_path):
-    """ctypes mirrors of nb_system / nb_batch_item / nb_hermite6 have the C sizes and offsets."""
+    """ctypes mirrors of nb_system / nb_batch_item / nb_hermite6 / nb_tidal_item have the
+    C sizes and offsets."""
     import ctypes
     import subprocess
     from paper_1411_5234_amd import _lib
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "nbody.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(nb_system), '
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+        'sizeof(nb_system), '
         'sizeof(nb_batch_item), offsetof(nb_batch_item, status), offsetof(nb_batch_item, eps), '
         'offsetof(nb_batch_item, m), offsetof(nb_batch_item, done), sizeof(nb_hermite6), '
-        'offsetof(nb_hermite6, axp32)); return 0; }\n')
+        'offsetof(nb_hermite6, axp32), sizeof(nb_tidal_item), offsetof(nb_tidal_item, m), '
+        'offsetof(nb_tidal_item, eps), offsetof(nb_tidal_item, status)); return 0; }\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     B = _lib.NbBatchItem
     H = _lib.NbHermite6
+    Ti = _lib.NbTidalItem
     want = [ctypes.sizeof(_lib.NbSystem), ctypes.sizeof(B), B.status.offset, B.eps.offset,
-            B.m.offset, B.done.offset, ctypes.sizeof(H), H.axp32.offset]
+            B.m.offset, B.done.offset, ctypes.sizeof(H), H.axp32.offset, ctypes.sizeof(Ti),
+            Ti.m.offset, Ti.eps.offset, Ti.status.offset]
     assert got == want

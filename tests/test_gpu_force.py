@@ -1,14 +1,18 @@
 """GPU parity of nb_force_active (acc + jerk) against the FP64 oracle.
 
 Gates (maximum over bodies): FP64 path, relative error of acceleration and jerk
-<= 1e-12; mixed and double-single (DS) paths, relative acceleration error <= 1e-6
-and jerk error <= 1e-6 of the jerk's magnitude scale sum_j |jerk_ij| (see
-gpu_helpers).  Cases: the N = 1024 Plummer sphere with
-every body active, the N = 65536 Salpeter cluster with active blocks of 64 .. 4096
-(plus sampled bodies of larger blocks), ragged sizes and j-ranges, every launch
-plan shape, bitwise repeatability, empty blocks, error paths, and the N = 2^20
-Plummer sphere with every body active (the benchmarked launch) on sampled bodies.
+<= 1e-12; mixed and double-single (DS) paths, error <= 1e-6 of the magnitude scales
+sum_j |a_ij| and sum_j |jerk_ij| for every body, and plain relative error <= 1e-6
+for every body whose cancellation factor is below the bound of gpu_helpers.
+Cases: the N = 1024 Plummer sphere with every body active, the N = 65536 Salpeter
+cluster with active blocks of 64 .. 4096 (plus sampled bodies of larger blocks),
+ragged sizes and j-ranges, every launch plan shape, bitwise repeatability, empty
+blocks, error paths, and the N = 2^20 Plummer sphere with every body active (the
+benchmarked launch) on random bodies and on the bodies of largest cancellation.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,6 +21,7 @@ from gpu_helpers import TOL, check, device_system, gpu_force, report
 from paper_1411_5234_amd import inputs
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -172,8 +177,21 @@ def test_argument_errors(ctx):
     ctx.sync()   # the word was cleared by the failing sync
 
 
+def top_kappa_2pow20():
+    """The 64 bodies of largest sum|a_ij|/|a_i| and the 64 of largest
+    sum|jerk_ij|/|jerk_i| of the N = 2^20 Plummer sphere (seed 3, eps = 1e-4), from a
+    full oracle scan (tests/golden/make_kappa_plummer_2pow20.py)."""
+    with open(os.path.join(GOLDEN, "kappa_plummer_2pow20_seed3.json")) as f:
+        rec = json.load(f)
+    return (np.asarray(rec["top_kappa_acc"]["index"], dtype=np.int64),
+            np.asarray(rec["top_kappa_jerk"]["index"], dtype=np.int64))
+
+
 @pytest.mark.parametrize("precision", ["mixed", "ds", "fp64"])
 def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
+    """The benchmarked launch (m = N = 2^20) on 256 random bodies and, chosen on
+    purpose, the 128 bodies whose acceleration or jerk cancels most (largest
+    kappa): there the FP32 pair sum is furthest from the plain relative error."""
     n = 1 << 20
     s = inputs.plummer(n, 3)
     sys = device_system(s.x, s.v, s.m)
@@ -181,6 +199,10 @@ def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
     pick = np.sort(np.random.default_rng(30).choice(n, 256, replace=False))
     check(orc, precision, ga[pick], gj[pick], s.x, s.v, s.m, 1e-4, pick,
           tag="N=2^20 all active (256 sampled)")
+    top_a, top_j = top_kappa_2pow20()
+    for name, top in (("acceleration", top_a), ("jerk", top_j)):
+        check(orc, precision, ga[top], gj[top], s.x, s.v, s.m, 1e-4, top,
+              tag="N=2^20 all active (64 largest kappa of the %s)" % name)
     # momentum balance over every body (a property at any size)
     ma = (s.m[:, None] * ga).sum(0)
     assert np.all(np.abs(ma) <= 1e-6 * (s.m[:, None] * np.abs(ga)).sum(0))

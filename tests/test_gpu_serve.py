@@ -96,6 +96,79 @@ def test_served_equals_single_system_integrator(ctx, precision):
     assert served[0].steps == steps and served[0].interactions == inter
 
 
+def _target_log(rid):
+    """An on_iteration hook recording, for request `rid`, the block time and the
+    active bodies of every block step the server ran for it (its first iteration is
+    the startup step)."""
+    log, seen = [], []
+
+    def hook(srv):
+        for k, sl in enumerate(srv.slots):
+            if sl.req.rid != rid:
+                continue
+            if not seen:
+                seen.append(True)       # admitted this iteration: the startup step
+                return
+            # the item array is rebuilt after a retirement; its values are then in sl.item
+            t_next, m, done, err = ((float(srv._view["t_next"][k]), int(srv._view["m"][k]),
+                                     int(srv._view["done"][k]), int(srv._view["error"][k]))
+                                    if srv._arr is not None else
+                                    (sl.item.t_next, sl.item.m, sl.item.done, sl.item.error))
+            if not done and not err:
+                log.append((t_next, sl.i_idx[:m].cpu().numpy().astype(np.int64)))
+    return log, hook
+
+
+def test_served_in_a_mix_against_the_oracle(ctx, orc):
+    """A request served while others are admitted and retired around it, against
+    the oracle's block-step integration of the same initial condition (Sec. 2 items
+    1-2).  FP64: the same block times and active bodies at every step, the same
+    final steps, and the final state and energy within the lockstep bound.  Mixed
+    precision, served in the same mix: the same number of block steps within a few
+    percent and an energy error of the oracle's order."""
+    from paper_1411_5234_amd.serve import Server
+    target = _req(0, 512, 21, t_end=0.25)
+    snap = target.snapshot()
+    olog = []
+    ost, osteps, _ = orc.integrate(snap.x, snap.v, snap.m, target.t_end,
+                                   orc.Params(eps=target.eps), log=olog)
+    E0 = orc.energy(snap.x, snap.v, snap.m, target.eps)[2]
+    o_drift = abs(orc.energy(ost.x, ost.v, ost.m, target.eps)[2] - E0) / abs(E0)
+    # two short requests retire while the target runs; two more are admitted then
+    mix = [_req(1, 300, 12, t_end=0.125), _req(2, 700, 13, t_end=0.125), target,
+           _req(3, 1500, 14), _req(4, 256, 15, t_end=0.5)]
+    res = {}
+    for precision in ("fp64", "mixed"):
+        log, hook = _target_log(0)
+        srv = Server(ctx, precision=precision, keep_state=True, max_slots=3)
+        out = {r.rid: r for r in srv.run(mix, realtime=False, on_iteration=hook)}
+        assert all(r.error is None for r in out.values())
+        # requests 3 and 4 wait for the slots that requests 1 and 2 free
+        first_free = min(out[1].finished, out[2].finished)
+        assert out[3].admitted >= first_free and out[4].admitted >= first_free
+        assert out[3].admitted < out[0].finished     # admitted while the target runs
+        res[precision] = (out[0], log)
+    r, log = res["fp64"]
+    assert len(log) == len(olog) == osteps == r.steps
+    for (gt, gil), (ot, oil) in zip(log, olog):
+        assert gt == ot
+        np.testing.assert_array_equal(gil, oil)
+    g = r.final
+    np.testing.assert_array_equal(g["t"], ost.t)
+    np.testing.assert_array_equal(g["dt"], ost.dt)
+    dx = np.abs(g["x"] - ost.x).max()
+    dv = np.abs(g["v"] - ost.v).max()
+    print("fp64 served: %d steps, max|dx| %.3e max|dv| %.3e, energy error %.3e (oracle %.3e)"
+          % (r.steps, dx, dv, r.energy_error, o_drift), flush=True)
+    assert dx < 1e-10 and dv < 1e-10
+    assert abs(r.energy1 - orc.energy(ost.x, ost.v, ost.m, target.eps)[2]) <= 1e-10 * abs(E0)
+    rm, _ = res["mixed"]
+    print("mixed served: %d steps (oracle %d), energy error %.3e (oracle %.3e)"
+          % (rm.steps, osteps, rm.energy_error, o_drift), flush=True)
+    assert abs(rm.steps - osteps) <= 0.05 * osteps
+    assert rm.energy_error <= 10 * o_drift + 1e-8
+
+
 def test_admission_respects_memory_budget(ctx):
     from paper_1411_5234_amd.serve import Server, footprint_bytes
     reqs = [_req(k, 600 + 50 * k, 30 + k, t_end=0.125) for k in range(8)]
@@ -165,3 +238,51 @@ def test_sixth_order_served_equals_integrator6_alone_and_in_a_mix(ctx, precision
         assert st[f].tobytes() == served[0].final[f].tobytes(), f
     assert served[0].steps == steps and served[0].interactions == inter
     assert served[0].energy_error < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_grouped_pairs_alone_in_a_mix_and_as_the_integrator(ctx, precision):
+    """Requests with primordial binaries served with the pairs carried as
+    centre-of-mass bodies (their orbits advanced on the CPU thread from batched
+    tidal tensors): the target's reduced state and pair orbits are bitwise the same
+    served alone, served in a mix that is admitted and retired around it, and run
+    by the single-system grouped integrator (which is checked against the oracle's
+    grouped integration in test_gpu_groups)."""
+    from paper_1411_5234_amd.groups import GroupedIntegrator
+    from paper_1411_5234_amd.nbody import Params
+    from paper_1411_5234_amd.serve import Server
+
+    def bin_req(rid, n, seed, t_end=0.125):
+        return inputs.Request(rid, 0.0, n, seed, 1e-5, t_end, "kroupa_binaries")
+
+    target = bin_req(0, 1500, 5101)
+    keys = FIELDS + ("pair_r", "pair_w", "members_x", "members_v")
+    srv = Server(ctx, precision=precision, keep_state=True, groups=True)
+    alone = srv.run([target], realtime=False)[0]
+    assert alone.error is None and alone.pairs == 75
+    mix = [_req(1, 300, 12, t_end=0.125), bin_req(2, 1100, 5102), target,
+           _req(3, 2048, 14, t_end=0.25), bin_req(4, 900, 5103)]
+    srv = Server(ctx, precision=precision, keep_state=True, groups=True, max_slots=2)
+    out = {r.rid: r for r in srv.run(mix, realtime=False)}
+    assert all(r.error is None for r in out.values()), {k: r.error for k, r in out.items()}
+    b = out[0]
+    for f in keys:
+        assert alone.final[f].tobytes() == b.final[f].tobytes(), f
+    assert alone.steps == b.steps
+    snap = target.snapshot()
+    gi = GroupedIntegrator(ctx, snap.x, snap.v, snap.m, snap.meta["pairs"],
+                           Params(eps=target.eps, precision=precision))
+    gi.startup()
+    steps, _ = gi.run(target.t_end)
+    st = gi.sys.state_numpy()
+    for f in FIELDS:
+        assert st[f].tobytes() == b.final[f].tobytes(), f
+    assert gi.r.tobytes() == b.final["pair_r"].tobytes()
+    assert gi.w.tobytes() == b.final["pair_w"].tobytes()
+    assert steps == b.steps
+    e_scheme = abs(b.energy1 - b.energy0) / abs(b.energy0)
+    e_direct = abs(b.direct1 - b.direct0) / abs(b.direct0)
+    print("%s grouped: %d block steps, scheme energy error %.3e, direct %.3e" %
+          (precision, b.steps, e_scheme, e_direct), flush=True)
+    assert abs(b.energy1 - gi.energy()) <= 1e-14 * abs(b.energy1)
+    assert e_scheme < 1e-4

@@ -141,3 +141,53 @@ def test_library_group_advance_refuses_repeated_or_negative_rows(L, idx):
     assert L.nb_groups_advance(2, _p(idx), _p(M), _p(rr), _p(v.copy()), _p(H), _p(T0), _p(T0),
                                32, 1 << 20, None) == -1
     np.testing.assert_array_equal(rr, r)
+
+
+def _reduce(L, x, v, m, pairs):
+    n, k = m.size, len(pairs)
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    xr, vr, mr = np.empty((n - k, 3)), np.empty((n - k, 3)), np.empty(n - k)
+    M, r, w = np.empty(max(k, 1)), np.empty((max(k, 1), 3)), np.empty((max(k, 1), 3))
+    rc = L.nb_pairs_reduce(n, _p(x), _p(v), _p(m), k, _p(pairs), _p(xr), _p(vr), _p(mr), _p(M),
+                           _p(r), _p(w))
+    return rc, xr, vr, mr, M[:k], r[:k], w[:k]
+
+
+def test_pairs_reduce_members_energy_match_oracle(L, orc):
+    """The library's reduction to centre-of-mass bodies equals the oracle's grouped
+    startup state, the members it reconstructs are the inputs (to rounding), and the
+    pairs' energy is the oracle's grouped energy less the reduced system's."""
+    from paper_1411_5234_amd import inputs
+    s = inputs.with_binaries(600, 7)
+    pairs = s.meta["pairs"]
+    x, v, m = (np.ascontiguousarray(a) for a in (s.x, s.v, s.m))
+    rc, xr, vr, mr, M, r, w = _reduce(L, x, v, m, pairs)
+    assert rc == 0
+    eps = 1e-5
+    g = orc.group_startup(x, v, m, pairs, orc.Params(eps=eps))
+    np.testing.assert_array_equal(mr, g.st.m)
+    np.testing.assert_array_equal(M, g.M)
+    np.testing.assert_array_equal(r, g.r)
+    np.testing.assert_array_equal(w, g.w)
+    np.testing.assert_allclose(xr, g.st.x, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(vr, g.st.v, rtol=0, atol=1e-15)
+    xo, vo = np.empty_like(x), np.empty_like(v)
+    rc = L.nb_pairs_members(m.size, _p(xr), _p(vr), _p(m), len(pairs), _p(np.ascontiguousarray(pairs)),
+                            _p(r), _p(w), _p(xo), _p(vo))
+    assert rc == 0
+    np.testing.assert_allclose(xo, x, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(vo, v, rtol=0, atol=1e-13)
+    out = C.c_double()
+    T = np.ascontiguousarray(g.T.reshape(-1, 9))
+    rc = L.nb_pairs_energy(len(pairs), _p(m), _p(np.ascontiguousarray(pairs)), _p(r), _p(w), _p(T),
+                           C.byref(out))
+    assert rc == 0
+    want = orc.group_energy(g, m, eps) - orc.energy(g.st.x, g.st.v, g.st.m, eps)[2]
+    assert abs(out.value - want) <= 1e-12 * abs(want)
+
+
+def test_pairs_reduce_rejects_bad_pairs(L):
+    x = np.zeros((4, 3)); v = np.zeros((4, 3)); m = np.ones(4)
+    assert _reduce(L, x, v, m, [(0, 1), (1, 2)])[0] == -1     # index twice
+    assert _reduce(L, x, v, m, [(0, 4)])[0] == -1             # out of range
+    assert _reduce(L, x, v, m, [(0, 1), (2, 3)])[0] == 0
