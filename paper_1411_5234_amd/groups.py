@@ -63,11 +63,75 @@ class PairSet:
         if rc != 0:
             raise ValueError("pairs must be distinct indices in [0, n)")
         self.cm0 = nr - self.np                  # first centre-of-mass body of the reduced system
+        # original indices of the bodies in no pair (the first cm0 reduced bodies)
+        self.singles = np.setdiff1d(np.arange(self.n, dtype=np.int64), self.pairs.ravel())
         self.T = np.zeros((k, 9))
         self.tpair = np.zeros(k)
         self.status = np.zeros(k, dtype=np.int32)
+        self.a0 = np.zeros(k)                    # semimajor axes at the start
         self._pending = []
         self.advanced = 0
+        if self.np:
+            self.perturbation(a_from_orbit=True)
+
+    def perturbation(self, T=None, idx=None, a_from_orbit=False):
+        """gamma = |T| (2a)^3 / M of pairs idx (all by default) with T (their rows;
+        default: the stored tensors) and a the starting semimajor axes
+        (a_from_orbit: recomputed from r and w, and stored as the starting ones)."""
+        idx = np.arange(self.np) if idx is None else np.asarray(idx)
+        M = np.ascontiguousarray(self.M[idx])
+        Tk = np.ascontiguousarray(self.T[idx] if T is None else T, dtype=np.float64)
+        a = np.ascontiguousarray(self.a0[idx])
+        g = np.empty(idx.size)
+        if a_from_orbit:
+            r = np.ascontiguousarray(self.r[idx])
+            w = np.ascontiguousarray(self.w[idx])
+            rc = self.L.nb_pairs_perturbation(idx.size, _p(M), _p(r), _p(w), _p(Tk), _p(a), _p(g))
+            self.a0[idx] = a
+        else:
+            rc = self.L.nb_pairs_perturbation(idx.size, _p(M), None, None, _p(Tk), _p(a), _p(g))
+        if rc != 0:
+            raise ValueError("bad pair arrays")
+        return g
+
+    def without(self, drop):
+        """A PairSet of the same bodies without pairs `drop` (their members become
+        single bodies); the other pairs keep their orbits, tensors and times."""
+        keep = np.setdiff1d(np.arange(self.np), np.asarray(drop, dtype=np.int64))
+        out = PairSet.__new__(PairSet)
+        out.L, out.m, out.n = self.L, self.m, self.n
+        out.pairs = np.ascontiguousarray(self.pairs[keep])
+        out.np = keep.size
+        kk = max(out.np, 1)
+        out.cm0 = self.n - 2 * out.np
+        out.singles = np.setdiff1d(np.arange(self.n, dtype=np.int64), out.pairs.ravel())
+
+        def rows(a, shape):
+            b = np.zeros((kk,) + shape)
+            b[: out.np] = a[keep]
+            return b
+        out.M = rows(self.M, ())
+        out.r, out.w = rows(self.r, (3,)), rows(self.w, (3,))
+        out.T = rows(self.T, (9,))
+        out.tpair = rows(self.tpair, ())
+        out.a0 = rows(self.a0, ())
+        out.status = np.zeros(kk, dtype=np.int32)
+        out.status[: out.np] = self.status[keep]
+        out._pending = []
+        out.advanced = self.advanced
+        return out
+
+    def split_energy(self, idx, eps):
+        """Change of the conserved quantity when pairs idx rejoin the N-body system
+        as two bodies (their mutual potential becomes the softened one)."""
+        out = C.c_double()
+        pairs = np.ascontiguousarray(self.pairs[idx])
+        r = np.ascontiguousarray(self.r[idx])
+        rc = self.L.nb_pairs_split_energy(len(idx), _p(self.m), _p(pairs), _p(r), float(eps),
+                                          C.byref(out))
+        if rc != 0:
+            raise ValueError("degenerate pair")
+        return out.value
 
     def due(self, tcm, t_block):
         """Pairs whose centre of mass was in the block at t_block (tcm: the

@@ -52,7 +52,9 @@ class Result:
     # energies of the reconstructed members
     direct0: float = float("nan")
     direct1: float = float("nan")
-    pairs: int = 0
+    pairs: int = 0               # pairs carried as centre-of-mass bodies at admission
+    splits: int = 0              # pairs returned to the N-body system during the run
+    split_energy: float = 0.0    # change of the conserved quantity at those returns
 
     @property
     def latency(self) -> float:
@@ -60,20 +62,25 @@ class Result:
 
     @property
     def energy_error(self) -> float:
-        return abs(self.energy1 - self.energy0) / abs(self.energy0)
+        """Relative error of the conserved quantity (grouped systems: the scheme's,
+        with the known change at each pair's return to the N-body system removed)."""
+        return abs(self.energy1 - self.split_energy - self.energy0) / abs(self.energy0)
 
 
 class _Slot:
     """One resident system: device state, work buffers and its batch item."""
 
-    def __init__(self, req, device, precision, now, order=4, L=None, groups=False):
-        snap = req.snapshot()
+    def __init__(self, req, device, precision, now, order=4, L=None, groups=False, pairs=None,
+                 snap=None):
+        snap = req.snapshot() if snap is None else snap
         self.req = req
         self.snap = snap
         self.ps = None                     # PairSet of a grouped system
         self.prev_t = None                 # grouped: block time of its last block step
         self.tid_off = 0                   # grouped: offset of its tidal rows
-        pairs = snap.meta.get("pairs") if groups else None
+        self.device = device
+        if pairs is None and groups:
+            pairs = snap.meta.get("pairs")
         if pairs is not None and len(pairs):
             self.ps = PairSet(L, snap.x, snap.v, snap.m, pairs)
             self.n = self.ps.n - self.ps.np
@@ -84,26 +91,30 @@ class _Slot:
             self.n = snap.n
             self.sys = System.from_arrays(snap.x, snap.v, snap.m, device=device,
                                           fp32_copies=(precision != "fp64"))
-        n1 = max(self.n, 1)
-        self.i_idx = torch.zeros(n1, dtype=torch.int32, device=device)
-        self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=device)
-        self.jerk = torch.zeros(3 * n1, dtype=torch.float64, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.item = NbBatchItem()
-        self.item.sys = self.sys._struct
-        self.item.i_idx = self.i_idx.data_ptr()
-        self.item.acc = self.acc.data_ptr()
-        self.item.jerk = self.jerk.data_ptr()
+        self._work_buffers()
         self.item.status = self.status.data_ptr()
         self.item.eps = float(req.eps)
         self.item.t_end = float(req.t_end)
         self.item.startup = 1
         if order == 6:
             self.h6 = Hermite6(self.sys, fp32_copies=(precision != "fp64"))
-            self.snap6 = torch.zeros(3 * n1, dtype=torch.float64, device=device)
+            self.snap6 = torch.zeros(3 * max(self.n, 1), dtype=torch.float64, device=device)
         self.result = Result(req.rid, snap.n, req.arrival, now, float("nan"))
         if self.ps is not None:
             self.result.pairs = self.ps.np
+
+    def _work_buffers(self):
+        """Active list and force outputs sized for the system, pointed to by the item."""
+        n1 = max(self.n, 1)
+        self.i_idx = torch.zeros(n1, dtype=torch.int32, device=self.device)
+        self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=self.device)
+        self.jerk = torch.zeros(3 * n1, dtype=torch.float64, device=self.device)
+        self.item.sys = self.sys._struct
+        self.item.i_idx = self.i_idx.data_ptr()
+        self.item.acc = self.acc.data_ptr()
+        self.item.jerk = self.jerk.data_ptr()
 
 
 def footprint_bytes(n: int, precision: str = "mixed", order: int = 4) -> int:
@@ -172,7 +183,7 @@ class Server:
                  eta: float | None = None, eta_s: float = 0.01, dt_max: float = 2.0 ** -3,
                  dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
                  order: int = 4, lanes: int = 0, groups: bool = False, per_period: int = 32,
-                 max_sub: int = 1 << 20):
+                 max_sub: int = 1 << 20, group_gamma: float = 1e-3, split_gamma: float = 1e-2):
         if precision not in PRECISIONS:
             raise ValueError(precision)
         if order not in (4, 6):
@@ -183,8 +194,14 @@ class Server:
         # as one body at its centre of mass; its relative orbit advances on the
         # context's CPU thread (tidal kicks and exact two-body drifts) while the
         # GPU runs the block steps of every resident system
+        # -- a pair is carried as one body only while its perturbation gamma (tidal
+        # acceleration across its orbit over its own, nb_pairs_perturbation) is
+        # small: below group_gamma at admission (wider or more perturbed pairs
+        # stay two bodies), and it returns to the N-body system as two bodies when
+        # gamma exceeds split_gamma at one of its steps (an approaching perturber)
         self.groups = bool(groups)
         self.per_period, self.max_sub = int(per_period), int(max_sub)
+        self.group_gamma, self.split_gamma = float(group_gamma), float(split_gamma)
         self._tid_stale = True
         self._tid_items = None
         self._tid_dev = None
@@ -249,9 +266,16 @@ class Server:
                 return
             slot = _Slot(req, self.device, self.precision, self._now(), self.order, self.L,
                          self.groups)
-            slot.item.lanes = self.lanes
             if slot.ps is not None:
                 self._pairs_startup(slot)
+                gamma = slot.ps.perturbation()
+                if np.any(gamma >= self.group_gamma):
+                    slot = _Slot(req, self.device, self.precision, slot.result.admitted,
+                                 self.order, self.L, True, slot.ps.pairs[gamma < self.group_gamma],
+                                 slot.snap)
+                    if slot.ps is not None:
+                        self._pairs_startup(slot)
+            slot.item.lanes = self.lanes
             if self.energy:
                 slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
                 if slot.ps is not None:
@@ -282,22 +306,132 @@ class Server:
     def _grouped(self):
         return [sl for sl in self.slots if sl.ps is not None]
 
-    def _queue_pairs(self):
+    def _queue_pairs(self, stepped):
         """Queue the advance of every grouped system's pairs that were in its last
         block; their tensors and times reached the pinned host buffer before the
-        selection's host sync of this iteration."""
+        selection's host sync of this iteration.  A pair whose perturbation has
+        grown past split_gamma returns to the N-body system instead (only in a
+        system that took a block step in this iteration, `stepped`: slot -> its
+        block time)."""
         if self._tid_host is None:
-            return
+            return {}
         host = self._tid_host.numpy()
+        splits = []
         for sl in self._tid_slots:
             if sl.prev_t is None or sl not in self.slots:
                 continue
             k, o = sl.ps.np, sl.tid_off
             tcm = host[o + 9 * k: o + 10 * k]
             idx = sl.ps.due(tcm, sl.prev_t)
-            if idx.size:
-                Tn = host[o: o + 9 * k].reshape(9, k).T[idx]
-                sl.ps.advance(self.ctx, idx, sl.prev_t, Tn, self.per_period, self.max_sub)
+            if not idx.size:
+                continue
+            Tn = host[o: o + 9 * k].reshape(9, k).T[idx]
+            out = np.zeros(idx.size, dtype=bool)
+            if sl in stepped and self.split_gamma > 0:
+                out = sl.ps.perturbation(T=Tn, idx=idx) > self.split_gamma
+            if np.any(~out):
+                sl.ps.advance(self.ctx, idx[~out], sl.prev_t, Tn[~out], self.per_period,
+                              self.max_sub)
+            if np.any(out):
+                splits.append((sl, idx[out], Tn[out]))
+        failed = {}
+        for sl, ks, Tk in splits:
+            try:
+                self._split(sl, ks, Tk, stepped[sl])
+            except (NbError, ValueError) as e:
+                failed[sl] = "pair return failed: %s" % e
+        return failed
+
+    def _split(self, sl, ks, Tk, t_now):
+        """Return pairs ks of a grouped system to the N-body system as two bodies at
+        the system's current block time t_now.  Their orbits advance to their last
+        block (tensor Tk there), then to t_now with the tensor at t_now; each pair's
+        centre of mass at t_now (its corrected state if it was in this block, else
+        its prediction) is replaced by the two members; their accelerations and
+        jerks come from the predicted set at t_now and their steps from the startup
+        rule, capped by the centre of mass's step and by the largest power of two
+        dividing t_now.  The rest of the system keeps its state."""
+        ps, ctx = sl.ps, self.ctx
+        eps = float(sl.req.eps)
+        ps.drain(ctx)
+        ps.advance(ctx, ks, sl.prev_t, Tk, self.per_period, self.max_sub, queue=False)
+        cm_rows = ps.cm0 + ks
+        T = torch.zeros(9 * ks.size, dtype=torch.float64, device=self.device)
+        rows_dev = torch.as_tensor(cm_rows.astype(np.int32), device=self.device)
+        self._check(self.L.nb_tidal_active(ctx.h, sl.sys.ref, rows_dev.data_ptr(), ks.size, 0,
+                                           sl.n, eps, T.data_ptr()))
+        ctx.sync()
+        Tnow = T.cpu().numpy().reshape(9, ks.size).T.copy()
+        later = ps.tpair[ks] < t_now
+        if np.any(later):
+            ps.advance(ctx, ks[later], t_now, Tnow[later], self.per_period, self.max_sub,
+                       queue=False)
+        st = sl.sys.state_numpy()
+        self._sync_items()
+        sl.result.split_energy += ps.split_energy(ks, eps)
+        sl.result.splits += ks.size
+        # the centres of mass at t_now, the members from them and the pairs' orbits
+        at_now = st["t"][cm_rows] == t_now
+        xc = np.where(at_now[:, None], st["x"][cm_rows], st["xp"][cm_rows])
+        vc = np.where(at_now[:, None], st["v"][cm_rows], st["vp"][cm_rows])
+        members = ps.pairs[ks].ravel()
+        xm, vm = np.empty((2 * ks.size, 3)), np.empty((2 * ks.size, 3))
+        for q in range(ks.size):
+            one = PairSet.__new__(PairSet)
+            one.L, one.n, one.np = self.L, 2, 1
+            one.m = np.ascontiguousarray(ps.m[ps.pairs[ks[q]]])
+            one.pairs = np.array([[0, 1]], dtype=np.int64)
+            one.r, one.w = ps.r[ks[q]: ks[q] + 1].copy(), ps.w[ks[q]: ks[q] + 1].copy()
+            xm[2 * q: 2 * q + 2], vm[2 * q: 2 * q + 2] = one.members(xc[q: q + 1], vc[q: q + 1])
+        cap_cm = float(st["dt"][cm_rows].min())
+        new_ps = ps.without(ks)
+        # the new reduced system: bodies in no pair in index order, then the
+        # remaining pairs' centres of mass (the layout nb_pairs_reduce makes)
+        old_row = {int(i): r for r, i in enumerate(ps.singles)}
+        mem_row = {int(i): q for q, i in enumerate(members)}
+        keep_pairs = np.setdiff1d(np.arange(ps.np), ks)
+        n_new = new_ps.cm0 + new_ps.np
+        src = np.empty(n_new, dtype=np.int64)          # old row, or -1 - member slot
+        for r, i in enumerate(new_ps.singles):
+            src[r] = old_row[int(i)] if int(i) in old_row else -1 - mem_row[int(i)]
+        src[new_ps.cm0:] = ps.cm0 + keep_pairs
+        old = src >= 0
+        x, v = np.empty((n_new, 3)), np.empty((n_new, 3))
+        a, j = np.zeros((n_new, 3)), np.zeros((n_new, 3))
+        m, t, dt = np.empty(n_new), np.empty(n_new), np.empty(n_new)
+        for f, arr in (("x", x), ("v", v), ("a", a), ("j", j), ("m", m), ("t", t), ("dt", dt)):
+            arr[old] = st[f][src[old]]
+        mq = -1 - src[~old]
+        x[~old], v[~old] = xm[mq], vm[mq]
+        m[~old] = ps.m[members[mq]]
+        t[~old], dt[~old] = t_now, cap_cm
+        sysn = System.from_arrays(x, v, m, device=self.device,
+                                  fp32_copies=(self.precision != "fp64"))
+        rows = sysn.buf64[:, :n_new]
+        rows[6:9] = torch.from_numpy(np.ascontiguousarray(a.T)).to(self.device)
+        rows[9:12] = torch.from_numpy(np.ascontiguousarray(j.T)).to(self.device)
+        rows[13] = torch.from_numpy(t).to(self.device)
+        rows[14] = torch.from_numpy(dt).to(self.device)
+        # the members' acceleration, jerk and step at t_now
+        new_rows = np.flatnonzero(~old).astype(np.int32)
+        idx = torch.as_tensor(new_rows, device=self.device)
+        k = new_rows.size
+        acc = torch.zeros(3 * k, dtype=torch.float64, device=self.device)
+        jerk = torch.zeros(3 * k, dtype=torch.float64, device=self.device)
+        ctx.predict(sysn, t_now)
+        ctx.force_active(sysn, idx, k, 0, n_new, eps, self.precision, acc, jerk)
+        tick = math.ldexp(1.0, -40)
+        steps = int(round(t_now / tick))
+        cap = min(cap_cm, (steps & -steps) * tick) if steps else cap_cm
+        self._check(self.L.nb_init_steps_active(ctx.h, sysn.ref, idx.data_ptr(), k,
+                                                acc.data_ptr(), jerk.data_ptr(), float(t_now),
+                                                self.eta_s, cap, self.dt_min))
+        ctx.sync()
+        sl.sys, sl.n, sl.ps = sysn, n_new, new_ps
+        sl._work_buffers()
+        sl.cm_idx = torch.arange(new_ps.cm0, n_new, dtype=torch.int32, device=self.device)
+        self._arr = None
+        self._tid_stale = True
 
     def _tidal_layout(self):
         """One device buffer and one pinned host buffer for the tidal outputs of every
@@ -423,30 +557,38 @@ class Server:
             self._check(self.L.nb_step_batch(self.ctx.h, self._arr, len(self.slots),
                                              self.prec_code, self.eta, self.eta_s, self.dt_max,
                                              self.dt_min))
-        err, done = v["error"], v["done"]
+        # copies: a pair's return to the N-body system below rebuilds the item array
+        err, done, t_next = v["error"].copy(), v["done"].copy(), v["t_next"].copy()
+        m_blk = v["m"].astype(np.int64)
         ran = (err == 0) & (done == 0)
         n = self._n
         passes = 2 if self.order == 6 else 1        # force passes of a startup step
-        inc = np.where(startup, passes * n * n, v["m"].astype(np.int64) * n)
+        inc = np.where(startup, passes * n * n, m_blk * n)
         self._inter[ran] += inc[ran]
         self._steps[ran & ~startup] += 1
         self.iterations += 1
         if self.groups:
-            # the previous block's pairs go to the CPU thread; this block's
-            # systems get their tidal tensors after the retirements below
-            self._queue_pairs()
-            stepped = set()
+            # the previous block's pairs go to the CPU thread (or return to the
+            # N-body system); this block's systems get their tidal tensors after
+            # the retirements below
+            stepped = {}
             for k in np.flatnonzero(ran & ~startup):
-                sl = self.slots[k]
-                if sl.ps is not None:
-                    sl.prev_t = float(v["t_next"][k])
-                    stepped.add(sl)
+                if self.slots[k].ps is not None:
+                    stepped[self.slots[k]] = float(t_next[k])
+            failed = self._queue_pairs(stepped) or {}
+            for sl, tb in stepped.items():
+                sl.prev_t = tb
+        else:
+            failed = {}
         leave = np.flatnonzero((err != 0) | (done != 0))
-        if leave.size:
-            gone = [(self.slots[k], int(err[k])) for k in leave]
-            for sl, e in gone:
-                self._retire(sl, _lib.STATUS.get(e, str(e)) if e != 0 else None)
+        gone = [(self.slots[k], _lib.STATUS.get(int(err[k]), str(int(err[k])))
+                 if err[k] != 0 else None) for k in leave]
+        gone += [(sl, msg) for sl, msg in failed.items() if sl not in dict(gone)]
+        for sl, e in gone:
+            self._retire(sl, e)
         if self.groups:
+            for sl, _ in gone:
+                stepped.pop(sl, None)
             self._tidal(stepped)
 
     # ---- driving a request stream ------------------------------------------------

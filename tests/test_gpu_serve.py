@@ -257,12 +257,15 @@ def test_grouped_pairs_alone_in_a_mix_and_as_the_integrator(ctx, precision):
 
     target = bin_req(0, 1500, 5101)
     keys = FIELDS + ("pair_r", "pair_w", "members_x", "members_v")
-    srv = Server(ctx, precision=precision, keep_state=True, groups=True)
+    # every pair grouped and none returned, as the single-system integrator does
+    kw = dict(precision=precision, keep_state=True, groups=True, group_gamma=float("inf"),
+              split_gamma=0.0)
+    srv = Server(ctx, **kw)
     alone = srv.run([target], realtime=False)[0]
     assert alone.error is None and alone.pairs == 75
     mix = [_req(1, 300, 12, t_end=0.125), bin_req(2, 1100, 5102), target,
            _req(3, 2048, 14, t_end=0.25), bin_req(4, 900, 5103)]
-    srv = Server(ctx, precision=precision, keep_state=True, groups=True, max_slots=2)
+    srv = Server(ctx, max_slots=2, **kw)
     out = {r.rid: r for r in srv.run(mix, realtime=False)}
     assert all(r.error is None for r in out.values()), {k: r.error for k, r in out.items()}
     b = out[0]
@@ -286,3 +289,39 @@ def test_grouped_pairs_alone_in_a_mix_and_as_the_integrator(ctx, precision):
           (precision, b.steps, e_scheme, e_direct), flush=True)
     assert abs(b.energy1 - gi.energy()) <= 1e-14 * abs(b.energy1)
     assert e_scheme < 1e-4
+
+
+def test_pairs_return_to_the_n_body_system(ctx):
+    """Grouped pairs whose perturbation grows past the split threshold rejoin the
+    N-body system as two bodies mid-run (here a low threshold makes many do so):
+    the run completes, the result is bitwise the same alone and in a mix, and the
+    scheme's conserved quantity (with the known change at each return) and the
+    full N-body energy stay conserved."""
+    from paper_1411_5234_amd.serve import Server
+
+    def bin_req(rid, n, seed, t_end=0.125):
+        return inputs.Request(rid, 0.0, n, seed, 1e-5, t_end, "kroupa_binaries")
+
+    target = bin_req(0, 1500, 5101)
+    keys = FIELDS + ("pair_r", "pair_w", "members_x", "members_v")
+    kw = dict(precision="fp64", keep_state=True, groups=True, split_gamma=1e-4)
+    alone = Server(ctx, **kw).run([target], realtime=False)[0]
+    assert alone.error is None, alone.error
+    print("grouped %d pairs, %d returned, %d block steps; conserved quantity error %.3e "
+          "(return offset %.3e), direct %.3e" % (
+              alone.pairs, alone.splits, alone.steps, alone.energy_error, alone.split_energy,
+              abs(alone.direct1 - alone.direct0) / abs(alone.direct0)), flush=True)
+    assert 0 < alone.splits < alone.pairs
+    assert alone.final["pair_r"].shape[0] == alone.pairs - alone.splits
+    mix = [_req(1, 300, 12, t_end=0.125), bin_req(2, 1100, 5102), target, bin_req(4, 900, 5103)]
+    out = {r.rid: r for r in Server(ctx, max_slots=2, **kw).run(mix, realtime=False)}
+    assert all(r.error is None for r in out.values()), {k: r.error for k, r in out.items()}
+    b = out[0]
+    for f in keys:
+        assert alone.final[f].tobytes() == b.final[f].tobytes(), f
+    assert (alone.steps, alone.splits) == (b.steps, b.splits)
+    assert alone.energy_error < 1e-4
+    # admission keeps only pairs below the grouping threshold
+    few = Server(ctx, precision="fp64", groups=True, group_gamma=1e-5).run([target],
+                                                                            realtime=False)[0]
+    assert few.error is None and few.pairs < alone.pairs

@@ -191,3 +191,33 @@ def test_pairs_reduce_rejects_bad_pairs(L):
     assert _reduce(L, x, v, m, [(0, 1), (1, 2)])[0] == -1     # index twice
     assert _reduce(L, x, v, m, [(0, 4)])[0] == -1             # out of range
     assert _reduce(L, x, v, m, [(0, 1), (2, 3)])[0] == 0
+
+
+def test_pair_perturbation_and_split_energy(L):
+    """Semimajor axis of a circular and an eccentric orbit (vis-viva), the
+    perturbation |T| (2a)^3 / M of an isotropic tensor, unbound pairs, the
+    input-a form, and the change of the pair potential at a return."""
+    M = np.array([2.0, 2.0, 2.0])
+    a_c, rp, e = 0.3, 0.1, 0.5
+    r = np.array([[a_c, 0, 0], [rp, 0, 0], [0.1, 0, 0]])
+    w = np.array([[0, math.sqrt(M[0] / a_c), 0],
+                  [0, math.sqrt(M[1] * (1 + e) / rp), 0],     # pericentre of a = rp / (1 - e)
+                  [0, 10.0, 0]])                               # unbound
+    T = np.zeros((3, 9))
+    T[:, [0, 4, 8]] = 0.7
+    a, g = np.empty(3), np.empty(3)
+    assert L.nb_pairs_perturbation(3, _p(M), _p(r), _p(w), _p(T), _p(a), _p(g)) == 0
+    np.testing.assert_allclose(a[:2], [a_c, rp / (1 - e)], rtol=1e-13)
+    np.testing.assert_allclose(g[:2], 0.7 * math.sqrt(3) * (2 * a[:2]) ** 3 / 2.0, rtol=1e-13)
+    assert math.isinf(a[2]) and math.isinf(g[2])
+    a2, g2 = a[:2].copy(), np.empty(2)
+    assert L.nb_pairs_perturbation(2, _p(M), None, None, None, _p(a2), _p(g2)) == 0
+    assert np.all(g2 == 0.0)
+    m = np.array([0.3, 0.5, 0.2, 0.1])
+    pairs = np.array([[0, 1], [2, 3]], dtype=np.int64)
+    rr = np.array([[1e-3, 0, 0], [0, 2e-4, 0]])
+    out = C.c_double()
+    assert L.nb_pairs_split_energy(2, _p(m), _p(pairs), _p(rr), 1e-5, C.byref(out)) == 0
+    want = sum(m[i] * m[j] * (1 / np.linalg.norm(q) - 1 / math.hypot(np.linalg.norm(q), 1e-5))
+               for (i, j), q in zip(pairs, rr))
+    assert abs(out.value - want) <= 1e-14 * abs(want)

@@ -55,3 +55,27 @@ def test_self_term_excluded(orc):
     # one body: no potential even though eps > 0 would give -m^2/eps
     T, W, E = orc.energy(np.zeros((1, 3)), np.ones((1, 3)), np.array([2.0]), 0.1)
     assert W == 0.0 and T == pytest.approx(3.0)
+
+
+def test_stored_energy_of_the_2pow20_sphere():
+    """The stored oracle energies of the N = 2^20 Plummer sphere (seed 3; written by
+    tests/golden/make_energy_plummer_2pow20.py, which calls only the oracle) belong
+    to that sphere: the kinetic energy equals sum m v^2 / 2 of the regenerated
+    bodies, the unsoftened potential is the Plummer model's W = -1/2 (Henon units)
+    within sampling noise, and softening raises it by a small positive amount."""
+    import json
+    import os
+
+    from paper_1411_5234_amd import inputs
+    path = os.path.join(os.path.dirname(__file__), "golden", "energy_plummer_2pow20_seed3.json")
+    with open(path) as f:
+        rec = json.load(f)["energy"]
+    s = inputs.plummer(1 << 20, 3)
+    T = 0.5 * float((s.m * (s.v ** 2).sum(1)).sum())
+    for eps in ("0.0001", "0"):
+        assert rec[eps]["kinetic"] == pytest.approx(T, rel=1e-13)
+        assert rec[eps]["total"] == pytest.approx(rec[eps]["kinetic"] + rec[eps]["potential"],
+                                                  rel=1e-15)
+    W0, W1 = rec["0"]["potential"], rec["0.0001"]["potential"]
+    assert abs(W0 + 0.5) < 5e-3
+    assert 0 < W1 - W0 < 1e-3 * abs(W0)
