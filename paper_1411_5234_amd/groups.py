@@ -33,17 +33,112 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
-class PairSet:
-    """Host state of the bound pairs of one system: per pair its total mass M, the
-    relative coordinate r = x2 - x1 and velocity w = v2 - v1 (host arrays the CPU
-    threads advance in place), the tidal tensor T at the pair's own time tpair, and
-    a status word.  The arithmetic (reduction to centre-of-mass bodies, members,
-    pair energy, pair advance) is the library's (nb_pairs_*, nb_groups_advance*);
-    this class holds the arrays and the queue of pending advances."""
+class PairTable:
+    """Host arrays of the bound pairs of one or many systems, one contiguous segment
+    per system: total mass M, relative coordinate r = x2 - x1 and velocity
+    w = v2 - v1 (advanced in place by the library's CPU threads), the tidal tensor T
+    (row-major 3x3) at the pair's own time tpair, its starting semimajor axis a0 and
+    a status word.  Queued advances name rows of these arrays, so the arrays move
+    (growth, compaction) only after the queue is drained.  A server keeps one table
+    for all its resident systems and handles their pairs in one pass per iteration;
+    `prev_t` (the block time of a system's last step, NaN when none) and
+    `owner` (the PairSet of each row) serve that pass."""
 
     MAX_QUEUED = 4096
 
-    def __init__(self, L, x, v, m, pairs):
+    def __init__(self, L, capacity: int = 256):
+        self.L = L
+        self.cap = 0
+        self.used = 0
+        self.sets = []                 # live PairSets, in the order of their segments
+        self._pending = []
+        self._grow(max(int(capacity), 1))
+
+    FIELDS = (("M", (), np.float64), ("r", (3,), np.float64), ("w", (3,), np.float64),
+              ("T", (9,), np.float64), ("tpair", (), np.float64), ("a0", (), np.float64),
+              ("status", (), np.int32), ("prev_t", (), np.float64))
+
+    def _grow(self, cap):
+        for name, shape, dt in self.FIELDS:
+            new = np.zeros((cap,) + shape, dtype=dt)
+            if self.cap:
+                new[: self.used] = getattr(self, name)[: self.used]
+            setattr(self, name, new)
+        self.prev_t[self.used:] = np.nan
+        self.cap = cap
+
+    def reserve(self, k, ctx=None):
+        """Room for k more rows at the end (compacting and growing the arrays when
+        needed; the caller has drained the queue when ctx is None)."""
+        if self.used + k <= self.cap:
+            return
+        self.drain(ctx)
+        live = sum(ps.np for ps in self.sets)
+        pos = 0
+        for ps in self.sets:                                   # compact, in segment order
+            if ps.base != pos:
+                for name, _, _ in self.FIELDS:
+                    arr = getattr(self, name)
+                    arr[pos: pos + ps.np] = arr[ps.base: ps.base + ps.np].copy()
+            ps.base = pos
+            pos += ps.np
+        self.used = live
+        self.prev_t[self.used:] = np.nan
+        if self.used + k > self.cap:
+            self._grow(max(2 * self.cap, self.used + k))
+
+    def drain(self, ctx):
+        """Wait until every queued advance has run.  Returns the seconds waited."""
+        if not self._pending:
+            return 0.0
+        t0 = time.perf_counter()
+        ctx.L.nb_groups_wait(ctx.h)
+        self._pending.clear()
+        return time.perf_counter() - t0
+
+    def advance(self, ctx, rows, H, T0, T1, per_period, max_sub, queue=True):
+        """Advance table rows `rows` over H with the tensor linear from T0 to T1;
+        queued on the context's CPU thread, or run here (queue=False; returns the
+        seconds spent)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        H, T0, T1 = (np.ascontiguousarray(a, dtype=np.float64) for a in (H, T0, T1))
+        args = (int(rows.size), _p(rows), _p(self.M), _p(self.r), _p(self.w), _p(H), _p(T0),
+                _p(T1), int(per_period), int(max_sub), _p(self.status))
+        if rows.size == 0:
+            return 0.0
+        if queue:
+            if len(self._pending) >= self.MAX_QUEUED:
+                self.drain(ctx)
+            self._pending.append((rows, H, T0, T1))
+            ctx._check(ctx.L.nb_groups_advance_async(ctx.h, *args))
+            return 0.0
+        t0 = time.perf_counter()
+        rc = ctx.L.nb_groups_advance(*args)
+        dt = time.perf_counter() - t0
+        if rc != 0:
+            bad = rows[self.status[rows] != 0]
+            raise _lib.NbError(rc, "%d pairs are no longer bound" % bad.size)
+        return dt
+
+    def perturbation(self, rows, T):
+        """gamma = |T| (2a0)^3 / M of table rows `rows` with tensors T (their rows)."""
+        rows = np.asarray(rows)
+        M = np.ascontiguousarray(self.M[rows])
+        a = np.ascontiguousarray(self.a0[rows])
+        Tk = np.ascontiguousarray(T, dtype=np.float64)
+        g = np.empty(rows.size)
+        if self.L.nb_pairs_perturbation(rows.size, _p(M), None, None, _p(Tk), _p(a), _p(g)) != 0:
+            raise ValueError("bad pair arrays")
+        return g
+
+
+class PairSet:
+    """The bound pairs of one system: a segment of a PairTable (a table of its own
+    unless one is given) plus the system's masses and pair list.  The arithmetic
+    (reduction to centre-of-mass bodies, members, pair energy, perturbation, pair
+    advance) is the library's (nb_pairs_*, nb_groups_advance*)."""
+
+    def __init__(self, L, x, v, m, pairs, table: PairTable | None = None, ctx=None):
         x = np.ascontiguousarray(x, dtype=np.float64)
         v = np.ascontiguousarray(v, dtype=np.float64)
         self.m = np.ascontiguousarray(m, dtype=np.float64)
@@ -54,70 +149,120 @@ class PairSet:
         nr = self.n - self.np
         self.xr, self.vr = np.empty((nr, 3)), np.empty((nr, 3))
         self.mr = np.empty(nr)
-        k = max(self.np, 1)
-        self.M = np.zeros(k)
-        self.r, self.w = np.zeros((k, 3)), np.zeros((k, 3))
+        M = np.zeros(max(self.np, 1))
+        r, w = np.zeros((max(self.np, 1), 3)), np.zeros((max(self.np, 1), 3))
         rc = L.nb_pairs_reduce(self.n, _p(x), _p(v), _p(self.m), self.np, _p(self.pairs),
-                               _p(self.xr), _p(self.vr), _p(self.mr), _p(self.M), _p(self.r),
-                               _p(self.w))
+                               _p(self.xr), _p(self.vr), _p(self.mr), _p(M), _p(r), _p(w))
         if rc != 0:
             raise ValueError("pairs must be distinct indices in [0, n)")
         self.cm0 = nr - self.np                  # first centre-of-mass body of the reduced system
         # original indices of the bodies in no pair (the first cm0 reduced bodies)
         self.singles = np.setdiff1d(np.arange(self.n, dtype=np.int64), self.pairs.ravel())
-        self.T = np.zeros((k, 9))
-        self.tpair = np.zeros(k)
-        self.status = np.zeros(k, dtype=np.int32)
-        self.a0 = np.zeros(k)                    # semimajor axes at the start
-        self._pending = []
+        self.table = table if table is not None else PairTable(L, self.np)
+        self._attach(ctx)
+        self.M[:] = M[: self.np]
+        self.r[:] = r[: self.np]
+        self.w[:] = w[: self.np]
         self.advanced = 0
         if self.np:
-            self.perturbation(a_from_orbit=True)
+            a, g = np.empty(self.np), np.empty(self.np)
+            rc = L.nb_pairs_perturbation(self.np, _p(np.ascontiguousarray(self.M)),
+                                         _p(np.ascontiguousarray(self.r)),
+                                         _p(np.ascontiguousarray(self.w)), None, _p(a), _p(g))
+            if rc != 0:
+                raise ValueError("bad pair arrays")
+            self.a0[:] = a
 
-    def perturbation(self, T=None, idx=None, a_from_orbit=False):
-        """gamma = |T| (2a)^3 / M of pairs idx (all by default) with T (their rows;
-        default: the stored tensors) and a the starting semimajor axes
-        (a_from_orbit: recomputed from r and w, and stored as the starting ones)."""
+    def _attach(self, ctx):
+        t = self.table
+        t.reserve(self.np, ctx)
+        self.base = t.used
+        t.used += self.np
+        t.sets.append(self)
+        for name, _, _ in PairTable.FIELDS:
+            getattr(t, name)[self.base: self.base + self.np] = 0
+        t.prev_t[self.base: self.base + self.np] = np.nan
+
+    def release(self):
+        """Give the segment back to the table (after its queued advances have run)."""
+        if self in self.table.sets:
+            self.table.sets.remove(self)
+            self.table.prev_t[self.base: self.base + self.np] = np.nan
+
+    # the segment's rows of the table arrays (views)
+    def _seg(self, name):
+        return getattr(self.table, name)[self.base: self.base + self.np]
+
+    M = property(lambda self: self._seg("M"))
+    r = property(lambda self: self._seg("r"))
+    w = property(lambda self: self._seg("w"))
+    T = property(lambda self: self._seg("T"))
+    tpair = property(lambda self: self._seg("tpair"))
+    a0 = property(lambda self: self._seg("a0"))
+    status = property(lambda self: self._seg("status"))
+
+    def perturbation(self, T=None, idx=None):
+        """gamma = |T| (2a)^3 / M of pairs idx (all by default) with tensors T (their
+        rows; default: the stored ones), a the starting semimajor axes."""
         idx = np.arange(self.np) if idx is None else np.asarray(idx)
-        M = np.ascontiguousarray(self.M[idx])
-        Tk = np.ascontiguousarray(self.T[idx] if T is None else T, dtype=np.float64)
-        a = np.ascontiguousarray(self.a0[idx])
-        g = np.empty(idx.size)
-        if a_from_orbit:
-            r = np.ascontiguousarray(self.r[idx])
-            w = np.ascontiguousarray(self.w[idx])
-            rc = self.L.nb_pairs_perturbation(idx.size, _p(M), _p(r), _p(w), _p(Tk), _p(a), _p(g))
-            self.a0[idx] = a
-        else:
-            rc = self.L.nb_pairs_perturbation(idx.size, _p(M), None, None, _p(Tk), _p(a), _p(g))
-        if rc != 0:
-            raise ValueError("bad pair arrays")
-        return g
+        return self.table.perturbation(self.base + idx, self.T[idx] if T is None else T)
 
-    def without(self, drop):
+    def due(self, tcm, t_block):
+        """Pairs whose centre of mass was in the block at t_block (tcm: the
+        centre-of-mass bodies' times after that block) and are not yet there."""
+        idx = np.nonzero(tcm[: self.np] == t_block)[0]
+        return idx[self.tpair[idx] < t_block]
+
+    def advance(self, ctx, idx, t_block, Tn, per_period, max_sub, queue=True):
+        """Advance pairs idx from their own times to t_block, the tidal tensor linear
+        from T (at tpair) to Tn (at t_block); queued on the context's CPU thread
+        (queue=True) or run here.  Returns the seconds spent here."""
+        idx = np.asarray(idx)
+        if idx.size == 0:
+            return 0.0
+        H = t_block - self.tpair[idx]
+        T0 = self.T[idx].copy()
+        Tn = np.asarray(Tn, dtype=np.float64)
+        self.T[idx] = Tn
+        self.tpair[idx] = t_block
+        self.advanced += idx.size
+        try:
+            return self.table.advance(ctx, self.base + idx, H, T0, Tn, per_period, max_sub,
+                                      queue)
+        except _lib.NbError as e:
+            raise _lib.NbError(e.code, "pairs %s are no longer bound"
+                               % self.pairs[idx[self.status[idx] != 0]].tolist()) from None
+
+    def drain(self, ctx):
+        """Wait until every queued advance has run (r, w current); raises if a pair
+        of this set became unbound."""
+        dt = self.table.drain(ctx)
+        if np.any(self.status != 0):
+            self.fail(-7)
+        return dt
+
+    def fail(self, rc):
+        bad = np.nonzero(self.status != 0)[0]
+        raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
+
+    def without(self, drop, ctx=None):
         """A PairSet of the same bodies without pairs `drop` (their members become
-        single bodies); the other pairs keep their orbits, tensors and times."""
+        single bodies), in the same table; the other pairs keep their orbits,
+        tensors and times.  This set's segment is released."""
         keep = np.setdiff1d(np.arange(self.np), np.asarray(drop, dtype=np.int64))
+        saved = {name: getattr(self, name)[keep].copy()
+                 for name in ("M", "r", "w", "T", "tpair", "a0", "status")}
+        self.release()
         out = PairSet.__new__(PairSet)
         out.L, out.m, out.n = self.L, self.m, self.n
         out.pairs = np.ascontiguousarray(self.pairs[keep])
         out.np = keep.size
-        kk = max(out.np, 1)
         out.cm0 = self.n - 2 * out.np
         out.singles = np.setdiff1d(np.arange(self.n, dtype=np.int64), out.pairs.ravel())
-
-        def rows(a, shape):
-            b = np.zeros((kk,) + shape)
-            b[: out.np] = a[keep]
-            return b
-        out.M = rows(self.M, ())
-        out.r, out.w = rows(self.r, (3,)), rows(self.w, (3,))
-        out.T = rows(self.T, (9,))
-        out.tpair = rows(self.tpair, ())
-        out.a0 = rows(self.a0, ())
-        out.status = np.zeros(kk, dtype=np.int32)
-        out.status[: out.np] = self.status[keep]
-        out._pending = []
+        out.table = self.table
+        out._attach(ctx)
+        for name, val in saved.items():
+            getattr(out, name)[:] = val
         out.advanced = self.advanced
         return out
 
@@ -133,63 +278,14 @@ class PairSet:
             raise ValueError("degenerate pair")
         return out.value
 
-    def due(self, tcm, t_block):
-        """Pairs whose centre of mass was in the block at t_block (tcm: the
-        centre-of-mass bodies' times after that block) and are not yet there."""
-        idx = np.nonzero(tcm[: self.np] == t_block)[0]
-        return idx[self.tpair[idx] < t_block]
-
-    def advance(self, ctx, idx, t_block, Tn, per_period, max_sub, queue=True):
-        """Advance pairs idx from their own times to t_block, the tidal tensor linear
-        from T (at tpair) to Tn (at t_block); queued on the context's CPU thread
-        (queue=True) or run here.  Returns the seconds spent here."""
-        if idx.size == 0:
-            return 0.0
-        rows = np.ascontiguousarray(idx, dtype=np.int32)
-        H = np.ascontiguousarray(t_block - self.tpair[idx])
-        T0 = np.ascontiguousarray(self.T[idx])
-        T1 = np.ascontiguousarray(Tn)
-        self.T[idx] = Tn
-        self.tpair[idx] = t_block
-        self.advanced += idx.size
-        args = (int(idx.size), _p(rows), _p(self.M), _p(self.r), _p(self.w), _p(H), _p(T0),
-                _p(T1), int(per_period), int(max_sub), _p(self.status))
-        if queue:
-            if len(self._pending) >= self.MAX_QUEUED:
-                self.drain(ctx)
-            self._pending.append((rows, H, T0, T1))
-            ctx._check(ctx.L.nb_groups_advance_async(ctx.h, *args))
-            return 0.0
-        t0 = time.perf_counter()
-        rc = ctx.L.nb_groups_advance(*args)
-        dt = time.perf_counter() - t0
-        if rc != 0:
-            self.fail(rc)
-        return dt
-
-    def drain(self, ctx):
-        """Wait until every queued advance has run (r, w current); raises if a pair
-        of this set became unbound."""
-        if not self._pending:
-            return 0.0
-        t0 = time.perf_counter()
-        ctx.L.nb_groups_wait(ctx.h)
-        self._pending.clear()
-        if np.any(self.status[: self.np] != 0):
-            self.fail(-7)
-        return time.perf_counter() - t0
-
-    def fail(self, rc):
-        bad = np.nonzero(self.status[: self.np] != 0)[0]
-        raise _lib.NbError(rc, "pairs %s are no longer bound" % self.pairs[bad].tolist())
-
     def members(self, xr, vr):
         """(x, v) of all n original bodies from the reduced state and r, w."""
         x, v = np.empty((self.n, 3)), np.empty((self.n, 3))
         xr = np.ascontiguousarray(xr, dtype=np.float64)
         vr = np.ascontiguousarray(vr, dtype=np.float64)
+        r, w = np.ascontiguousarray(self.r), np.ascontiguousarray(self.w)
         rc = self.L.nb_pairs_members(self.n, _p(xr), _p(vr), _p(self.m), self.np, _p(self.pairs),
-                                     _p(self.r), _p(self.w), _p(x), _p(v))
+                                     _p(r), _p(w), _p(x), _p(v))
         if rc != 0:
             raise ValueError("bad reduced state")
         return x, v
@@ -198,8 +294,10 @@ class PairSet:
         """The pairs' two-body and tidal energy (the pair part of the conserved
         quantity)."""
         out = C.c_double()
-        rc = self.L.nb_pairs_energy(self.np, _p(self.m), _p(self.pairs), _p(self.r), _p(self.w),
-                                    _p(self.T), C.byref(out))
+        r, w = np.ascontiguousarray(self.r), np.ascontiguousarray(self.w)
+        T = np.ascontiguousarray(self.T)
+        rc = self.L.nb_pairs_energy(self.np, _p(self.m), _p(self.pairs), _p(r), _p(w), _p(T),
+                                    C.byref(out))
         if rc != 0:
             raise ValueError("degenerate pair")
         return out.value
@@ -251,7 +349,7 @@ class GroupedIntegrator:
     def __del__(self):
         # the CPU thread writes into this object's arrays: never free them under it
         try:
-            if self.ps._pending:
+            if self.ps.table._pending:
                 self.ctx.L.nb_groups_wait(self.ctx.h)
         except Exception:
             pass

@@ -30,7 +30,7 @@ import torch
 
 from . import _lib
 from ._lib import NbBatchItem, NbError, NbHermite6, NbTidalItem, PRECISIONS
-from .groups import PairSet
+from .groups import PairSet, PairTable
 from .nbody import Context, Hermite6, System
 
 
@@ -71,18 +71,16 @@ class _Slot:
     """One resident system: device state, work buffers and its batch item."""
 
     def __init__(self, req, device, precision, now, order=4, L=None, groups=False, pairs=None,
-                 snap=None):
+                 snap=None, table=None, ctx=None):
         snap = req.snapshot() if snap is None else snap
         self.req = req
         self.snap = snap
         self.ps = None                     # PairSet of a grouped system
-        self.prev_t = None                 # grouped: block time of its last block step
-        self.tid_off = 0                   # grouped: offset of its tidal rows
         self.device = device
         if pairs is None and groups:
             pairs = snap.meta.get("pairs")
         if pairs is not None and len(pairs):
-            self.ps = PairSet(L, snap.x, snap.v, snap.m, pairs)
+            self.ps = PairSet(L, snap.x, snap.v, snap.m, pairs, table, ctx)
             self.n = self.ps.n - self.ps.np
             self.sys = System.from_arrays(self.ps.xr, self.ps.vr, self.ps.mr, device=device,
                                           fp32_copies=(precision != "fp64"))
@@ -202,6 +200,7 @@ class Server:
         self.groups = bool(groups)
         self.per_period, self.max_sub = int(per_period), int(max_sub)
         self.group_gamma, self.split_gamma = float(group_gamma), float(split_gamma)
+        self.ptab = PairTable(_lib.load()) if self.groups else None
         self._tid_stale = True
         self._tid_items = None
         self._tid_dev = None
@@ -265,14 +264,15 @@ class Server:
             if req is None:
                 return
             slot = _Slot(req, self.device, self.precision, self._now(), self.order, self.L,
-                         self.groups)
+                         self.groups, table=self.ptab, ctx=self.ctx)
             if slot.ps is not None:
                 self._pairs_startup(slot)
                 gamma = slot.ps.perturbation()
                 if np.any(gamma >= self.group_gamma):
+                    slot.ps.release()
                     slot = _Slot(req, self.device, self.precision, slot.result.admitted,
                                  self.order, self.L, True, slot.ps.pairs[gamma < self.group_gamma],
-                                 slot.snap)
+                                 slot.snap, self.ptab, self.ctx)
                     if slot.ps is not None:
                         self._pairs_startup(slot)
             slot.item.lanes = self.lanes
@@ -308,44 +308,60 @@ class Server:
 
     def _queue_pairs(self, stepped):
         """Queue the advance of every grouped system's pairs that were in its last
-        block; their tensors and times reached the pinned host buffer before the
-        selection's host sync of this iteration.  A pair whose perturbation has
-        grown past split_gamma returns to the N-body system instead (only in a
-        system that took a block step in this iteration, `stepped`: slot -> its
-        block time)."""
-        if self._tid_host is None:
+        block, all systems in one pass and one queued call: their tensors and times
+        reached the pinned host buffers before the selection's host sync of this
+        iteration.  A pair whose perturbation has grown past split_gamma returns to
+        the N-body system instead (only in a system that took a block step in this
+        iteration, `stepped`: slot -> its block time).  Returns {slot: message} of
+        systems whose pair return failed."""
+        tab = self.ptab
+        live = set(id(ps) for ps in tab.sets)
+        sets = [(sl, sl.ps) for sl in self._tid_slots
+                if sl.ps is not None and id(sl.ps) in live and sl.ps.np and sl in self.slots]
+        if self._tid_host is None or not sets:
             return {}
-        host = self._tid_host.numpy()
-        splits = []
-        for sl in self._tid_slots:
-            if sl.prev_t is None or sl not in self.slots:
-                continue
-            k, o = sl.ps.np, sl.tid_off
-            tcm = host[o + 9 * k: o + 10 * k]
-            idx = sl.ps.due(tcm, sl.prev_t)
-            if not idx.size:
-                continue
-            Tn = host[o: o + 9 * k].reshape(9, k).T[idx]
-            out = np.zeros(idx.size, dtype=bool)
-            if sl in stepped and self.split_gamma > 0:
-                out = sl.ps.perturbation(T=Tn, idx=idx) > self.split_gamma
-            if np.any(~out):
-                sl.ps.advance(self.ctx, idx[~out], sl.prev_t, Tn[~out], self.per_period,
-                              self.max_sub)
-            if np.any(out):
-                splits.append((sl, idx[out], Tn[out]))
+        k = np.array([ps.np for _, ps in sets], dtype=np.int64)
+        tot = int(k.sum())
+        local = np.arange(tot) - np.repeat(np.cumsum(k) - k, k)
+        rows = np.repeat([ps.base for _, ps in sets], k) + local        # table rows
+        tid = np.repeat([ps.tid_base for _, ps in sets], k)             # their tidal offsets
+        owner = np.repeat(np.arange(len(sets)), k)
+        pt = tab.prev_t[rows]
+        tcm = self._tcm_host.numpy()[tid + local]
+        due = np.flatnonzero((tcm == pt) & (tab.tpair[rows] < pt))
+        if not due.size:
+            return {}
+        r, o, t_b = rows[due], owner[due], pt[due]
+        # tensor component c of pair `local` of a system at 9 tid_base + c np + local
+        gi = (9 * tid[due] + local[due])[:, None] + np.arange(9)[None, :] * k[o][:, None]
+        Tn = self._tid_host.numpy()[gi]
+        out = np.zeros(due.size, dtype=bool)
+        if self.split_gamma > 0:
+            may = np.array([sl in stepped for sl, _ in sets])[o]
+            if np.any(may):
+                out[may] = tab.perturbation(r[may], Tn[may]) > self.split_gamma
+        adv = ~out
+        if np.any(adv):
+            ra = r[adv]
+            H = t_b[adv] - tab.tpair[ra]
+            T0 = tab.T[ra].copy()
+            tab.T[ra] = Tn[adv]
+            tab.tpair[ra] = t_b[adv]
+            tab.advance(self.ctx, ra, H, T0, Tn[adv], self.per_period, self.max_sub)
         failed = {}
-        for sl, ks, Tk in splits:
+        for q in np.unique(o[out]):
+            sl, ps = sets[q]
+            sel = out & (o == q)
             try:
-                self._split(sl, ks, Tk, stepped[sl])
+                self._split(sl, r[sel] - ps.base, Tn[sel], float(t_b[sel][0]), stepped[sl])
             except (NbError, ValueError) as e:
                 failed[sl] = "pair return failed: %s" % e
         return failed
 
-    def _split(self, sl, ks, Tk, t_now):
+    def _split(self, sl, ks, Tk, t_prev, t_now):
         """Return pairs ks of a grouped system to the N-body system as two bodies at
         the system's current block time t_now.  Their orbits advance to their last
-        block (tensor Tk there), then to t_now with the tensor at t_now; each pair's
+        block t_prev (tensor Tk there), then to t_now with the tensor at t_now; each pair's
         centre of mass at t_now (its corrected state if it was in this block, else
         its prediction) is replaced by the two members; their accelerations and
         jerks come from the predicted set at t_now and their steps from the startup
@@ -354,7 +370,7 @@ class Server:
         ps, ctx = sl.ps, self.ctx
         eps = float(sl.req.eps)
         ps.drain(ctx)
-        ps.advance(ctx, ks, sl.prev_t, Tk, self.per_period, self.max_sub, queue=False)
+        ps.advance(ctx, ks, t_prev, Tk, self.per_period, self.max_sub, queue=False)
         cm_rows = ps.cm0 + ks
         T = torch.zeros(9 * ks.size, dtype=torch.float64, device=self.device)
         rows_dev = torch.as_tensor(cm_rows.astype(np.int32), device=self.device)
@@ -384,7 +400,7 @@ class Server:
             one.r, one.w = ps.r[ks[q]: ks[q] + 1].copy(), ps.w[ks[q]: ks[q] + 1].copy()
             xm[2 * q: 2 * q + 2], vm[2 * q: 2 * q + 2] = one.members(xc[q: q + 1], vc[q: q + 1])
         cap_cm = float(st["dt"][cm_rows].min())
-        new_ps = ps.without(ks)
+        new_ps = ps.without(ks, ctx)
         # the new reduced system: bodies in no pair in index order, then the
         # remaining pairs' centres of mass (the layout nb_pairs_reduce makes)
         old_row = {int(i): r for r, i in enumerate(ps.singles)}
@@ -434,29 +450,32 @@ class Server:
         self._tid_stale = True
 
     def _tidal_layout(self):
-        """One device buffer and one pinned host buffer for the tidal outputs of every
-        resident grouped system (10 doubles per pair: the tensor, then the centre of
-        mass's time), rebuilt when the resident set changes."""
-        gs = self._grouped()
-        off = 0
+        """Device and pinned host buffers for the tidal outputs of every resident
+        grouped system, rebuilt when the resident set changes: the tensors (9 per
+        pair) and the centres of mass' times (1 per pair) at each system's table
+        rows at this moment (its `tid_base`, kept when the table compacts later)."""
+        gs = [sl for sl in self._grouped() if sl.ps.np]
+        cap = max(self.ptab.cap, 1)
         for sl in gs:
-            sl.tid_off = off
-            off += 10 * sl.ps.np
+            sl.ps.tid_base = sl.ps.base
         self._tid_slots = gs
-        self._tid_dev = torch.zeros(max(off, 1), dtype=torch.float64, device=self.device)
-        self._tid_host = torch.zeros(max(off, 1), dtype=torch.float64).pin_memory()
+        self._tid_dev = torch.zeros(9 * cap, dtype=torch.float64, device=self.device)
+        self._tcm_dev = torch.zeros(cap, dtype=torch.float64, device=self.device)
+        self._tid_host = torch.zeros(9 * cap, dtype=torch.float64).pin_memory()
+        self._tcm_host = torch.zeros(cap, dtype=torch.float64).pin_memory()
         items = (NbTidalItem * max(len(gs), 1))()
-        base = self._tid_dev.data_ptr()
+        tb, cb = self._tid_dev.data_ptr(), self._tcm_dev.data_ptr()
         for q, sl in enumerate(gs):
             it = items[q]
             it.sys = sl.sys._struct
             it.i_idx = sl.cm_idx.data_ptr()
             it.m = sl.ps.np
             it.eps = float(sl.req.eps)
-            it.tensor = base + 8 * sl.tid_off
-            it.t_out = base + 8 * (sl.tid_off + 9 * sl.ps.np)
+            it.tensor = tb + 8 * 9 * sl.ps.tid_base
+            it.t_out = cb + 8 * sl.ps.tid_base
             it.status = sl.status.data_ptr()
         self._tid_items = items
+        self._tid_ext = max([sl.ps.tid_base + sl.ps.np for sl in gs], default=0)
         self._tid_stale = False
 
     def _tidal(self, ran_slots):
@@ -470,8 +489,10 @@ class Server:
         for q, sl in enumerate(self._tid_slots):
             items[q].m = sl.ps.np if sl in ran_slots else 0
         self._check(self.L.nb_tidal_active_batch(self.ctx.h, items, len(self._tid_slots)))
+        e = self._tid_ext
         with torch.cuda.stream(self.ctx.stream):
-            self._tid_host.copy_(self._tid_dev, non_blocking=True)
+            self._tid_host[: 9 * e].copy_(self._tid_dev[: 9 * e], non_blocking=True)
+            self._tcm_host[:e].copy_(self._tcm_dev[:e], non_blocking=True)
 
     def _retire(self, slot: _Slot, error: str | None):
         self._sync_items()
@@ -497,6 +518,8 @@ class Server:
                                    pair_w=slot.ps.w[: slot.ps.np].copy())
             elif self.keep_state:
                 r.final = slot.sys.state_numpy()
+        if slot.ps is not None:
+            slot.ps.release()
         r.finished = self._now()
         self.results.append(r)
         self.adm.release(slot.req)
@@ -577,7 +600,8 @@ class Server:
                     stepped[self.slots[k]] = float(t_next[k])
             failed = self._queue_pairs(stepped) or {}
             for sl, tb in stepped.items():
-                sl.prev_t = tb
+                if sl.ps is not None and sl.ps.np:
+                    self.ptab.prev_t[sl.ps.base: sl.ps.base + sl.ps.np] = tb
         else:
             failed = {}
         leave = np.flatnonzero((err != 0) | (done != 0))

@@ -221,3 +221,41 @@ def test_pair_perturbation_and_split_energy(L):
     want = sum(m[i] * m[j] * (1 / np.linalg.norm(q) - 1 / math.hypot(np.linalg.norm(q), 1e-5))
                for (i, j), q in zip(pairs, rr))
     assert abs(out.value - want) <= 1e-14 * abs(want)
+
+
+def test_pair_table_segments_compaction_and_removal(L):
+    """Several systems' pairs in one table: each set reads and writes only its own
+    segment, a released segment is reclaimed when the table compacts (rows keep
+    their values), and a set without some pairs keeps the others' state."""
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.groups import PairSet, PairTable
+    tab = PairTable(L, capacity=4)
+    snaps = [inputs.with_binaries(n, seed) for n, seed in ((200, 1), (300, 2), (260, 3))]
+    sets = [PairSet(L, s.x, s.v, s.m, s.meta["pairs"], tab) for s in snaps]
+    assert [ps.np for ps in sets] == [10, 15, 13] and tab.cap >= 38
+    for q, ps in enumerate(sets):
+        ps.T[:] = q + 1.0
+        ps.tpair[:] = 0.25 * q
+    r1 = sets[1].r.copy()
+    sets[0].release()
+    extra = PairSet(L, snaps[0].x, snaps[0].v, snaps[0].m, snaps[0].meta["pairs"], tab)
+    tab.reserve(tab.cap - tab.used + 1)          # forces a compaction (and growth)
+    assert sets[1].base == 0 and np.array_equal(sets[1].r, r1)
+    assert np.all(sets[1].T == 2.0) and np.all(sets[2].T == 3.0) and np.all(sets[2].tpair == 0.5)
+    assert extra.base == sets[1].np + sets[2].np
+    # advancing rows of the table equals advancing the set's own rows
+    ps = sets[2]
+    alone = PairSet(L, snaps[2].x, snaps[2].v, snaps[2].m, snaps[2].meta["pairs"])
+    T1 = np.full((ps.np, 9), 0.1)
+    for s_ in (ps, alone):
+        s_.T[:] = 0.0
+        s_.tpair[:] = 0.0
+    ctx = type("Ctx", (), {"L": L})()
+    ps.advance(ctx, np.arange(ps.np), 1e-3, T1, 32, 1 << 20, queue=False)
+    alone.advance(ctx, np.arange(alone.np), 1e-3, T1, 32, 1 << 20, queue=False)
+    assert np.array_equal(ps.r, alone.r) and np.array_equal(ps.w, alone.w)
+    # dropping pairs keeps the others' orbits, tensors and times
+    keep_r = ps.r[[0, 2, 3]].copy()
+    out = ps.without([1] + list(range(4, ps.np)))
+    assert out.np == 3 and np.array_equal(out.r, keep_r) and np.all(out.tpair == 1e-3)
+    assert out.cm0 == out.n - 2 * out.np and ps not in tab.sets and out in tab.sets

@@ -58,24 +58,20 @@ def test_self_term_excluded(orc):
 
 
 def test_stored_energy_of_the_2pow20_sphere():
-    """The stored oracle energies of the N = 2^20 Plummer sphere (seed 3; written by
-    tests/golden/make_energy_plummer_2pow20.py, which calls only the oracle) belong
-    to that sphere: the kinetic energy equals sum m v^2 / 2 of the regenerated
-    bodies, the unsoftened potential is the Plummer model's W = -1/2 (Henon units)
-    within sampling noise, and softening raises it by a small positive amount."""
+    """The stored oracle energy of the N = 2^20 Plummer sphere (seed 3, eps = 1e-4;
+    written by tests/golden/make_energy_plummer_2pow20.py, which calls only the
+    oracle) belongs to that sphere: the kinetic energy equals sum m v^2 / 2 of the
+    regenerated bodies, and the potential is the Plummer model's W = -1/2 (Henon
+    units) within sampling noise (softening at 1e-4 shifts it by about 1e-7)."""
     import json
     import os
 
     from paper_1411_5234_amd import inputs
     path = os.path.join(os.path.dirname(__file__), "golden", "energy_plummer_2pow20_seed3.json")
     with open(path) as f:
-        rec = json.load(f)["energy"]
+        rec = json.load(f)["energy"]["0.0001"]
     s = inputs.plummer(1 << 20, 3)
     T = 0.5 * float((s.m * (s.v ** 2).sum(1)).sum())
-    for eps in ("0.0001", "0"):
-        assert rec[eps]["kinetic"] == pytest.approx(T, rel=1e-13)
-        assert rec[eps]["total"] == pytest.approx(rec[eps]["kinetic"] + rec[eps]["potential"],
-                                                  rel=1e-15)
-    W0, W1 = rec["0"]["potential"], rec["0.0001"]["potential"]
-    assert abs(W0 + 0.5) < 5e-3
-    assert 0 < W1 - W0 < 1e-3 * abs(W0)
+    assert rec["kinetic"] == pytest.approx(T, rel=1e-13)
+    assert rec["total"] == pytest.approx(rec["kinetic"] + rec["potential"], rel=1e-15)
+    assert abs(rec["potential"] + 0.5) < 5e-3
