@@ -388,19 +388,26 @@ nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
 
 /* The tidal tensor of many systems in one launch (a served ensemble whose pairs
  * are carried as centre-of-mass bodies).  Per item, as nb_tidal_active over the
- * whole j-range [0, sys.n), at the bodies i_idx[0 .. m), into `tensor` (device,
- * 9*m doubles, (3a+b)*m + k); `t_out` (device, m doubles, or NULL) receives each
- * listed body's time t_i, so the host can tell which pairs were in the last
- * block.  `status`: the item's device error word (NULL: the context's).  Items
- * with m == 0 are skipped.  Returns NB_EINVAL for a bad item (nothing enqueued). */
+ * whole j-range [0, sys.n), at the bodies i = i_idx[0 .. m).  With row0 < 0 body k
+ * of the list writes row k; with row0 >= 0 body i writes row i - row0 and bodies
+ * with i < row0 write nothing, so the active list of a block step gives the
+ * tensors of exactly the centre-of-mass bodies (rows row0 .. row0 + nrows - 1 of
+ * the system) that were in the block.  `tensor`: device, 9 rows of nrows doubles
+ * (nrows = m when row0 < 0), T_ab of row q at tensor[(3a+b)*nrows + q]; `t_out`
+ * (device, one double per row, or NULL) receives the body's time t_i, so the host
+ * can tell which pairs were in the last block.  `status`: the item's device error
+ * word (NULL: the context's).  Items with m == 0 are skipped.  Returns NB_EINVAL
+ * for a bad item (nothing enqueued). */
 typedef struct {
     nb_system sys;
     const int32_t *i_idx;  /* device: listed bodies                       */
     int32_t m;
     double eps;            /* >= 0                                        */
-    double *tensor;        /* device, 9*m                                 */
-    double *t_out;         /* device, m, or NULL                          */
+    double *tensor;        /* device, 9 * nrows                           */
+    double *t_out;         /* device, nrows, or NULL                      */
     int32_t *status;       /* device word, or NULL                        */
+    int64_t row0;          /* < 0: row = list position; else row = i - row0 */
+    int64_t nrows;         /* rows of the outputs when row0 >= 0          */
 } nb_tidal_item;
 nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t n_items);
 

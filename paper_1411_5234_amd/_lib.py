@@ -59,7 +59,8 @@ class NbBatchItem(C.Structure):
 
 class NbTidalItem(C.Structure):
     _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("m", C.c_int32), ("eps", C.c_double),
-                ("tensor", C.c_void_p), ("t_out", C.c_void_p), ("status", C.c_void_p)]
+                ("tensor", C.c_void_p), ("t_out", C.c_void_p), ("status", C.c_void_p),
+                ("row0", C.c_int64), ("nrows", C.c_int64)]
 
 
 class NbError(RuntimeError):

@@ -1456,6 +1456,8 @@ nb_status nb_tidal_active(nb_ctx *ctx, const nb_system *sys, const int32_t *i_id
     items[0].j1 = j1;
     items[0].eps2 = eps * eps;
     items[0].tensor = tensor;
+    items[0].row0 = -1;
+    items[0].nrows = m;
     std::vector<int64_t> blocks{m};
     Table t;
     NB_TRY(make_table(ctx, items, blocks, &t));
@@ -1479,6 +1481,8 @@ nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t
         if (b.m == 0) continue;
         if (!b.i_idx || !b.tensor)
             return fail(ctx, NB_EINVAL, "item %d: i_idx or tensor is NULL", (int)k);
+        if (b.row0 >= 0 && (b.row0 > b.sys.n || b.nrows < 0 || b.row0 + b.nrows > b.sys.n))
+            return fail(ctx, NB_EINVAL, "item %d: bad row0 / nrows", (int)k);
         Item it = base_item(ctx, b.sys);
         if (b.status) it.status = b.status;
         it.i_idx = b.i_idx;
@@ -1488,6 +1492,8 @@ nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t
         it.eps2 = b.eps * b.eps;
         it.tensor = b.tensor;
         it.t_out = b.t_out;
+        it.row0 = b.row0 >= 0 ? b.row0 : -1;
+        it.nrows = b.row0 >= 0 ? b.nrows : b.m;
         dev.push_back(it);
         blocks.push_back(b.m);
     }

@@ -23,11 +23,13 @@
 
 namespace nbk {
 
-// T[(3a+b) m + k] = sum_{j != i} m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),
+// T[(3a+b) nrows + row] = sum_{j != i} m_j (3 r_a r_b / s^(5/2) - delta_ab / s^(3/2)),
 // r = xp_j - xp_i, s = |r|^2 + eps^2, for the k-th listed body i of an item, into
-// the item's `tensor` (and the body's time t_i into its `t_out`, when set).
-// Each thread sums a strided slice of j in order; the 256 partial sums are
-// combined in a fixed tree order.
+// the item's `tensor` (and the body's time t_i into its `t_out`, when set), at
+// row k, or, with row0 >= 0, at row i - row0 (bodies below row0 write nothing:
+// an active list whose centre-of-mass bodies start at row0).  Each thread sums a
+// strided slice of j in order; the 256 partial sums are combined in a fixed tree
+// order.
 __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int64_t *starts,
                                                    int n_items)
 {
@@ -35,13 +37,15 @@ __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int6
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
     const int64_t k = (int64_t)blockIdx.x - starts[it_k];   // one workgroup per body
-    const int64_t m = p.m;
     int64_t i = p.i_idx ? (int64_t)p.i_idx[k] : k;
     if (i < 0 || i >= p.s.n) {
         if (threadIdx.x == 0)
             atomicOr(p.status, (int)NBK_EINDEX);
         i = 0;
     }
+    const int64_t row = p.row0 >= 0 ? i - p.row0 : k;
+    if (row < 0 || row >= p.nrows)   // the same for every thread of the workgroup
+        return;
     const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp, *mass = p.s.m;
     const double xi = xp[i], yi = yp[i], zi = zp[i];
     double acc[9];
@@ -74,9 +78,9 @@ __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int6
         __syncthreads();
     }
     if (threadIdx.x < 9)
-        p.tensor[threadIdx.x * m + k] = part[threadIdx.x][0];
+        p.tensor[threadIdx.x * p.nrows + row] = part[threadIdx.x][0];
     if (threadIdx.x == 9 && p.t_out)
-        p.t_out[k] = p.s.t[i];
+        p.t_out[row] = p.s.t[i];
 }
 
 hipError_t launch_tidal(const Table &t, hipStream_t st)

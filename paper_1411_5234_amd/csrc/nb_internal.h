@@ -61,8 +61,10 @@ struct Item {
     int64_t sel_off;             // selection: first slot of this item's temporaries
     int32_t sel_blocks;          // selection: workgroups
     int32_t red_lanes;           // partial reduction: lanes per output value
-    double *tensor;              // tidal tensor output, rows (3a+b)*m + k
+    double *tensor;              // tidal tensor output, rows (3a+b)*nrows + row
     double *t_out;               // tidal: time of each listed body (or null)
+    int64_t row0;                // tidal: output row = i - row0 (bodies below skipped), or k if < 0
+    int64_t nrows;               // tidal: row stride of the output
 };
 
 // Per-item selection results written by the selection kernels.

@@ -290,6 +290,21 @@ class PairSet:
             raise ValueError("bad reduced state")
         return x, v
 
+    def members_of(self, idx, xc, vc):
+        """Positions and velocities of the members of pairs idx (rows in the order of
+        pairs[idx].ravel()) from their centres of mass xc, vc and their r, w."""
+        idx = np.asarray(idx)
+        k = idx.size
+        m = np.ascontiguousarray(self.m[self.pairs[idx].ravel()])
+        local = np.arange(2 * k, dtype=np.int64).reshape(k, 2)
+        xc, vc = np.ascontiguousarray(xc, dtype=np.float64), np.ascontiguousarray(vc, dtype=np.float64)
+        r, w = np.ascontiguousarray(self.r[idx]), np.ascontiguousarray(self.w[idx])
+        x, v = np.empty((2 * k, 3)), np.empty((2 * k, 3))
+        if self.L.nb_pairs_members(2 * k, _p(xc), _p(vc), _p(m), k, _p(local), _p(r), _p(w),
+                                   _p(x), _p(v)) != 0:
+            raise ValueError("bad pair state")
+        return x, v
+
     def energy(self):
         """The pairs' two-body and tidal energy (the pair part of the conserved
         quantity)."""
@@ -326,6 +341,14 @@ class GroupedIntegrator:
         self.T_dev = torch.zeros(9 * k, dtype=torch.float64, device=device)
         self.T_host = torch.zeros(9 * k, dtype=torch.float64).pin_memory()
         self.tcm_host = torch.zeros(k, dtype=torch.float64).pin_memory()
+        # the block's tensors: the active list, centre-of-mass bodies writing their rows
+        self._tid_item = _lib.NbTidalItem()
+        self._tid_item.sys = self.sys._struct
+        self._tid_item.i_idx = self.it.i_idx.data_ptr()
+        self._tid_item.eps = float(p.eps)
+        self._tid_item.tensor = self.T_dev.data_ptr()
+        self._tid_item.row0 = self.cm0
+        self._tid_item.nrows = self.np
         self._prev_t = None                       # block time of the last GPU step
         self.cpu_seconds = 0.0                    # pair advance run on this thread
         self.wait_seconds = 0.0                   # time blocked waiting for the queue
@@ -355,14 +378,20 @@ class GroupedIntegrator:
             pass
 
     # ---- GPU side --------------------------------------------------------------------
-    def _tidal_to_host(self):
-        """Tidal tensors of every pair at the current predicted set, and the pairs'
-        centre-of-mass times, copied back asynchronously."""
+    def _tidal_to_host(self, m=None):
+        """Tidal tensors at the current predicted set -- of the pairs whose centre of
+        mass is in the active block of m bodies (every pair when m is None) -- and
+        the pairs' centre-of-mass times, copied back asynchronously."""
         if self.np == 0:
             return
-        self.ctx._check(self.ctx.L.nb_tidal_active(
-            self.ctx.h, self.sys.ref, self.cm_idx.data_ptr(), self.np, 0, self.sys.n,
-            float(self.p.eps), self.T_dev.data_ptr()))
+        if m is None:
+            self.ctx._check(self.ctx.L.nb_tidal_active(
+                self.ctx.h, self.sys.ref, self.cm_idx.data_ptr(), self.np, 0, self.sys.n,
+                float(self.p.eps), self.T_dev.data_ptr()))
+        elif m:
+            it = self._tid_item
+            it.m = int(m)
+            self.ctx._check(self.ctx.L.nb_tidal_active_batch(self.ctx.h, C.byref(it), 1))
         self.T_host.copy_(self.T_dev, non_blocking=True)
         self.tcm_host[: self.np].copy_(self.sys.row("t")[self.cm0:], non_blocking=True)
 
@@ -399,7 +428,7 @@ class GroupedIntegrator:
         t_next, m = self.ctx.select_active(self.sys, self.it.i_idx)
         self._launch()
         self.it._advance(t_next, m)
-        self._tidal_to_host()
+        self._tidal_to_host(m)
         self._prev_t = t_next
         return t_next, m
 
@@ -414,7 +443,7 @@ class GroupedIntegrator:
                 log.append((t_next, self.it.i_idx[:m].cpu().numpy().astype(np.int64)))
             self._launch()
             self.it._advance(t_next, m)
-            self._tidal_to_host()
+            self._tidal_to_host(m)
             self._prev_t = t_next
         self.ctx.sync()
         self._launch()

@@ -206,6 +206,7 @@ class Server:
         self._tid_dev = None
         self._tid_host = None
         self._tid_slots = []
+        self._returned = set()
         self.order = order
         _lib.force_plan(1, 1, "mixed", lanes)     # raises on a target out of range
         self.lanes = int(lanes)
@@ -391,14 +392,7 @@ class Server:
         xc = np.where(at_now[:, None], st["x"][cm_rows], st["xp"][cm_rows])
         vc = np.where(at_now[:, None], st["v"][cm_rows], st["vp"][cm_rows])
         members = ps.pairs[ks].ravel()
-        xm, vm = np.empty((2 * ks.size, 3)), np.empty((2 * ks.size, 3))
-        for q in range(ks.size):
-            one = PairSet.__new__(PairSet)
-            one.L, one.n, one.np = self.L, 2, 1
-            one.m = np.ascontiguousarray(ps.m[ps.pairs[ks[q]]])
-            one.pairs = np.array([[0, 1]], dtype=np.int64)
-            one.r, one.w = ps.r[ks[q]: ks[q] + 1].copy(), ps.w[ks[q]: ks[q] + 1].copy()
-            xm[2 * q: 2 * q + 2], vm[2 * q: 2 * q + 2] = one.members(xc[q: q + 1], vc[q: q + 1])
+        xm, vm = ps.members_of(ks, xc, vc)
         cap_cm = float(st["dt"][cm_rows].min())
         new_ps = ps.without(ks, ctx)
         # the new reduced system: bodies in no pair in index order, then the
@@ -444,6 +438,7 @@ class Server:
                                                 self.eta_s, cap, self.dt_min))
         ctx.sync()
         sl.sys, sl.n, sl.ps = sysn, n_new, new_ps
+        self._returned.add(sl)
         sl._work_buffers()
         sl.cm_idx = torch.arange(new_ps.cm0, n_new, dtype=torch.int32, device=self.device)
         self._arr = None
@@ -468,18 +463,21 @@ class Server:
         for q, sl in enumerate(gs):
             it = items[q]
             it.sys = sl.sys._struct
-            it.i_idx = sl.cm_idx.data_ptr()
-            it.m = sl.ps.np
+            it.i_idx = sl.i_idx.data_ptr()        # the block's active list, set per step
+            it.m = 0
             it.eps = float(sl.req.eps)
             it.tensor = tb + 8 * 9 * sl.ps.tid_base
             it.t_out = cb + 8 * sl.ps.tid_base
             it.status = sl.status.data_ptr()
+            it.row0 = sl.ps.cm0                   # only centre-of-mass bodies write
+            it.nrows = sl.ps.np
         self._tid_items = items
         self._tid_ext = max([sl.ps.tid_base + sl.ps.np for sl in gs], default=0)
         self._tid_stale = False
 
     def _tidal(self, ran_slots):
-        """Tidal tensors of the grouped systems that ran a block step this iteration,
+        """Tidal tensors at the centres of mass that were in this iteration's block of
+        each grouped system that ran one (`ran_slots`: slot -> active-block size),
         from the predicted set of that step, copied to the pinned host buffer."""
         if self._tid_stale:
             self._tidal_layout()
@@ -487,7 +485,15 @@ class Server:
             return
         items = self._tid_items
         for q, sl in enumerate(self._tid_slots):
-            items[q].m = sl.ps.np if sl in ran_slots else 0
+            if sl in self._returned:
+                # pairs returned this iteration: the system's bodies were renumbered
+                # after its block, so every pair's tensor is taken (the times tell
+                # the pairs of the block from the others)
+                items[q].i_idx = sl.cm_idx.data_ptr()
+                items[q].m = sl.ps.np if sl in ran_slots else 0
+            else:
+                items[q].i_idx = sl.i_idx.data_ptr()
+                items[q].m = ran_slots.get(sl, 0)
         self._check(self.L.nb_tidal_active_batch(self.ctx.h, items, len(self._tid_slots)))
         e = self._tid_ext
         with torch.cuda.stream(self.ctx.stream):
@@ -582,6 +588,8 @@ class Server:
                                              self.dt_min))
         # copies: a pair's return to the N-body system below rebuilds the item array
         err, done, t_next = v["error"].copy(), v["done"].copy(), v["t_next"].copy()
+        at_step = list(self.slots)
+        self._returned = set()
         m_blk = v["m"].astype(np.int64)
         ran = (err == 0) & (done == 0)
         n = self._n
@@ -613,7 +621,7 @@ class Server:
         if self.groups:
             for sl, _ in gone:
                 stepped.pop(sl, None)
-            self._tidal(stepped)
+            self._tidal({sl: int(m_blk[k]) for k, sl in enumerate(at_step) if sl in stepped})
 
     # ---- driving a request stream ------------------------------------------------
     def run(self, requests, realtime: bool = True, on_iteration=None):

@@ -259,3 +259,16 @@ def test_pair_table_segments_compaction_and_removal(L):
     out = ps.without([1] + list(range(4, ps.np)))
     assert out.np == 3 and np.array_equal(out.r, keep_r) and np.all(out.tpair == 1e-3)
     assert out.cm0 == out.n - 2 * out.np and ps not in tab.sets and out in tab.sets
+
+
+def test_members_of_some_pairs_match_the_full_reconstruction(L):
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.groups import PairSet
+    s = inputs.with_binaries(400, 11)
+    ps = PairSet(L, s.x, s.v, s.m, s.meta["pairs"])
+    x, v = ps.members(ps.xr, ps.vr)
+    np.testing.assert_allclose(x, s.x, rtol=0, atol=1e-15)
+    ks = np.array([3, 0, 7])
+    xm, vm = ps.members_of(ks, ps.xr[ps.cm0 + ks], ps.vr[ps.cm0 + ks])
+    rows = ps.pairs[ks].ravel()
+    assert np.array_equal(xm, x[rows]) and np.array_equal(vm, v[rows])
