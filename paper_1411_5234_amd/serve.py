@@ -454,10 +454,16 @@ class Server:
         for sl in gs:
             sl.ps.tid_base = sl.ps.base
         self._tid_slots = gs
-        self._tid_dev = torch.zeros(9 * cap, dtype=torch.float64, device=self.device)
-        self._tcm_dev = torch.zeros(cap, dtype=torch.float64, device=self.device)
-        self._tid_host = torch.zeros(9 * cap, dtype=torch.float64).pin_memory()
-        self._tcm_host = torch.zeros(cap, dtype=torch.float64).pin_memory()
+        if self._tid_dev is None or self._tcm_dev.numel() < cap:
+            # sized to the table's capacity, which grows geometrically: a rebuild of
+            # the layout (admission, retirement, a pair's return) reuses them
+            self._tid_dev = torch.zeros(9 * cap, dtype=torch.float64, device=self.device)
+            self._tcm_dev = torch.zeros(cap, dtype=torch.float64, device=self.device)
+            self._tid_host = torch.zeros(9 * cap, dtype=torch.float64).pin_memory()
+            self._tcm_host = torch.zeros(cap, dtype=torch.float64).pin_memory()
+        # rows of a moved or new system must not show an earlier owner's block time
+        with torch.cuda.stream(self.ctx.stream):
+            self._tcm_dev.fill_(float("nan"))
         items = (NbTidalItem * max(len(gs), 1))()
         tb, cb = self._tid_dev.data_ptr(), self._tcm_dev.data_ptr()
         for q, sl in enumerate(gs):
