@@ -42,13 +42,8 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per force launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
 # plain-copy calibration: x2.0 fetch, x1.0 write), keyed by the hash of the force
 # kernel's sources, the precision, N and the launch plan.  Reported only for that
-# exact kernel and launch; null otherwise.  The counters were taken with the
-# sources of hashes 9e96cd04d187ddd4 / 9934743e5b1fc733; the only change since
-# (the cross-lane group sum of plans with S > 1) leaves the machine code of the
-# S = 1 launches measured here byte for byte the same (compared in the assembly of
-# both builds), so the figures are keyed to the current sources.
-TRAFFIC = {("96d0468f6286faf8", "mixed", 1 << 20, (2, 1, 4)): 2.7712e9 + 2.0133e8,
-           ("a46af5a77bcfb013", "mixed", 1 << 20, (2, 1, 4)): 3.6469e9 + 3.6029e8}
+# exact kernel and launch; null otherwise.  Taken with the current sources.
+TRAFFIC = {("69214b403c3b8785", "mixed", 1 << 20, (2, 1, 4)): 2.7709e9 + 2.0133e8}
 
 
 def _kernel_source_hash(order=4):
