@@ -78,6 +78,12 @@ def lib():
         L.orc_tidal.restype = C.c_int
         L.orc_tidal.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, C.c_int64, C.c_int64,
                                 C.c_double, _dp]
+        L.orc_tidal_points.restype = C.c_int
+        L.orc_tidal_points.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _dp, _ip, C.c_double,
+                                       _dp]
+        L.orc_nearest.restype = C.c_int
+        L.orc_nearest.argtypes = [C.c_int64, _dp, C.c_int64, _ip, C.c_int64, C.c_void_p,
+                                  C.c_double, _ip, _dp]
         L.orc_kepler_drift.restype = C.c_int
         L.orc_kepler_drift.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp, _dp]
         L.orc_group_advance.restype = C.c_int
@@ -433,6 +439,34 @@ def tidal(x, m, eps, ilist=None, j0=0, j1=None):
     T = np.zeros(9 * ilist.size)
     _check(lib().orc_tidal(n, x, m, ilist.size, ilist, int(j0), j1, float(eps), T))
     return T.reshape(-1, 3, 3)
+
+
+def tidal_points(x, m, eps, points, excl=None):
+    """Tidal tensor (k, 3, 3) of the softened field at the points (k, 3), leaving out
+    the bodies excl[k] (k, 2; -1: none) for point k."""
+    x, m, points = _c(x), _c(m), _c(np.reshape(points, (-1, 3)))
+    k = points.shape[0]
+    excl = np.full((k, 2), -1, dtype=np.int64) if excl is None else _c(excl, np.int64)
+    T = np.zeros(9 * k)
+    _check(lib().orc_tidal_points(m.shape[0], x, m, k, points, excl.reshape(-1), float(eps), T))
+    return T.reshape(-1, 3, 3)
+
+
+def nearest(x, ilist=None, row_end=None, dt=None, dt_cap=float("inf")):
+    """Nearest other body of each listed body (lowest index on equal distances) and
+    its squared distance; -1 / inf for bodies not searched (index >= row_end, or
+    dt > dt_cap)."""
+    x = _c(x)
+    n = x.shape[0]
+    ilist = np.arange(n, dtype=np.int64) if ilist is None else _c(ilist, np.int64)
+    row_end = n if row_end is None else int(row_end)
+    dtp = None if dt is None else _c(dt)
+    nn = np.empty(ilist.size, dtype=np.int64)
+    r2 = np.empty(ilist.size)
+    _check(lib().orc_nearest(n, x, ilist.size, ilist, row_end,
+                             None if dtp is None else dtp.ctypes.data_as(C.c_void_p),
+                             float(dt_cap), nn, r2))
+    return nn, r2
 
 
 def kepler_drift(M, r, v, dt):

@@ -676,6 +676,87 @@ int orc_tidal(int64_t n, const double *x, const double *m, int64_t ni, const int
     return 0;
 }
 
+/* ---- tidal tensor at a point -----------------------------------------------------
+ * The tidal tensor of the softened field at arbitrary points p_k, with up to two
+ * bodies left out per point (excl[2k], excl[2k+1]; -1 leaves out none): the field
+ * of the rest of the system at the centre of mass of a pair that is about to be
+ * taken out of the N-body system.  The same sum as orc_tidal with r = x_j - p_k.
+ */
+int orc_tidal_points(int64_t n, const double *x, const double *m, int64_t np,
+                     const double *p, const int64_t *excl, double eps, double *T)
+{
+    for (int64_t k = 0; k < 2 * np; k++)
+        if (excl[k] < -1 || excl[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < np; k++) {
+        csum acc[9];
+        for (int q = 0; q < 9; q++) {
+            acc[q].s = 0.0;
+            acc[q].c = 0.0;
+        }
+        for (int64_t j = 0; j < n; j++) {
+            if (j == excl[2 * k] || j == excl[2 * k + 1])
+                continue;
+            double d[3];
+            for (int c = 0; c < 3; c++)
+                d[c] = x[3 * j + c] - p[3 * k + c];
+            const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+            const double w3 = m[j] / (s * sqrt(s));          /* m / s^(3/2) */
+            const double w5 = 3.0 * w3 / s;                  /* 3 m / s^(5/2) */
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++)
+                    cs_add(&acc[3 * a + b], w5 * d[a] * d[b] - (a == b ? w3 : 0.0));
+        }
+        for (int q = 0; q < 9; q++)
+            T[9 * k + q] = cs_val(&acc[q]);
+    }
+    return 0;
+}
+
+/* ---- nearest neighbour ------------------------------------------------------------
+ * For each listed body i: the other body j (any index in [0, n)) with the least
+ * squared distance |x_j - x_i|^2, formed as (dx dx + dy dy) + dz dz in FP64 without
+ * contraction; the lowest j among equal distances.  A listed body is searched
+ * only if i < row_end and dt_i <= dt_cap (dt may be NULL: every body qualifies);
+ * otherwise, or when no other body exists, nn = -1 and r2 = +inf.  This is how
+ * candidates for a new bound pair are found: two bodies of the same block that
+ * are each other's nearest neighbour.
+ */
+int orc_nearest(int64_t n, const double *x, int64_t ni, const int64_t *ilist, int64_t row_end,
+                const double *dt, double dt_cap, int64_t *nn, double *r2)
+{
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        int64_t best = -1;
+        double bd = INFINITY;
+        if (i < row_end && (!dt || dt[i] <= dt_cap)) {
+            for (int64_t j = 0; j < n; j++) {
+                if (j == i)
+                    continue;
+                const double dx = x[3 * j] - x[3 * i];
+                const double dy = x[3 * j + 1] - x[3 * i + 1];
+                const double dz = x[3 * j + 2] - x[3 * i + 2];
+                const double d = dx * dx + dy * dy + dz * dz;
+                if (d < bd) {
+                    bd = d;
+                    best = j;
+                }
+            }
+        }
+        nn[k] = best;
+        r2[k] = best >= 0 ? bd : INFINITY;
+    }
+    return 0;
+}
+
 /* ---- Kepler drift -----------------------------------------------------------------
  * Exact motion of the relative coordinate of an isolated bound pair of total
  * mass M over a time dt (r'' = -M r / |r|^3), by the f and g functions of the

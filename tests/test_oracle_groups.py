@@ -59,6 +59,91 @@ def test_tidal_symmetry_trace_and_ranges(orc):
     np.testing.assert_allclose(lo + hi, T, rtol=0, atol=1e-12 * np.abs(T).max())
 
 
+def _phi_rest_mp(y, xs, ms, eps, skip):
+    """Softened potential at point y from every body not in `skip` (40-digit)."""
+    tot = mp.mpf(0)
+    for j in range(len(ms)):
+        if j in skip:
+            continue
+        d2 = sum((y[c] - xs[j][c]) ** 2 for c in range(3))
+        tot -= ms[j] / mp.sqrt(d2 + eps * eps)
+    return tot
+
+
+def test_tidal_at_points_is_minus_hessian_of_the_rest(orc):
+    """The tensor at a pair's centre of mass from the rest of the system: the second
+    derivatives of the potential of the bodies not left out, at 40 digits."""
+    x, v, m = _tiny_system(11, n=6)
+    eps = 0.05
+    cm = (m[0] * x[0] + m[1] * x[1]) / (m[0] + m[1])
+    pts = np.array([cm, [0.3, -0.2, 0.7], x[4]])
+    excl = np.array([[0, 1], [-1, -1], [4, -1]])
+    T = orc.tidal_points(x, m, eps, pts, excl)
+    mp.mp.dps = 40
+    xs = [[mp.mpf(float(c)) for c in row] for row in x]
+    ms = [mp.mpf(float(q)) for q in m]
+    e = mp.mpf(eps)
+    for k in range(3):
+        skip = {int(q) for q in excl[k] if q >= 0}
+        p = [mp.mpf(float(c)) for c in pts[k]]
+        for a in range(3):
+            for b in range(3):
+                def F(u, w, a=a, b=b, p=p, skip=skip):
+                    y = list(p)
+                    y[a] = y[a] + u
+                    y[b] = y[b] + w
+                    return _phi_rest_mp(y, xs, ms, e, skip)
+                h = -mp.diff(F, (0, 0), (1, 1))
+                assert abs(float(h) - T[k, a, b]) <= 1e-12 * np.abs(T[k]).max(), (k, a, b)
+    # the bodies left out do not matter, wherever they are
+    x2 = x.copy()
+    x2[0] += 10.0
+    x2[1] -= 3.0
+    T2 = orc.tidal_points(x2, m, eps, pts[:1], excl[:1])
+    assert np.array_equal(T2[0], T[0])
+
+
+def _nearest_brute(x, rows, row_end, dt, dt_cap):
+    """Plain loops: the least (dx dx + dy dy) + dz dz over every other body, the lowest
+    index first among equals."""
+    out_j, out_d = [], []
+    for i in rows:
+        best, bd = -1, math.inf
+        if i < row_end and (dt is None or dt[i] <= dt_cap):
+            for j in range(len(x)):
+                if j == i:
+                    continue
+                dx = float(x[j][0]) - float(x[i][0])
+                dy = float(x[j][1]) - float(x[i][1])
+                dz = float(x[j][2]) - float(x[i][2])
+                d = dx * dx + dy * dy + dz * dz
+                if d < bd:
+                    best, bd = j, d
+        out_j.append(best)
+        out_d.append(bd)
+    return np.array(out_j), np.array(out_d)
+
+
+def test_nearest_is_the_brute_force_scan(orc):
+    rng = np.random.default_rng(5)
+    n = 60
+    x = rng.normal(size=(n, 3))
+    x[7] = x[3]                           # coincident bodies: distance 0
+    x[20] = x[10] + [0.0, 0.0, 1e-3]      # two bodies at equal distance from 10
+    x[30] = x[10] - [0.0, 0.0, 1e-3]
+    x[41] = x[40] * (1.0 + 1e-15)         # a near tie far from the origin
+    dt = rng.choice([2.0 ** -12, 2.0 ** -6], n)
+    for rows, row_end, dtv, cap in ((np.arange(n), n, None, math.inf),
+                                    (np.array([3, 7, 10, 40, 41, 59, 0]), 45, dt, 2.0 ** -10)):
+        nn, r2 = orc.nearest(x, rows, row_end, dtv, cap)
+        wj, wd = _nearest_brute(x.tolist(), rows.tolist(), row_end, dtv, cap)
+        assert np.array_equal(nn, wj)
+        assert np.array_equal(r2, wd)
+    nn, r2 = orc.nearest(x, [3, 7, 10])
+    assert nn.tolist() == [7, 3, 20] and r2[0] == 0.0 and r2[1] == 0.0
+    assert orc.nearest(x[:1], [0])[0].tolist() == [-1]      # no other body
+
+
 # ---- Kepler drift -----------------------------------------------------------------------
 
 def _rel(m1, m2, a, e, t, M0=0.0):

@@ -122,6 +122,14 @@ MUTANTS = [
      lambda o: tg.test_group_advance_conserves_the_jacobi_integral_of_a_constant_tide(o)),
     ("tidal kicks at the substep start only", "const double w = half == 0 ? wa : wb;", "const double w = wa;",
      lambda o: tg.test_group_advance_is_second_order(o)),
+    ("nearest keeps the last of equal distances", "                if (d < bd) {", "                if (d <= bd) {",
+     lambda o: tg.test_nearest_is_the_brute_force_scan(o)),
+    ("nearest counts the body itself", "            if (j == i)\n                    continue;\n                const double dx", "            if (0)\n                    continue;\n                const double dx",
+     lambda o: tg.test_nearest_is_the_brute_force_scan(o)),
+    ("tidal at points leaves out only the first body", "if (j == excl[2 * k] || j == excl[2 * k + 1])", "if (j == excl[2 * k])",
+     lambda o: tg.test_tidal_at_points_is_minus_hessian_of_the_rest(o)),
+    ("tidal at points measured from the origin", "d[c] = x[3 * j + c] - p[3 * k + c];", "d[c] = x[3 * j + c];",
+     lambda o: tg.test_tidal_at_points_is_minus_hessian_of_the_rest(o)),
 ]
 
 
