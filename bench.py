@@ -96,6 +96,11 @@ def parse():
     ap.add_argument("--groups", action="store_true",
                     help="serve mode, C5 stream: carry each primordial binary as one body at its "
                          "centre of mass, its relative orbit advanced on CPU threads")
+    ap.add_argument("--capture-every", type=int, default=16,
+                    help="serve mode, C5 stream with --groups: every that many block steps of "
+                         "a system, single bodies of its block that are each other's nearest "
+                         "neighbours, bound and weakly perturbed become a pair (0: off; "
+                         "16 was the fastest of 4, 16 and off)")
     ap.add_argument("--precisions", default="mixed,fp64",
                     help="serve mode, C5 stream: the precisions each request is served in")
     ap.add_argument("--closed-only", action="store_true",
@@ -655,13 +660,14 @@ def mode_serve_c5(args):
     out = {"metric": "ensemble solves/s and energy error per request, mixed vs FP64",
            "mode": "serve", "config": {"workload": "c5", "requests": args.requests,
                                        "slots": args.slots, "groups": args.groups,
+                                       "capture_every": args.capture_every,
                                        "lanes": args.lanes, "precisions": precs,
                                        **{k: v for k, v in spec.items() if k != "base"}}}
     progress = _progress()
     per = {}
     for prec in precs:
         srv = Server(ctx, precision=prec, max_slots=args.slots, energy=True, lanes=args.lanes,
-                     groups=args.groups)
+                     groups=args.groups, capture_every=args.capture_every)
         t0 = time.perf_counter()
         res = srv.run(reqs, realtime=False, on_iteration=progress)
         out["closed_batch_" + prec] = summarize(res, time.perf_counter() - t0)
@@ -678,6 +684,9 @@ def mode_serve_c5(args):
                 continue
             row["pairs"] = r.pairs
             row["steps_" + prec] = r.steps
+            if args.groups:
+                row["returns_" + prec] = r.splits
+                row["captures_" + prec] = r.captures
             row["energy_error_" + prec] = r.energy_error
             if args.groups:
                 row["direct_energy_error_" + prec] = abs(r.direct1 - r.direct0) / abs(r.direct0)

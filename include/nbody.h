@@ -411,6 +411,43 @@ typedef struct {
 } nb_tidal_item;
 nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t n_items);
 
+/* The tidal tensor of the rest of the system at k arbitrary points: at the centre
+ * of mass of two bodies that are about to become a pair (Sec. 3 of the paper:
+ * tight systems found during the run are taken out of the N-body integration),
+ * the field of every body but the two.  As nb_tidal_active over [0, sys.n), with
+ * point q at (pts[q], pts[k + q], pts[2k + q]) in place of a body and the rows
+ * excl[q] and excl[k + q] left out (-1: none; excl may be NULL).  pts, excl,
+ * tensor: device; tensor as in nb_tidal_active (T_ab of point q at
+ * tensor[(3a+b)*k + q]).  Returns NB_EINVAL for eps < 0 or k < 0; k == 0 is a
+ * no-op. */
+nb_status nb_tidal_points(nb_ctx *ctx, const nb_system *sys, int32_t k, const double *pts,
+                          const int32_t *excl, double eps, double *tensor);
+
+/* The nearest neighbour of listed bodies, many systems in one launch: the
+ * search for new tight pairs during the run (Sec. 3 of the paper: groups of
+ * particles in tight systems are identified as the system evolves).  For body
+ * i = i_idx[q] of an item: the other body j in [0, sys.n) of least squared
+ * distance over the predicted set, |r|^2 = (dx dx + dy dy) + dz dz in FP64 with
+ * every operation rounded (no fused multiply-add), the lowest j among equal
+ * distances; nn[q] = j, r2[q] = |r|^2.  Bodies with i >= row_end (the
+ * centre-of-mass bodies of a grouped system) or dt_i > dt_cap are not searched:
+ * nn[q] = -1, r2[q] = +inf (also when the system has one body).  One workgroup
+ * per listed body; integer results are exact and reproducible.  i_idx, nn, r2:
+ * device; `status`: the item's device error word (NULL: the context's), which
+ * receives NB_EINDEX for an index outside [0, n).  Items with m == 0 are
+ * skipped.  Returns NB_EINVAL for a bad item (nothing enqueued). */
+typedef struct {
+    nb_system sys;
+    const int32_t *i_idx;  /* device: listed bodies                            */
+    int32_t m;
+    int64_t row_end;       /* bodies at or above this row are not searched     */
+    double dt_cap;         /* bodies with a larger step are not searched       */
+    int32_t *nn;           /* device, m: nearest other body, or -1             */
+    double *r2;            /* device, m: its squared distance, or +inf         */
+    int32_t *status;       /* device word, or NULL                             */
+} nb_nearest_item;
+nb_status nb_nearest_active_batch(nb_ctx *ctx, const nb_nearest_item *items, int32_t n_items);
+
 /* Host.  The reduced system of n bodies with n_pairs bound pairs (pairs[2k],
  * pairs[2k+1]: distinct indices in [0, n)): the bodies in no pair, in index
  * order, then one body per pair at its centre of mass, mass M = m1 + m2,

@@ -38,7 +38,8 @@ EXPORTS = ["nb_ctx_create", "nb_ctx_destroy", "nb_last_error", "nb_sync", "nb_se
            "nb_predict6", "nb_force6_active", "nb_force6_active_plan", "nb_init_steps6",
            "nb_correct6", "nb_step6", "nb_step6_batch", "nb_tidal_active", "nb_tidal_active_batch",
            "nb_pairs_reduce", "nb_pairs_members", "nb_pairs_energy", "nb_kepler_drift",
-           "nb_groups_advance", "nb_groups_advance_async", "nb_groups_wait"]
+           "nb_groups_advance", "nb_groups_advance_async", "nb_groups_wait", "nb_tidal_points",
+           "nb_nearest_active_batch"]
 
 
 class NbSystem(C.Structure):
@@ -61,6 +62,12 @@ class NbTidalItem(C.Structure):
     _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("m", C.c_int32), ("eps", C.c_double),
                 ("tensor", C.c_void_p), ("t_out", C.c_void_p), ("status", C.c_void_p),
                 ("row0", C.c_int64), ("nrows", C.c_int64)]
+
+
+class NbNearestItem(C.Structure):
+    _fields_ = [("sys", NbSystem), ("i_idx", C.c_void_p), ("m", C.c_int32),
+                ("row_end", C.c_int64), ("dt_cap", C.c_double), ("nn", C.c_void_p),
+                ("r2", C.c_void_p), ("status", C.c_void_p)]
 
 
 class NbError(RuntimeError):
@@ -123,6 +130,8 @@ def load() -> C.CDLL:
                                      C.c_int, f64, f64, f64, f64]),
         "nb_tidal_active": (C.c_int, [vp, ps, vp, i32, i64, i64, f64, vp]),
         "nb_tidal_active_batch": (C.c_int, [vp, C.POINTER(NbTidalItem), i32]),
+        "nb_tidal_points": (C.c_int, [vp, vp, i32, vp, vp, C.c_double, vp]),
+        "nb_nearest_active_batch": (C.c_int, [vp, C.POINTER(NbNearestItem), i32]),
         "nb_pairs_reduce": (C.c_int, [i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]),
         "nb_pairs_members": (C.c_int, [i64, vp, vp, vp, i32, vp, vp, vp, vp, vp]),
         "nb_pairs_energy": (C.c_int, [i32, vp, vp, vp, vp, vp, vp]),

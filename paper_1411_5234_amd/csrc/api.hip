@@ -1503,6 +1503,64 @@ nb_status nb_tidal_active_batch(nb_ctx *ctx, const nb_tidal_item *items, int32_t
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
 }
 
+nb_status nb_tidal_points(nb_ctx *ctx, const nb_system *sys, int32_t k, const double *pts,
+                          const int32_t *excl, double eps, double *tensor)
+{
+    NB_TRY(check_system(ctx, sys, true));
+    if (!(eps >= 0.0) || !isfinite(eps)) return fail(ctx, NB_EINVAL, "eps must be >= 0 and finite");
+    if (k < 0) return fail(ctx, NB_EINVAL, "k < 0");
+    if (k == 0) return NB_OK;
+    if (!pts || !tensor) return fail(ctx, NB_EINVAL, "pts or tensor is NULL");
+    std::vector<Item> items{base_item(ctx, *sys)};
+    items[0].m = k;
+    items[0].j0 = 0;
+    items[0].j1 = sys->n;
+    items[0].eps2 = eps * eps;
+    items[0].tensor = tensor;
+    items[0].row0 = -1;
+    items[0].nrows = k;
+    items[0].pts = pts;
+    items[0].excl = excl;
+    std::vector<int64_t> blocks{k};
+    Table t;
+    NB_TRY(make_table(ctx, items, blocks, &t));
+    hipError_t e = nbk::launch_tidal(t, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "tidal launch");
+}
+
+nb_status nb_nearest_active_batch(nb_ctx *ctx, const nb_nearest_item *items, int32_t n_items)
+{
+    if (!ctx) return NB_EINVAL;
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(ctx, NB_EINVAL, "bad item array");
+    std::vector<Item> dev;
+    std::vector<int64_t> blocks;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const nb_nearest_item &b = items[k];
+        NB_TRY(check_system(ctx, &b.sys, true));
+        if (b.m < 0 || (int64_t)b.m > b.sys.n)
+            return fail(ctx, NB_EINVAL, "item %d: m out of range", (int)k);
+        if (b.dt_cap != b.dt_cap)
+            return fail(ctx, NB_EINVAL, "item %d: dt_cap is NaN", (int)k);
+        if (b.m == 0) continue;
+        if (!b.i_idx || !b.nn || !b.r2)
+            return fail(ctx, NB_EINVAL, "item %d: i_idx, nn or r2 is NULL", (int)k);
+        Item it = base_item(ctx, b.sys);
+        if (b.status) it.status = b.status;
+        it.i_idx = b.i_idx;
+        it.m = b.m;
+        it.nn = b.nn;
+        it.r2 = b.r2;
+        it.row_end = b.row_end;
+        it.dt_cap = b.dt_cap;
+        dev.push_back(it);
+        blocks.push_back(b.m);
+    }
+    Table t;
+    NB_TRY(make_table(ctx, dev, blocks, &t));
+    hipError_t e = nbk::launch_nearest(t, ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e, "nearest launch");
+}
+
 nb_status nb_groups_advance_async(nb_ctx *ctx, int32_t n, const int32_t *idx, const double *M,
                                   double *r, double *v, const double *H, const double *T0,
                                   const double *T1, int32_t per_period, int64_t max_sub,

@@ -27,33 +27,49 @@ namespace nbk {
 // r = xp_j - xp_i, s = |r|^2 + eps^2, for the k-th listed body i of an item, into
 // the item's `tensor` (and the body's time t_i into its `t_out`, when set), at
 // row k, or, with row0 >= 0, at row i - row0 (bodies below row0 write nothing:
-// an active list whose centre-of-mass bodies start at row0).  Each thread sums a
-// strided slice of j in order; the 256 partial sums are combined in a fixed tree
-// order.
+// an active list whose centre-of-mass bodies start at row0).  With `pts` set the
+// k-th workgroup takes the point k of `pts` instead of a body, leaves out the two
+// rows excl[k] and excl[nrows + k] instead of i, and writes row k.  Each thread
+// sums a strided slice of j in order; the 256 partial sums are combined in a
+// fixed tree order.
 __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int64_t *starts,
                                                    int n_items)
 {
     __shared__ double part[9][WG];
     const int it_k = find_item(starts, n_items, blockIdx.x);
     const Item &p = items[it_k];
-    const int64_t k = (int64_t)blockIdx.x - starts[it_k];   // one workgroup per body
-    int64_t i = p.i_idx ? (int64_t)p.i_idx[k] : k;
-    if (i < 0 || i >= p.s.n) {
-        if (threadIdx.x == 0)
-            atomicOr(p.status, (int)NBK_EINDEX);
-        i = 0;
-    }
-    const int64_t row = p.row0 >= 0 ? i - p.row0 : k;
-    if (row < 0 || row >= p.nrows)   // the same for every thread of the workgroup
-        return;
+    const int64_t k = (int64_t)blockIdx.x - starts[it_k];   // one workgroup per body or point
     const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp, *mass = p.s.m;
-    const double xi = xp[i], yi = yp[i], zi = zp[i];
+    int64_t i = -1, skip0, skip1 = -1, row;
+    double xi, yi, zi;
+    if (p.pts) {
+        row = k;
+        xi = p.pts[k];
+        yi = p.pts[p.nrows + k];
+        zi = p.pts[2 * p.nrows + k];
+        skip0 = p.excl ? p.excl[k] : -1;
+        skip1 = p.excl ? p.excl[p.nrows + k] : -1;
+    } else {
+        i = p.i_idx ? (int64_t)p.i_idx[k] : k;
+        if (i < 0 || i >= p.s.n) {
+            if (threadIdx.x == 0)
+                atomicOr(p.status, (int)NBK_EINDEX);
+            i = 0;
+        }
+        row = p.row0 >= 0 ? i - p.row0 : k;
+        if (row < 0 || row >= p.nrows)   // the same for every thread of the workgroup
+            return;
+        xi = xp[i];
+        yi = yp[i];
+        zi = zp[i];
+        skip0 = i;
+    }
     double acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         acc[q] = 0.0;
     for (int64_t j = p.j0 + threadIdx.x; j < p.j1; j += WG) {
-        if (j == i)
+        if (j == skip0 || j == skip1)
             continue;
         const double d[3] = {xp[j] - xi, yp[j] - yi, zp[j] - zi};
         const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + p.eps2;
@@ -79,8 +95,76 @@ __global__ __launch_bounds__(WG) void tidal_kernel(const Item *items, const int6
     }
     if (threadIdx.x < 9)
         p.tensor[threadIdx.x * p.nrows + row] = part[threadIdx.x][0];
-    if (threadIdx.x == 9 && p.t_out)
+    if (threadIdx.x == 9 && p.t_out && i >= 0)
         p.t_out[row] = p.s.t[i];
+}
+
+// |r|^2 = (dx dx + dy dy) + dz dz in FP64, rounded after every operation (no fused
+// multiply-add), so that equal inputs give equal distances everywhere.
+__device__ __forceinline__ double dist2_rn(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Nearest other body of the k-th listed body i, over the whole predicted set:
+// the least dist2_rn(xp_j - xp_i), the lowest j among equal distances.  Bodies at
+// or above row_end, or with dt_i > dt_cap, are not searched (nn = -1, r2 = inf).
+// Each thread scans a strided slice of j in order; the 256 (distance, index)
+// candidates are then combined by a tree over LDS.
+__global__ __launch_bounds__(WG) void nearest_kernel(const Item *items, const int64_t *starts,
+                                                     int n_items)
+{
+    __shared__ double bd[WG];
+    __shared__ int32_t bj[WG];
+    const int it_k = find_item(starts, n_items, blockIdx.x);
+    const Item &p = items[it_k];
+    const int64_t k = (int64_t)blockIdx.x - starts[it_k];   // one workgroup per listed body
+    const int64_t n = p.s.n;
+    const int64_t i = p.i_idx ? (int64_t)p.i_idx[k] : k;
+    const bool bad = i < 0 || i >= n;
+    if (bad || i >= p.row_end || !(p.s.dt[i] <= p.dt_cap)) {   // uniform over the workgroup
+        if (threadIdx.x == 0) {
+            if (bad)
+                atomicOr(p.status, (int)NBK_EINDEX);
+            p.nn[k] = -1;
+            p.r2[k] = INFINITY;
+        }
+        return;
+    }
+    const double *xp = p.s.xp, *yp = p.s.yp, *zp = p.s.zp;
+    const double xi = xp[i], yi = yp[i], zi = zp[i];
+    double best = INFINITY;
+    int32_t bestj = -1;
+    for (int64_t j = threadIdx.x; j < n; j += WG) {
+        if (j == i)
+            continue;
+        const double d = dist2_rn(xp[j] - xi, yp[j] - yi, zp[j] - zi);
+        if (d < best) {          // j grows along the slice: the first of equals stays
+            best = d;
+            bestj = (int32_t)j;
+        }
+    }
+    bd[threadIdx.x] = best;
+    bj[threadIdx.x] = bestj;
+    __syncthreads();
+    for (int half = WG / 2; half >= 1; half >>= 1) {
+        if ((int)threadIdx.x < half) {
+            const double o = bd[threadIdx.x + half];
+            const int32_t oj = bj[threadIdx.x + half];
+            const int32_t mj = bj[threadIdx.x];
+            // (distance, index) order; -1 marks an empty slice (distance inf)
+            if (oj >= 0 && (mj < 0 || o < bd[threadIdx.x] || (o == bd[threadIdx.x] && oj < mj))) {
+                bd[threadIdx.x] = o;
+                bj[threadIdx.x] = oj;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        p.nn[k] = bj[0];
+        p.r2[k] = bj[0] >= 0 ? bd[0] : INFINITY;
+    }
 }
 
 hipError_t launch_tidal(const Table &t, hipStream_t st)
@@ -88,6 +172,14 @@ hipError_t launch_tidal(const Table &t, hipStream_t st)
     if (t.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(tidal_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items, t.starts,
                        t.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nearest(const Table &t, hipStream_t st)
+{
+    if (t.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nearest_kernel, dim3((unsigned)t.blocks), dim3(WG), 0, st, t.items,
+                       t.starts, t.n);
     return hipGetLastError();
 }
 

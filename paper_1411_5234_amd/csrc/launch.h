@@ -20,6 +20,7 @@ hipError_t launch_energy(const nb_system &s, double eps2, double *rows, double *
 
 // Tidal tensors of the listed bodies, one workgroup per body, rows (3a+b)*m + k.
 hipError_t launch_tidal(const Table &t, hipStream_t st);
+hipError_t launch_nearest(const Table &t, hipStream_t st);
 // Selection: two passes over per-item workgroup slices, then per-item results.
 hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
                          hipStream_t st);

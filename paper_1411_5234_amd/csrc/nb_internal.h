@@ -65,6 +65,12 @@ struct Item {
     double *t_out;               // tidal: time of each listed body (or null)
     int64_t row0;                // tidal: output row = i - row0 (bodies below skipped), or k if < 0
     int64_t nrows;               // tidal: row stride of the output
+    const double *pts;           // tidal at points: 3 * nrows coordinates (x, then y, then z), or null
+    const int32_t *excl;         // tidal at points: 2 * nrows rows left out (-1: none), or null
+    int32_t *nn;                 // nearest: neighbour of each listed body (-1: not searched)
+    double *r2;                  // nearest: its squared distance
+    int64_t row_end;             // nearest: listed bodies at or above this row are not searched
+    double dt_cap;               // nearest: listed bodies with a larger step are not searched
 };
 
 // Per-item selection results written by the selection kernels.

@@ -266,6 +266,42 @@ class PairSet:
         out.advanced = self.advanced
         return out
 
+    def with_pairs(self, new_pairs, M, r, w, T, a0, tpair, ctx=None):
+        """A PairSet of the same bodies with the pairs `new_pairs` (index pairs of
+        bodies in no pair) added after the existing ones, in the same table; their
+        orbits (M, r, w), tensors T and starting semimajor axes a0 are given, at time
+        tpair.  The existing pairs keep their orbits, tensors and times.  This set's
+        segment is released (its queued advances must have run)."""
+        new_pairs = np.asarray(new_pairs, dtype=np.int64).reshape(-1, 2)
+        k = new_pairs.shape[0]
+        pairs = np.ascontiguousarray(np.concatenate([self.pairs, new_pairs]))
+        if (np.unique(pairs).size != pairs.size or new_pairs.min(initial=0) < 0
+                or new_pairs.max(initial=0) >= self.n):
+            raise ValueError("new pairs must be distinct bodies in no pair")
+        saved = {name: getattr(self, name)[:].copy()
+                 for name in ("M", "r", "w", "T", "tpair", "a0", "status")}
+        self.release()
+        out = PairSet.__new__(PairSet)
+        out.L, out.m, out.n = self.L, self.m, self.n
+        out.pairs = pairs
+        out.np = out.pairs.shape[0]
+        out.cm0 = self.n - 2 * out.np
+        out.singles = np.setdiff1d(np.arange(self.n, dtype=np.int64), out.pairs.ravel())
+        out.table = self.table
+        out._attach(ctx)
+        for name, val in saved.items():
+            getattr(out, name)[: self.np] = val
+        new = slice(self.np, out.np)
+        out.M[new] = M
+        out.r[new] = r
+        out.w[new] = w
+        out.T[new] = np.asarray(T).reshape(k, 9)
+        out.a0[new] = a0
+        out.tpair[new] = tpair
+        out.status[new] = 0
+        out.advanced = self.advanced
+        return out
+
     def split_energy(self, idx, eps):
         """Change of the conserved quantity when pairs idx rejoin the N-body system
         as two bodies (their mutual potential becomes the softened one)."""

@@ -55,6 +55,8 @@ class Result:
     pairs: int = 0               # pairs carried as centre-of-mass bodies at admission
     splits: int = 0              # pairs returned to the N-body system during the run
     split_energy: float = 0.0    # change of the conserved quantity at those returns
+    captures: int = 0            # pairs formed from two single bodies during the run
+    capture_energy: float = 0.0  # change of the conserved quantity at those captures
 
     @property
     def latency(self) -> float:
@@ -63,15 +65,17 @@ class Result:
     @property
     def energy_error(self) -> float:
         """Relative error of the conserved quantity (grouped systems: the scheme's,
-        with the known change at each pair's return to the N-body system removed)."""
-        return abs(self.energy1 - self.split_energy - self.energy0) / abs(self.energy0)
+        with the known change at each pair's return to the N-body system and at each
+        capture removed)."""
+        return (abs(self.energy1 - self.split_energy - self.capture_energy - self.energy0)
+                / abs(self.energy0))
 
 
 class _Slot:
     """One resident system: device state, work buffers and its batch item."""
 
     def __init__(self, req, device, precision, now, order=4, L=None, groups=False, pairs=None,
-                 snap=None, table=None, ctx=None):
+                 snap=None, table=None, ctx=None, capture=False):
         snap = req.snapshot() if snap is None else snap
         self.req = req
         self.snap = snap
@@ -79,7 +83,9 @@ class _Slot:
         self.device = device
         if pairs is None and groups:
             pairs = snap.meta.get("pairs")
-        if pairs is not None and len(pairs):
+        if groups and capture and (pairs is None or not len(pairs)):
+            pairs = np.zeros((0, 2), dtype=np.int64)     # pairs may still form during the run
+        if pairs is not None and (len(pairs) or capture):
             self.ps = PairSet(L, snap.x, snap.v, snap.m, pairs, table, ctx)
             self.n = self.ps.n - self.ps.np
             self.sys = System.from_arrays(self.ps.xr, self.ps.vr, self.ps.mr, device=device,
@@ -181,7 +187,8 @@ class Server:
                  eta: float | None = None, eta_s: float = 0.01, dt_max: float = 2.0 ** -3,
                  dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
                  order: int = 4, lanes: int = 0, groups: bool = False, per_period: int = 32,
-                 max_sub: int = 1 << 20, group_gamma: float = 1e-3, split_gamma: float = 1e-2):
+                 max_sub: int = 1 << 20, group_gamma: float = 1e-3, split_gamma: float = 1e-2,
+                 capture_every: int = 0, capture_dt: float | None = None):
         if precision not in PRECISIONS:
             raise ValueError(precision)
         if order not in (4, 6):
@@ -197,7 +204,19 @@ class Server:
         # small: below group_gamma at admission (wider or more perturbed pairs
         # stay two bodies), and it returns to the N-body system as two bodies when
         # gamma exceeds split_gamma at one of its steps (an approaching perturber)
+        # -- capture_every > 0: every that many iterations, two single bodies of a
+        # grouped system that were in its block together, are each other's nearest
+        # neighbours (nb_nearest_active_batch; only bodies whose step is at most
+        # capture_dt, default dt_max / 256, are searched), form a bound pair and have
+        # gamma below min(group_gamma, split_gamma / 10) in the field of the rest
+        # (nb_tidal_points) become a pair carried as one body (the tight systems
+        # that form during the run)
         self.groups = bool(groups)
+        self.capture_every = int(capture_every) if self.groups else 0
+        self.capture_dt = float(capture_dt) if capture_dt is not None else dt_max / 256.0
+        # a captured pair starts at least ten times below the return threshold, so
+        # that it does not return at its next step
+        self.capture_gamma = min(float(group_gamma), 0.1 * float(split_gamma))
         self.per_period, self.max_sub = int(per_period), int(max_sub)
         self.group_gamma, self.split_gamma = float(group_gamma), float(split_gamma)
         self.ptab = PairTable(_lib.load()) if self.groups else None
@@ -265,16 +284,17 @@ class Server:
             if req is None:
                 return
             slot = _Slot(req, self.device, self.precision, self._now(), self.order, self.L,
-                         self.groups, table=self.ptab, ctx=self.ctx)
-            if slot.ps is not None:
+                         self.groups, table=self.ptab, ctx=self.ctx,
+                         capture=self.capture_every > 0)
+            if slot.ps is not None and slot.ps.np:
                 self._pairs_startup(slot)
                 gamma = slot.ps.perturbation()
                 if np.any(gamma >= self.group_gamma):
                     slot.ps.release()
                     slot = _Slot(req, self.device, self.precision, slot.result.admitted,
                                  self.order, self.L, True, slot.ps.pairs[gamma < self.group_gamma],
-                                 slot.snap, self.ptab, self.ctx)
-                    if slot.ps is not None:
+                                 slot.snap, self.ptab, self.ctx, capture=self.capture_every > 0)
+                    if slot.ps is not None and slot.ps.np:
                         self._pairs_startup(slot)
             slot.item.lanes = self.lanes
             if self.energy:
@@ -354,10 +374,55 @@ class Server:
             sl, ps = sets[q]
             sel = out & (o == q)
             try:
-                self._split(sl, r[sel] - ps.base, Tn[sel], float(t_b[sel][0]), stepped[sl])
+                # pairs by their place in the set: an earlier return in this loop may
+                # have compacted the table and moved this set's rows
+                self._split(sl, local[due][sel], Tn[sel], float(t_b[sel][0]), stepped[sl])
             except (NbError, ValueError) as e:
                 failed[sl] = "pair return failed: %s" % e
         return failed
+
+    def _rows(self, sl, rows):
+        """The FP64 state rows (FIELDS64 order, one column per body) of bodies `rows`
+        of a slot's system, gathered on the device and copied to the host."""
+        idx = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=self.device)
+        with torch.cuda.stream(self.ctx.stream):
+            return sl.sys.buf64[:, idx].cpu().numpy()
+
+    def _rebuild(self, sl, src, new64):
+        """A new System for a slot after pairs returned or formed: body r takes every
+        row (state and predicted set, FP64 and FP32) of body src[r] of the slot's
+        system when src[r] >= 0, gathered on the device, and otherwise the FP64 rows
+        new64[:, -1 - src[r]] (FIELDS64 order, its predicted set equal to its state),
+        with FP32 copies rounded from them."""
+        n_new = src.size
+        sysn = System(n_new, self.device, fp32_copies=(self.precision != "fp64"))
+        old = src >= 0
+        with torch.cuda.stream(self.ctx.stream):
+            if np.any(old):
+                dst = torch.as_tensor(np.flatnonzero(old), device=self.device)
+                so = torch.as_tensor(src[old], device=self.device)
+                sysn.buf64[:, dst] = sl.sys.buf64[:, so]
+                if sysn.buf32 is not None:
+                    sysn.buf32[:, dst] = sl.sys.buf32[:, so]
+            if not np.all(old):
+                dn = torch.as_tensor(np.flatnonzero(~old), device=self.device)
+                vals = torch.as_tensor(np.ascontiguousarray(new64[:, -1 - src[~old]]),
+                                       device=self.device)
+                sysn.buf64[:, dn] = vals
+                if sysn.buf32 is not None:
+                    sysn.buf32[0:3, dn] = vals[18:21].float()
+                    sysn.buf32[3, dn] = vals[12].float()
+        return sysn
+
+    @staticmethod
+    def _new_rows(x, v, a, j, m, t, dt):
+        """FP64 rows (FIELDS64 order) of new bodies whose predicted set is their state."""
+        k = len(m)
+        out = np.empty((21, k))
+        out[0:3], out[3:6], out[6:9], out[9:12] = x.T, v.T, a.T, j.T
+        out[12], out[13], out[14] = m, t, dt
+        out[15:18], out[18:21] = x.T, v.T
+        return out
 
     def _split(self, sl, ks, Tk, t_prev, t_now):
         """Return pairs ks of a grouped system to the N-body system as two bodies at
@@ -383,45 +448,37 @@ class Server:
         if np.any(later):
             ps.advance(ctx, ks[later], t_now, Tnow[later], self.per_period, self.max_sub,
                        queue=False)
-        st = sl.sys.state_numpy()
+        cm = self._rows(sl, cm_rows)                     # the centres of mass' rows
         self._sync_items()
         sl.result.split_energy += ps.split_energy(ks, eps)
         sl.result.splits += ks.size
         # the centres of mass at t_now, the members from them and the pairs' orbits
-        at_now = st["t"][cm_rows] == t_now
-        xc = np.where(at_now[:, None], st["x"][cm_rows], st["xp"][cm_rows])
-        vc = np.where(at_now[:, None], st["v"][cm_rows], st["vp"][cm_rows])
+        at_now = cm[13] == t_now
+        xc = np.where(at_now[:, None], cm[0:3].T, cm[15:18].T)
+        vc = np.where(at_now[:, None], cm[3:6].T, cm[18:21].T)
         members = ps.pairs[ks].ravel()
         xm, vm = ps.members_of(ks, xc, vc)
-        cap_cm = float(st["dt"][cm_rows].min())
+        cap_cm = float(cm[14].min())
         new_ps = ps.without(ks, ctx)
         # the new reduced system: bodies in no pair in index order, then the
         # remaining pairs' centres of mass (the layout nb_pairs_reduce makes)
-        old_row = {int(i): r for r, i in enumerate(ps.singles)}
-        mem_row = {int(i): q for q, i in enumerate(members)}
         keep_pairs = np.setdiff1d(np.arange(ps.np), ks)
         n_new = new_ps.cm0 + new_ps.np
         src = np.empty(n_new, dtype=np.int64)          # old row, or -1 - member slot
-        for r, i in enumerate(new_ps.singles):
-            src[r] = old_row[int(i)] if int(i) in old_row else -1 - mem_row[int(i)]
+        # both lists of single bodies are sorted: rows by binary search
+        ns = new_ps.singles
+        at = np.minimum(np.searchsorted(ps.singles, ns), max(ps.singles.size - 1, 0))
+        was = ps.singles.size > 0
+        is_old = (ps.singles[at] == ns) if was else np.zeros(ns.size, dtype=bool)
+        src[: ns.size][is_old] = at[is_old]
+        order = np.argsort(members)
+        src[: ns.size][~is_old] = -1 - order[np.searchsorted(members[order], ns[~is_old])]
         src[new_ps.cm0:] = ps.cm0 + keep_pairs
+        km = members.size
+        new64 = self._new_rows(xm, vm, np.zeros((km, 3)), np.zeros((km, 3)), ps.m[members],
+                               np.full(km, t_now), np.full(km, cap_cm))
+        sysn = self._rebuild(sl, src, new64)
         old = src >= 0
-        x, v = np.empty((n_new, 3)), np.empty((n_new, 3))
-        a, j = np.zeros((n_new, 3)), np.zeros((n_new, 3))
-        m, t, dt = np.empty(n_new), np.empty(n_new), np.empty(n_new)
-        for f, arr in (("x", x), ("v", v), ("a", a), ("j", j), ("m", m), ("t", t), ("dt", dt)):
-            arr[old] = st[f][src[old]]
-        mq = -1 - src[~old]
-        x[~old], v[~old] = xm[mq], vm[mq]
-        m[~old] = ps.m[members[mq]]
-        t[~old], dt[~old] = t_now, cap_cm
-        sysn = System.from_arrays(x, v, m, device=self.device,
-                                  fp32_copies=(self.precision != "fp64"))
-        rows = sysn.buf64[:, :n_new]
-        rows[6:9] = torch.from_numpy(np.ascontiguousarray(a.T)).to(self.device)
-        rows[9:12] = torch.from_numpy(np.ascontiguousarray(j.T)).to(self.device)
-        rows[13] = torch.from_numpy(t).to(self.device)
-        rows[14] = torch.from_numpy(dt).to(self.device)
         # the members' acceleration, jerk and step at t_now
         new_rows = np.flatnonzero(~old).astype(np.int32)
         idx = torch.as_tensor(new_rows, device=self.device)
@@ -437,6 +494,174 @@ class Server:
                                                 acc.data_ptr(), jerk.data_ptr(), float(t_now),
                                                 self.eta_s, cap, self.dt_min))
         ctx.sync()
+        sl.sys, sl.n, sl.ps = sysn, n_new, new_ps
+        self._returned.add(sl)
+        sl._work_buffers()
+        sl.cm_idx = torch.arange(new_ps.cm0, n_new, dtype=torch.int32, device=self.device)
+        self._arr = None
+        self._tid_stale = True
+
+    # a candidate pair refused at a capture pass of its system is not examined again
+    # for this many passes of that system (its perturbation changes slowly)
+    CAPTURE_RETRY = 16
+
+    def _capture(self, blocks, stepped):
+        """Pairs that formed in this iteration's blocks (`blocks`: slot -> active-block
+        size; `stepped`: slot -> block time).  The GPU finds the nearest neighbour of
+        every single body of the block whose step is at most capture_dt; two bodies
+        that are each other's nearest neighbour, bound to each other and perturbed by
+        the rest below capture_gamma become a pair carried as one body.  Returns
+        {slot: message} of systems whose capture failed."""
+        from ._lib import NbNearestItem
+        cand = [(sl, m) for sl, m in blocks.items()
+                if sl.ps is not None and m > 0 and sl not in self._returned and sl.n >= 2]
+        if not cand:
+            return {}
+        tot = sum(m for _, m in cand)
+        nn = torch.empty(tot, dtype=torch.int32, device=self.device)
+        r2 = torch.empty(tot, dtype=torch.float64, device=self.device)
+        rows = torch.empty(tot, dtype=torch.int32, device=self.device)
+        items = (NbNearestItem * len(cand))()
+        off = 0
+        with torch.cuda.stream(self.ctx.stream):
+            for q, (sl, m) in enumerate(cand):
+                it = items[q]
+                it.sys = sl.sys._struct
+                it.i_idx = sl.i_idx.data_ptr()
+                it.m = m
+                it.row_end = sl.ps.cm0
+                it.dt_cap = self.capture_dt
+                it.nn = nn.data_ptr() + 4 * off
+                it.r2 = r2.data_ptr() + 8 * off
+                it.status = sl.status.data_ptr()
+                rows[off: off + m].copy_(sl.i_idx[:m])
+                off += m
+            self._check(self.L.nb_nearest_active_batch(self.ctx.h, items, len(cand)))
+            nn_h = nn.cpu().numpy().astype(np.int64)
+            rows_h = rows.cpu().numpy().astype(np.int64)
+        failed = {}
+        off = 0
+        for sl, m in cand:
+            r_, n_ = rows_h[off: off + m], nn_h[off: off + m]
+            off += m
+            sl.capture_pass = getattr(sl, "capture_pass", 0) + 1
+            ok = n_ >= 0
+            if not np.any(ok):
+                continue
+            nbr = np.full(sl.n, -1, dtype=np.int64)
+            nbr[r_[ok]] = n_[ok]
+            mutual = ok & (nbr[np.maximum(n_, 0)] == r_) & (r_ < n_)
+            if not np.any(mutual):
+                continue
+            p, q = r_[mutual], n_[mutual]
+            # candidates refused in the last CAPTURE_RETRY passes wait
+            refused = getattr(sl, "refused", None)
+            if refused is None:
+                refused = sl.refused = {}
+            keys = list(zip(sl.ps.singles[p].tolist(), sl.ps.singles[q].tolist()))
+            fresh = np.array([sl.capture_pass - refused.get(key, -self.CAPTURE_RETRY)
+                              >= self.CAPTURE_RETRY for key in keys])
+            if not np.any(fresh):
+                continue
+            try:
+                self._merge(sl, p[fresh], q[fresh], stepped[sl])
+            except (NbError, ValueError) as e:
+                failed[sl] = "pair capture failed: %s" % e
+        return failed
+
+    def _merge(self, sl, p, q, t_b):
+        """Carry the bound, weakly perturbed ones of the candidate pairs (rows p[k],
+        q[k] of the reduced system, both single bodies corrected at the block time
+        t_b) as one body each from now on.  The new centre of mass takes the
+        members' mass-weighted position, velocity, acceleration and jerk at t_b (the
+        pair's internal forces cancel in these sums) and the smaller of their
+        steps; the pair's relative orbit starts at t_b with the tidal tensor of the
+        rest of the system at the centre of mass.  The rest keeps its state.
+        Candidates that are refused are remembered for CAPTURE_RETRY passes."""
+        ps, ctx = sl.ps, self.ctx
+        eps = float(sl.req.eps)
+        both = np.stack([p, q], axis=1).ravel()
+        st = self._rows(sl, both)                     # the candidates' rows only
+        t2 = st[13].reshape(-1, 2)
+        sync = (t2[:, 0] == t_b) & (t2[:, 1] == t_b)
+        _ptr = lambda z: z.ctypes.data_as(C.c_void_p)
+
+        def refuse(mask):
+            for key in zip(ps.singles[p[mask]].tolist(), ps.singles[q[mask]].tolist()):
+                sl.refused[key] = sl.capture_pass
+
+        def reduce(x, v, sel):
+            cols = np.stack([2 * sel, 2 * sel + 1], axis=1).ravel()
+            k = sel.size
+            xr, vr = np.empty((k, 3)), np.empty((k, 3))
+            mr, M = np.empty(k), np.empty(k)
+            r, w = np.empty((k, 3)), np.empty((k, 3))
+            local = np.arange(2 * k, dtype=np.int64).reshape(k, 2)
+            args = [np.ascontiguousarray(z) for z in (x[:, cols].T, v[:, cols].T, st[12][cols])]
+            rc = self.L.nb_pairs_reduce(2 * k, *[_ptr(z) for z in args], k, _ptr(local),
+                                        *[_ptr(z) for z in (xr, vr, mr, M, r, w)])
+            if rc != 0:
+                raise ValueError("bad candidate pairs")
+            return xr, vr, M, r, w
+
+        sel = np.flatnonzero(sync)
+        if sel.size == 0:
+            return
+        xc, vc, M, r, w = reduce(st[0:3], st[3:6], sel)
+        k = sel.size
+        a, g = np.empty(k), np.empty(k)
+        self._check(self.L.nb_pairs_perturbation(k, _ptr(M), _ptr(r), _ptr(w), None, _ptr(a),
+                                                 _ptr(g)))
+        bound = np.isfinite(a) & (a > 0.0)
+        refuse(np.isin(np.arange(p.size), sel[~bound]))
+        if not np.any(bound):
+            return
+        sel, xc, vc, M, r, w, a = (z[bound] for z in (sel, xc, vc, M, r, w, a))
+        kb = sel.size
+        pts = torch.as_tensor(np.ascontiguousarray(xc.T).ravel(), device=self.device)
+        exc = torch.as_tensor(np.ascontiguousarray(np.stack([p[sel], q[sel]])).ravel()
+                              .astype(np.int32), device=self.device)
+        T = torch.empty(9 * kb, dtype=torch.float64, device=self.device)
+        self._check(self.L.nb_tidal_points(ctx.h, sl.sys.ref, kb, pts.data_ptr(), exc.data_ptr(),
+                                           eps, T.data_ptr()))
+        ctx.sync()
+        Tk = np.ascontiguousarray(T.cpu().numpy().reshape(9, kb).T)
+        ab, gb = np.ascontiguousarray(a), np.empty(kb)
+        Mb = np.ascontiguousarray(M)
+        self._check(self.L.nb_pairs_perturbation(kb, _ptr(Mb), None, None, _ptr(Tk), _ptr(ab),
+                                                 _ptr(gb)))
+        take = gb < self.capture_gamma
+        refuse(np.isin(np.arange(p.size), sel[~take]))
+        if not np.any(take):
+            return
+        sel, xc, vc, M, r, w, Tk, ab = (z[take] for z in (sel, xc, vc, M, r, w, Tk, ab))
+        kt = sel.size
+        # the centres of mass' acceleration and jerk: mass-weighted sums, as the
+        # positions and velocities (the same reduction applied to a and j)
+        ac, jc, _, _, _ = reduce(st[6:9], st[9:12], sel)
+        dts = st[14].reshape(-1, 2)[sel].min(axis=1)
+        ps.drain(ctx)
+        self._sync_items()
+        new_pairs = np.stack([ps.singles[p[sel]], ps.singles[q[sel]]], axis=1)
+        out = C.c_double()
+        rk = np.ascontiguousarray(r)
+        npairs = np.ascontiguousarray(new_pairs)
+        self._check(self.L.nb_pairs_split_energy(kt, _ptr(ps.m), _ptr(npairs), _ptr(rk), eps,
+                                                 C.byref(out)))
+        new_ps = ps.with_pairs(new_pairs, M, r, w, Tk, ab, t_b, ctx)
+        # the new reduced system: bodies in no pair in index order, then the old
+        # pairs' centres of mass, then the new ones (the layout nb_pairs_reduce makes)
+        n_new = new_ps.cm0 + new_ps.np
+        src = np.empty(n_new, dtype=np.int64)            # old row, or -1 - new pair
+        # the new singles are old ones; both lists are sorted
+        src[: new_ps.cm0] = np.searchsorted(ps.singles, new_ps.singles)
+        src[new_ps.cm0: new_ps.cm0 + ps.np] = ps.cm0 + np.arange(ps.np)
+        src[new_ps.cm0 + ps.np:] = -1 - np.arange(kt)
+        new64 = self._new_rows(xc, vc, ac, jc, M, np.full(kt, t_b), dts)
+        sysn = self._rebuild(sl, src, new64)
+        ctx.sync()
+        sl.result.capture_energy -= out.value
+        sl.result.captures += kt
         sl.sys, sl.n, sl.ps = sysn, n_new, new_ps
         self._returned.add(sl)
         sl._work_buffers()
@@ -527,7 +752,8 @@ class Server:
                 if self.keep_state:
                     r.final = dict(st, members_x=x, members_v=v,
                                    pair_r=slot.ps.r[: slot.ps.np].copy(),
-                                   pair_w=slot.ps.w[: slot.ps.np].copy())
+                                   pair_w=slot.ps.w[: slot.ps.np].copy(),
+                                   pairs=slot.ps.pairs.copy())
             elif self.keep_state:
                 r.final = slot.sys.state_numpy()
         if slot.ps is not None:
@@ -613,6 +839,13 @@ class Server:
                 if self.slots[k].ps is not None:
                     stepped[self.slots[k]] = float(t_next[k])
             failed = self._queue_pairs(stepped) or {}
+            if self.capture_every:
+                # on every capture_every-th block step of each system (its own count,
+                # so that a system's run does not depend on what else is resident)
+                blocks = {sl: int(m_blk[k]) for k, sl in enumerate(at_step)
+                          if sl in stepped and sl not in failed
+                          and self._steps[k] % self.capture_every == 0}
+                failed.update(self._capture(blocks, stepped))
             for sl, tb in stepped.items():
                 if sl.ps is not None and sl.ps.np:
                     self.ptab.prev_t[sl.ps.base: sl.ps.base + sl.ps.np] = tb
@@ -665,6 +898,10 @@ def summarize(results, wall: float) -> dict:
            "wall_s": wall, "solves_per_s": len(ok) / wall if wall > 0 else float("nan"),
            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
            "interactions": int(inter), "interactions_per_s": inter / wall if wall > 0 else float("nan")}
+    if any(r.pairs or r.splits or r.captures for r in ok):
+        out["pairs_at_admission"] = int(sum(r.pairs for r in ok))
+        out["pair_returns"] = int(sum(r.splits for r in ok))
+        out["pair_captures"] = int(sum(r.captures for r in ok))
     with_e = [r for r in ok if not math.isnan(r.energy1)]
     if with_e:
         errs = [r.energy_error for r in with_e]

@@ -95,20 +95,22 @@ def test_force_plan_lane_target():
 
 
 def test_struct_layouts_match_the_header(tmp_path):
-    """ctypes mirrors of nb_system / nb_batch_item / nb_hermite6 / nb_tidal_item have the
-    C sizes and offsets."""
+    """ctypes mirrors of nb_system / nb_batch_item / nb_hermite6 / nb_tidal_item /
+    nb_nearest_item have the C sizes and offsets."""
     import ctypes
     import subprocess
     from paper_1411_5234_amd import _lib
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "nbody.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
         'sizeof(nb_system), '
         'sizeof(nb_batch_item), offsetof(nb_batch_item, status), offsetof(nb_batch_item, eps), '
         'offsetof(nb_batch_item, m), offsetof(nb_batch_item, done), sizeof(nb_hermite6), '
         'offsetof(nb_hermite6, axp32), sizeof(nb_tidal_item), offsetof(nb_tidal_item, m), '
-        'offsetof(nb_tidal_item, eps), offsetof(nb_tidal_item, status)); return 0; }\n')
+        'offsetof(nb_tidal_item, eps), offsetof(nb_tidal_item, status), '
+        'sizeof(nb_nearest_item), offsetof(nb_nearest_item, row_end), '
+        'offsetof(nb_nearest_item, dt_cap), offsetof(nb_nearest_item, status)); return 0; }\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
@@ -117,5 +119,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     Ti = _lib.NbTidalItem
     want = [ctypes.sizeof(_lib.NbSystem), ctypes.sizeof(B), B.status.offset, B.eps.offset,
             B.m.offset, B.done.offset, ctypes.sizeof(H), H.axp32.offset, ctypes.sizeof(Ti),
-            Ti.m.offset, Ti.eps.offset, Ti.status.offset]
+            Ti.m.offset, Ti.eps.offset, Ti.status.offset, ctypes.sizeof(_lib.NbNearestItem),
+            _lib.NbNearestItem.row_end.offset, _lib.NbNearestItem.dt_cap.offset,
+            _lib.NbNearestItem.status.offset]
     assert got == want

@@ -45,6 +45,105 @@ def test_tidal_matches_oracle(ctx, orc, eps):
         assert err.max() <= 1e-12
 
 
+def test_tidal_at_points_matches_oracle(ctx, orc):
+    """The field of the rest of the system at arbitrary points, two bodies left out
+    per point (the centre of mass of a pair about to be formed)."""
+    s = inputs.plummer(2500, 91, masses=inputs.salpeter_masses(2500, 92))
+    sys = device_system(s.x, s.v, s.m)
+    rng = np.random.default_rng(93)
+    k = 37
+    a = rng.choice(2500, k, replace=False)
+    b = rng.choice(2500, k, replace=False)
+    pts = 0.5 * (s.x[a] + s.x[b])
+    pts[0] = s.x[a[0]]                       # a point on a body that is left out
+    excl = np.stack([a, b], axis=1)
+    excl[1] = -1                             # nothing left out
+    excl[2, 1] = -1
+    P = torch.as_tensor(np.ascontiguousarray(pts.T).ravel(), device="cuda")
+    E = torch.as_tensor(np.ascontiguousarray(excl.T).ravel().astype(np.int32), device="cuda")
+    for eps in (1e-3, 0.0):
+        if eps == 0.0:
+            pts_e, excl_e = pts[1:], excl[1:]
+            P = torch.as_tensor(np.ascontiguousarray(pts_e.T).ravel(), device="cuda")
+            E = torch.as_tensor(np.ascontiguousarray(excl_e.T).ravel().astype(np.int32),
+                                device="cuda")
+        else:
+            pts_e, excl_e = pts, excl
+        kk = len(pts_e)
+        T = torch.full((9 * kk,), np.nan, dtype=torch.float64, device="cuda")
+        ctx._check(ctx.L.nb_tidal_points(ctx.h, sys.ref, kk, P.data_ptr(), E.data_ptr(), eps,
+                                         T.data_ptr()))
+        ctx.sync()
+        g = T.view(9, kk).T.cpu().numpy().reshape(kk, 3, 3)
+        o = orc.tidal_points(s.x, s.m, eps, pts_e, excl_e)
+        err = np.abs(g - o).max(axis=(1, 2)) / np.abs(o).max(axis=(1, 2))
+        print("tidal at points eps=%g: max rel %.3e" % (eps, err.max()), flush=True)
+        assert err.max() <= 1e-12
+
+
+def _gpu_nearest(ctx, systems):
+    """nb_nearest_active_batch over several (sys, rows, row_end, dt_cap) items."""
+    from paper_1411_5234_amd._lib import NbNearestItem
+    items = (NbNearestItem * len(systems))()
+    keep = []
+    for q, (sys, rows, row_end, cap) in enumerate(systems):
+        m = len(rows)
+        idx = torch.as_tensor(np.asarray(rows, dtype=np.int32), device="cuda")
+        nn = torch.full((max(m, 1),), -7, dtype=torch.int32, device="cuda")
+        r2 = torch.full((max(m, 1),), np.nan, dtype=torch.float64, device="cuda")
+        keep.append((idx, nn, r2, m))
+        it = items[q]
+        it.sys = sys._struct
+        it.i_idx = idx.data_ptr()
+        it.m = m
+        it.row_end = row_end
+        it.dt_cap = cap
+        it.nn = nn.data_ptr()
+        it.r2 = r2.data_ptr()
+        it.status = None
+    ctx._check(ctx.L.nb_nearest_active_batch(ctx.h, items, len(systems)))
+    ctx.sync()
+    return [(nn[:m].cpu().numpy().astype(np.int64), r2[:m].cpu().numpy()) for _, nn, r2, m in keep]
+
+
+def test_nearest_matches_oracle_exactly(ctx, orc):
+    """Nearest-neighbour indices and squared distances, bit for bit: ragged systems
+    in one launch (one body; a few tiles with a ragged tail; C5-sized), coincident
+    bodies and equal distances planted, rows filtered by index and by step."""
+    rng = np.random.default_rng(101)
+    cases = []
+    for n, seed in ((1, 1), (2, 2), (700, 3), (5003, 4), (65536, 5)):
+        s = inputs.plummer(n, 100 + seed)
+        x = s.x.copy()
+        if n >= 700:
+            x[5] = x[17]                                     # coincident
+            x[30] = [0.5, 0.25, 0.125]                       # exactly equal distances
+            x[40] = [0.5, 0.25 + 2.0 ** -10, 0.125]          # from 30 (exact differences)
+            x[50] = [0.5, 0.25 - 2.0 ** -10, 0.125]
+        sys = device_system(x, s.v, s.m)
+        dt = rng.choice([2.0 ** -14, 2.0 ** -8, 2.0 ** -3], n)
+        sys.buf64[14, :n] = torch.as_tensor(dt, device="cuda")
+        m = min(n, 512)
+        rows = np.sort(rng.choice(n, m, replace=False)) if n > m else np.arange(n)
+        if n >= 700:
+            rows = np.unique(np.concatenate([rows, [5, 17, 30, 40, 50]]))
+        row_end = n if seed % 2 else max(n - 100, 0)
+        cap = np.inf if seed % 2 else 2.0 ** -8
+        cases.append((sys, rows, row_end, cap, x, dt))
+    got = _gpu_nearest(ctx, [(c[0], c[1], c[2], c[3]) for c in cases])
+    for (sys, rows, row_end, cap, x, dt), (nn, r2) in zip(cases, got):
+        onn, or2 = orc.nearest(x, rows, row_end, dt, cap)
+        print("nearest n=%d rows=%d searched=%d" % (len(x), len(rows), int((onn >= 0).sum())),
+              flush=True)
+        assert np.array_equal(nn, onn)
+        assert np.array_equal(r2, or2)
+    # the planted cases (n = 700: every row searched)
+    rows, (nn, r2) = cases[2][1], got[2]
+    at = {int(r): q for q, r in enumerate(rows)}
+    assert nn[at[5]] == 17 and nn[at[17]] == 5 and r2[at[5]] == 0.0
+    assert nn[at[30]] == 40                                  # the lower of two equal distances
+
+
 def _cluster(a_hi=1e-3):
     s = inputs.with_binaries(160, 10, frac_members=0.2, a_lo=1e-4, a_hi=a_hi, imf="equal")
     return s, [(2 * k, 2 * k + 1) for k in range(16)]

@@ -321,7 +321,95 @@ def test_pairs_return_to_the_n_body_system(ctx):
         assert alone.final[f].tobytes() == b.final[f].tobytes(), f
     assert (alone.steps, alone.splits) == (b.steps, b.splits)
     assert alone.energy_error < 1e-4
+    # with captures too: returns and captures in several systems of one iteration
+    # move segments of the shared pair table under each other
+    kc = dict(kw, capture_every=1)
+    solo = Server(ctx, **kc).run([target], realtime=False)[0]
+    outc = {r.rid: r for r in Server(ctx, max_slots=3, **kc).run(mix, realtime=False)}
+    assert solo.error is None and all(r.error is None for r in outc.values()), \
+        {k: r.error for k, r in outc.items()}
+    print("with captures: %d returned, %d captured; conserved quantity error %.3e" % (
+        solo.splits, solo.captures, solo.energy_error), flush=True)
+    for f in keys + ("pairs",):
+        assert solo.final[f].tobytes() == outc[0].final[f].tobytes(), f
+    assert solo.energy_error < 1e-4
     # admission keeps only pairs below the grouping threshold
     few = Server(ctx, precision="fp64", groups=True, group_gamma=1e-5).run([target],
                                                                             realtime=False)[0]
     assert few.error is None and few.pairs < alone.pairs
+
+
+def _forming_ic(n=600, seed=7301):
+    """A cluster with hard binaries that no one has declared as pairs, plus two
+    single bodies on a fast (unbound) close flyby of each other."""
+    from dataclasses import dataclass
+    b = inputs.with_binaries(n, seed, frac_members=0.02, a_lo=1e-4, a_hi=3e-4, imf="equal")
+    x, v, m = b.x.copy(), b.v.copy(), b.m.copy()
+    planted = [tuple(int(i) for i in q) for q in b.meta["pairs"]]
+    i, j = n - 1, n - 2                        # singles of the sample
+    x[j] = x[i] + [2e-4, 0.0, 0.0]
+    w = 3.0 * math.sqrt((m[i] + m[j]) / 2e-4)  # well above the escape speed
+    v[j] = v[i] + [0.0, w, 0.0]
+    snap = inputs.Snapshot(x, v, m, {"kind": "binaries, undeclared"})
+
+    @dataclass
+    class _Req(inputs.Request):
+        def snapshot(self):
+            return snap
+    return snap, planted, (j, i), _Req
+
+
+def test_pairs_form_during_the_run(ctx, orc):
+    """Bound pairs that nobody declared are found during the run and carried as one
+    body: each captured pair is one of the planted binaries (mutual nearest
+    neighbours, bound, weakly perturbed), never the unbound flyby; the tidal
+    tensor a new pair starts with matches the oracle's at its centre of mass; the
+    result is bitwise the same alone and in a mix; and the conserved quantity,
+    with the known change at each capture, stays conserved."""
+    import time
+    from paper_1411_5234_amd.serve import Server
+    snap, planted, flyby, Req = _forming_ic()
+    eps = 1e-5
+    target = Req(0, 0.0, snap.n, 0, eps, 0.125, "custom")
+    kw = dict(precision="fp64", keep_state=True, groups=True, capture_every=1)
+    # step by step up to the first capture: the new pairs' starting tensors
+    srv = Server(ctx, **kw)
+    srv.t0 = time.perf_counter()
+    srv.submit(target)
+    srv._admit()
+    slot = srv.slots[0]
+    for _ in range(2000):
+        srv.step()
+        if slot.result.captures:
+            break
+    k = slot.result.captures
+    assert k > 0
+    ps = slot.ps
+    st = slot.sys.state_numpy()
+    rows = np.arange(ps.cm0 + ps.np - k, ps.cm0 + ps.np)
+    T_or = orc.tidal(st["xp"], st["m"], eps, rows)
+    T_gpu = ps.T[ps.np - k:].reshape(k, 3, 3)
+    err = np.abs(T_gpu - T_or).max() / np.abs(T_or).max()
+    print("first capture: %d pairs at t = %.6g; tensor vs oracle %.3e" % (
+        k, ps.tpair[ps.np - 1], err), flush=True)
+    assert err <= 1e-12
+    assert np.all(st["t"][rows] == ps.tpair[ps.np - k:])
+    # whole runs, alone and in a mix
+    alone = Server(ctx, **kw).run([target], realtime=False)[0]
+    assert alone.error is None, alone.error
+    got = {tuple(sorted(int(i) for i in q)) for q in alone.final["pairs"]}
+    print("captured %d, returned %d, held at the end %s of planted %s; energy error %.3e "
+          "(capture offset %.3e), direct %.3e" % (
+              alone.captures, alone.splits, sorted(got), sorted(planted), alone.energy_error,
+              alone.capture_energy, abs(alone.direct1 - alone.direct0) / abs(alone.direct0)),
+          flush=True)
+    assert alone.captures >= 1 and got and got <= set(planted)
+    assert tuple(sorted(flyby)) not in got
+    assert alone.energy_error < 1e-4
+    mix = [_req(1, 300, 12, t_end=0.125), target, _req(2, 800, 13, t_end=0.125)]
+    out = {r.rid: r for r in Server(ctx, max_slots=2, **kw).run(mix, realtime=False)}
+    assert all(r.error is None for r in out.values()), {k: r.error for k, r in out.items()}
+    b = out[0]
+    for f in FIELDS + ("pair_r", "pair_w", "members_x", "members_v", "pairs"):
+        assert alone.final[f].tobytes() == b.final[f].tobytes(), f
+    assert (alone.steps, alone.captures, alone.splits) == (b.steps, b.captures, b.splits)

@@ -272,3 +272,37 @@ def test_members_of_some_pairs_match_the_full_reconstruction(L):
     xm, vm = ps.members_of(ks, ps.xr[ps.cm0 + ks], ps.vr[ps.cm0 + ks])
     rows = ps.pairs[ks].ravel()
     assert np.array_equal(xm, x[rows]) and np.array_equal(vm, v[rows])
+
+
+def test_pairs_added_during_a_run_keep_the_layout_and_the_old_pairs(L):
+    """PairSet.with_pairs: the old pairs keep their rows' orbits, tensors and times;
+    the new ones follow them; the reduced layout (bodies in no pair in index order,
+    then the centres of mass in pair order) is the one a fresh PairSet of all the
+    pairs makes from the same state."""
+    from paper_1411_5234_amd import inputs
+    from paper_1411_5234_amd.groups import PairSet, PairTable
+    s = inputs.with_binaries(300, 12)
+    pairs = s.meta["pairs"]
+    tab = PairTable(L, 4)
+    old = PairSet(L, s.x, s.v, s.m, pairs[:5], tab)
+    old.T[:] = np.arange(45.0).reshape(5, 9)
+    old.tpair[:] = 0.25
+    other = PairSet(L, s.x, s.v, s.m, pairs[9:11], tab)       # another system in the table
+    other.T[:] = 7.0
+    full = PairSet(L, s.x, s.v, s.m, pairs[:8])
+    new = old.with_pairs(pairs[5:8], full.M[5:8], full.r[5:8], full.w[5:8],
+                         np.ones((3, 9)), full.a0[5:8], 0.5)
+    assert new.np == 8 and new.cm0 == full.cm0
+    assert np.array_equal(new.pairs, full.pairs) and np.array_equal(new.singles, full.singles)
+    for f in ("M", "r", "w", "a0"):
+        assert np.array_equal(getattr(new, f), getattr(full, f)), f
+    assert np.array_equal(new.T[:5], np.arange(45.0).reshape(5, 9))
+    assert np.all(new.T[5:] == 1.0) and np.all(new.tpair[:5] == 0.25) and np.all(new.tpair[5:] == 0.5)
+    assert np.all(other.T == 7.0)                               # untouched by the move
+    assert old not in tab.sets and new in tab.sets
+    with pytest.raises(ValueError):
+        new.with_pairs([[pairs[0][0], pairs[9][0]]], [1.0], np.ones((1, 3)), np.ones((1, 3)),
+                       np.zeros((1, 9)), [1.0], 0.5)
+    assert new in tab.sets                                      # a refused call changes nothing
+    empty = PairSet(L, s.x, s.v, s.m, np.zeros((0, 2), dtype=np.int64))
+    assert empty.np == 0 and empty.cm0 == 300 and np.array_equal(empty.xr, s.x)

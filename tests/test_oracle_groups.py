@@ -129,8 +129,9 @@ def test_nearest_is_the_brute_force_scan(orc):
     n = 60
     x = rng.normal(size=(n, 3))
     x[7] = x[3]                           # coincident bodies: distance 0
-    x[20] = x[10] + [0.0, 0.0, 1e-3]      # two bodies at equal distance from 10
-    x[30] = x[10] - [0.0, 0.0, 1e-3]
+    x[10] = [0.5, 0.25, 0.125]            # two bodies at exactly equal distance from 10
+    x[20] = [0.5, 0.25, 0.125 + 2.0 ** -10]
+    x[30] = [0.5, 0.25, 0.125 - 2.0 ** -10]
     x[41] = x[40] * (1.0 + 1e-15)         # a near tie far from the origin
     dt = rng.choice([2.0 ** -12, 2.0 ** -6], n)
     for rows, row_end, dtv, cap in ((np.arange(n), n, None, math.inf),
