@@ -103,6 +103,9 @@ def parse():
                          "16 was the fastest of 4, 16 and off)")
     ap.add_argument("--precisions", default="mixed,fp64",
                     help="serve mode, C5 stream: the precisions each request is served in")
+    ap.add_argument("--pipes", type=int, default=1, choices=[1, 2],
+                    help="serving: split the resident systems between this many contexts "
+                         "(streams), stepped one after the other")
     ap.add_argument("--closed-only", action="store_true",
                     help="serve mode: the closed batch alone (no Poisson replay, baselines "
                          "or reruns), e.g. for a kernel trace")
@@ -351,10 +354,12 @@ def mode_step(args):
         # the serving half of the metric: a bounded sample of the C4 stream
         print("serving: first %d requests of the C4 stream" % args.serving_requests,
               file=sys.stderr, flush=True)
-        sv = serving_runs(ctx, "c4", args.serving_requests, baseline=args.baseline_requests)
+        sv = serving_runs(ctx, "c4", args.serving_requests, baseline=args.baseline_requests,
+                          pipes=args.pipes)
         out["serving"] = {"workload": "c4: equal-mass Plummer, N log-uniform in [256, 32768], "
                                       "eps = 1e-3, to t = 1, first %d requests" % args.serving_requests,
-                          "precision": "mixed", "lanes": default_lanes("c4", 4), **sv}
+                          "precision": "mixed", "lanes": default_lanes("c4", 4),
+                          "pipes": args.pipes, **sv}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -547,7 +552,7 @@ def _progress():
 
 
 def serving_runs(ctx, stream, requests, precision="mixed", order=4, slots=256, lanes=None,
-                 baseline=32, closed_only=False):
+                 baseline=32, closed_only=False, pipes=1):
     """The first `requests` requests of a serving stream, served four ways:
     - closed batch: all arrive at t = 0 (saturated throughput);
     - Poisson replay in real time at 0.8 x the closed-batch rate;
@@ -558,7 +563,8 @@ def serving_runs(ctx, stream, requests, precision="mixed", order=4, slots=256, l
     lanes = default_lanes(stream, order) if lanes is None else lanes
     progress = _progress()
     out = {}
-    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes)
+    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes,
+                 pipes=pipes)
     t0 = time.perf_counter()
     res = srv.run(serve_stream(stream, 0.0, requests), realtime=False, on_iteration=progress)
     out["closed_batch"] = summarize(res, time.perf_counter() - t0)
@@ -566,7 +572,8 @@ def serving_runs(ctx, stream, requests, precision="mixed", order=4, slots=256, l
     if closed_only:
         return out
     rate = 0.8 * out["closed_batch"]["solves_per_s"]
-    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes)
+    srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order, lanes=lanes,
+                 pipes=pipes)
     t0 = time.perf_counter()
     res = srv.run(serve_stream(stream, rate, requests), realtime=True, on_iteration=progress)
     out["poisson"] = summarize(res, time.perf_counter() - t0)
@@ -582,7 +589,7 @@ def serving_runs(ctx, stream, requests, precision="mixed", order=4, slots=256, l
         out["one_at_a_time_fp64"]["requests_served"] = k
         print("one at a time fp64: %s" % out["one_at_a_time_fp64"], file=sys.stderr, flush=True)
         srv = Server(ctx, precision=precision, max_slots=slots, energy=True, order=order,
-                     lanes=lanes)
+                     lanes=lanes, pipes=pipes)
         t0 = time.perf_counter()
         res = srv.run(serve_stream(stream, 0.0, requests)[:k], realtime=False)
         out["batched_same_requests"] = summarize(res, time.perf_counter() - t0)
@@ -612,7 +619,8 @@ def mode_serve(args):
                       "precision": args.precision, "order": args.order, "lanes": args.lanes,
                       **{k: v for k, v in spec.items() if k != "base"}}}
     out.update(serving_runs(ctx, args.stream, args.requests, args.precision, args.order,
-                            args.slots, args.lanes, args.baseline_requests, args.closed_only))
+                            args.slots, args.lanes, args.baseline_requests, args.closed_only,
+                            pipes=args.pipes))
     closed = out["closed_batch"]
     if args.closed_only:
         ctx.close()

@@ -121,6 +121,24 @@ class _Slot:
         self.item.jerk = self.jerk.data_ptr()
 
 
+class _Pipe:
+    """A context (stream and scratch) and the resident systems stepped on it, with
+    their batch items: one contiguous array handed to every nb_step_batch call and
+    updated in place by it, rebuilt only when the set of resident systems changes
+    (`view` reads its host fields with numpy)."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        self.slots = []
+        self.arr = None
+        self.view = None
+        self.n = None
+        self.steps = None
+        self.inter = None
+        self.h6 = None
+        self.snaps = None
+
+
 def footprint_bytes(n: int, precision: str = "mixed", order: int = 4) -> int:
     """Device bytes one resident system of n bodies holds (state + work buffers;
     at 6th order also snap, crackle, predicted acceleration and the snap output)."""
@@ -188,7 +206,7 @@ class Server:
                  dt_min: float = 2.0 ** -40, keep_state: bool = False, energy: bool = True,
                  order: int = 4, lanes: int = 0, groups: bool = False, per_period: int = 32,
                  max_sub: int = 1 << 20, group_gamma: float = 1e-3, split_gamma: float = 1e-2,
-                 capture_every: int = 0, capture_dt: float | None = None):
+                 capture_every: int = 0, capture_dt: float | None = None, pipes: int = 1):
         if precision not in PRECISIONS:
             raise ValueError(precision)
         if order not in (4, 6):
@@ -248,14 +266,16 @@ class Server:
         self.results: list[Result] = []
         self.iterations = 0
         self.t0 = None
-        # the resident systems' batch items, one contiguous array handed to every
-        # nb_step_batch call and updated in place by it; rebuilt only when the set
-        # of resident systems changes.  _view reads its host fields with numpy.
-        self._arr = None
-        self._view = None
-        self._n = None
-        self._steps = None
-        self._inter = None
+        # pipes: the resident systems are split between this many contexts, each
+        # with its own stream and scratch; an iteration steps them one after the
+        # other, so that one pipe's kernels run while the host waits for the other's
+        # selection and builds its launches.  Grouped serving uses one pipe.
+        if pipes not in (1, 2) or (pipes == 2 and self.groups):
+            raise ValueError("pipes must be 1 or 2 (1 with groups)")
+        self._pipes = [_Pipe(self.ctx)]
+        if pipes == 2:
+            self._pipes.append(_Pipe(Context(self.ctx.device,
+                                             stream=torch.cuda.Stream(self.ctx.device))))
 
     # ---- admission -----------------------------------------------------------
     @property
@@ -297,14 +317,19 @@ class Server:
                     if slot.ps is not None and slot.ps.np:
                         self._pairs_startup(slot)
             slot.item.lanes = self.lanes
+            # the pipe with the least resident work (the system's state was written
+            # on torch's current stream: the pipe's stream waits for it)
+            slot.pipe = min(self._pipes, key=lambda p: sum(sl.n * sl.n for sl in p.slots))
+            slot.pipe.ctx.stream.wait_stream(torch.cuda.current_stream(self.device))
             if self.energy:
-                slot.result.energy0 = self.ctx.energy(slot.sys, req.eps)[2]
+                slot.result.energy0 = slot.pipe.ctx.energy(slot.sys, req.eps)[2]
                 if slot.ps is not None:
                     slot.result.energy0 += slot.ps.energy()
                     slot.result.direct0 = self._direct_energy(slot, slot.snap.x, slot.snap.v)
             self._sync_items()
             self.slots.append(slot)
-            self._arr = None
+            slot.pipe.slots.append(slot)
+            self._invalidate()
             self._tid_stale = True
 
     # ---- grouped pairs -----------------------------------------------------------
@@ -498,7 +523,7 @@ class Server:
         self._returned.add(sl)
         sl._work_buffers()
         sl.cm_idx = torch.arange(new_ps.cm0, n_new, dtype=torch.int32, device=self.device)
-        self._arr = None
+        self._invalidate()
         self._tid_stale = True
 
     # a candidate pair refused at a capture pass of its system is not examined again
@@ -666,7 +691,7 @@ class Server:
         self._returned.add(sl)
         sl._work_buffers()
         sl.cm_idx = torch.arange(new_ps.cm0, n_new, dtype=torch.int32, device=self.device)
-        self._arr = None
+        self._invalidate()
         self._tid_stale = True
 
     def _tidal_layout(self):
@@ -741,8 +766,9 @@ class Server:
                 error = error or "NB_EUNBOUND: %s" % e
         r.error = error
         if error is None:
+            slot.pipe.ctx.sync()
             if self.energy:
-                r.energy1 = self.ctx.energy(slot.sys, slot.req.eps)[2]
+                r.energy1 = slot.pipe.ctx.energy(slot.sys, slot.req.eps)[2]
             if slot.ps is not None:
                 st = slot.sys.state_numpy()
                 x, v = slot.ps.members(st["x"], st["v"])
@@ -762,89 +788,103 @@ class Server:
         self.results.append(r)
         self.adm.release(slot.req)
         self.slots.remove(slot)
-        self._arr = None
+        slot.pipe.slots.remove(slot)
+        self._invalidate()
         self._tid_stale = True
 
     # ---- one iteration: one block step of every resident system ---------------
-    def _check(self, rc):
+    def _check(self, rc, ctx=None):
         if rc != 0:
-            raise NbError(rc, self.L.nb_last_error(self.ctx.h).decode())
+            raise NbError(rc, self.L.nb_last_error((ctx or self.ctx).h).decode())
 
     _FIELDS = ("t_next", "m", "startup", "error", "done")
     _DTYPE = np.dtype({"names": list(_FIELDS), "formats": ["<f8", "<i4", "<i4", "<i4", "<i4"],
                        "offsets": [getattr(NbBatchItem, f).offset for f in _FIELDS],
                        "itemsize": C.sizeof(NbBatchItem)})
 
-    def _sync_items(self):
-        """Copy the item array's state (updated by the native calls) and the step
-        counters back into the slots, before the resident set changes."""
-        if self._arr is None:
-            return
-        for k, sl in enumerate(self.slots):
-            sl.item = NbBatchItem.from_buffer_copy(self._arr[k])
-            sl.result.steps = int(self._steps[k])
-            sl.result.interactions = int(self._inter[k])
+    def _invalidate(self):
+        """The resident set changed: every pipe rebuilds its item array before its
+        next step (after _sync_items has copied the arrays back)."""
+        for p in self._pipes:
+            p.arr = None
 
-    def _build_items(self):
-        k = len(self.slots)
-        self._arr = (NbBatchItem * k)(*[sl.item for sl in self.slots])
+    def _sync_items(self):
+        """Copy the item arrays' state (updated by the native calls) and the step
+        counters back into the slots, before the resident set changes."""
+        for p in self._pipes:
+            if p.arr is None:
+                continue
+            for k, sl in enumerate(p.slots):
+                sl.item = NbBatchItem.from_buffer_copy(p.arr[k])
+                sl.result.steps = int(p.steps[k])
+                sl.result.interactions = int(p.inter[k])
+
+    def _build_items(self, p):
+        k = len(p.slots)
+        p.arr = (NbBatchItem * k)(*[sl.item for sl in p.slots])
         if self.order == 6:
-            self._h6 = (NbHermite6 * k)(*[sl.h6._struct for sl in self.slots])
-            self._snaps = (C.c_void_p * k)(*[sl.snap6.data_ptr() for sl in self.slots])
-        raw = (C.c_char * C.sizeof(self._arr)).from_address(C.addressof(self._arr))
-        self._view = np.frombuffer(raw, dtype=self._DTYPE)
-        self._n = np.array([sl.n for sl in self.slots], dtype=np.int64)
-        self._steps = np.array([sl.result.steps for sl in self.slots], dtype=np.int64)
-        self._inter = np.array([sl.result.interactions for sl in self.slots], dtype=np.int64)
+            p.h6 = (NbHermite6 * k)(*[sl.h6._struct for sl in p.slots])
+            p.snaps = (C.c_void_p * k)(*[sl.snap6.data_ptr() for sl in p.slots])
+        raw = (C.c_char * C.sizeof(p.arr)).from_address(C.addressof(p.arr))
+        p.view = np.frombuffer(raw, dtype=self._DTYPE)
+        p.n = np.array([sl.n for sl in p.slots], dtype=np.int64)
+        p.steps = np.array([sl.result.steps for sl in p.slots], dtype=np.int64)
+        p.inter = np.array([sl.result.interactions for sl in p.slots], dtype=np.int64)
 
     def step(self):
-        """One iteration: every resident system advances one block step in one
-        native call (select, then predict, force and correct for every system not
-        yet past its t_end, one launch per phase); finished or failed systems are
-        retired.  The items live in one array across iterations and the per-system
-        bookkeeping is vectorised, so the host work per iteration does not grow with
-        the number of resident systems."""
+        """One iteration: every resident system advances one block step, one native
+        call per pipe (select, then predict, force and correct for every system of
+        the pipe not yet past its t_end, one launch per phase); finished or failed
+        systems are retired.  The items live in one array per pipe across iterations
+        and the per-system bookkeeping is vectorised, so the host work per iteration
+        does not grow with the number of resident systems."""
         if not self.slots:
             return
-        if self._arr is None:
-            self._build_items()
-        v = self._view
+        for p in self._pipes:
+            if p.slots:
+                self._step_pipe(p)
+        self.iterations += 1
+
+    def _step_pipe(self, p):
+        if p.arr is None:
+            self._build_items(p)
+        v = p.view
+        k_items = len(p.slots)
         startup = v["startup"] != 0          # before the call, which clears it
         if self.order == 6:
-            self._check(self.L.nb_step6_batch(self.ctx.h, self._arr, self._h6, self._snaps,
-                                              len(self.slots), self.prec_code, self.eta,
-                                              self.eta_s, self.dt_max, self.dt_min))
+            self._check(self.L.nb_step6_batch(p.ctx.h, p.arr, p.h6, p.snaps, k_items,
+                                              self.prec_code, self.eta, self.eta_s, self.dt_max,
+                                              self.dt_min), p.ctx)
         else:
-            self._check(self.L.nb_step_batch(self.ctx.h, self._arr, len(self.slots),
-                                             self.prec_code, self.eta, self.eta_s, self.dt_max,
-                                             self.dt_min))
+            self._check(self.L.nb_step_batch(p.ctx.h, p.arr, k_items, self.prec_code, self.eta,
+                                             self.eta_s, self.dt_max, self.dt_min), p.ctx)
         # copies: a pair's return to the N-body system below rebuilds the item array
         err, done, t_next = v["error"].copy(), v["done"].copy(), v["t_next"].copy()
-        at_step = list(self.slots)
+        at_step = list(p.slots)
         self._returned = set()
         m_blk = v["m"].astype(np.int64)
         ran = (err == 0) & (done == 0)
-        n = self._n
+        n = p.n
         passes = 2 if self.order == 6 else 1        # force passes of a startup step
         inc = np.where(startup, passes * n * n, m_blk * n)
-        self._inter[ran] += inc[ran]
-        self._steps[ran & ~startup] += 1
-        self.iterations += 1
+        p.inter[ran] += inc[ran]
+        p.steps[ran & ~startup] += 1
+        steps = p.steps.copy()
         if self.groups:
             # the previous block's pairs go to the CPU thread (or return to the
             # N-body system); this block's systems get their tidal tensors after
             # the retirements below
             stepped = {}
             for k in np.flatnonzero(ran & ~startup):
-                if self.slots[k].ps is not None:
-                    stepped[self.slots[k]] = float(t_next[k])
+                if at_step[k].ps is not None:
+                    stepped[at_step[k]] = float(t_next[k])
             failed = self._queue_pairs(stepped) or {}
             if self.capture_every:
                 # on every capture_every-th block step of each system (its own count,
                 # so that a system's run does not depend on what else is resident)
                 blocks = {sl: int(m_blk[k]) for k, sl in enumerate(at_step)
                           if sl in stepped and sl not in failed
-                          and self._steps[k] % self.capture_every == 0}
+                          and steps[k] % self.capture_every == 0}
                 failed.update(self._capture(blocks, stepped))
             for sl, tb in stepped.items():
                 if sl.ps is not None and sl.ps.np:
@@ -852,7 +892,7 @@ class Server:
         else:
             failed = {}
         leave = np.flatnonzero((err != 0) | (done != 0))
-        gone = [(self.slots[k], _lib.STATUS.get(int(err[k]), str(int(err[k])))
+        gone = [(at_step[k], _lib.STATUS.get(int(err[k]), str(int(err[k])))
                  if err[k] != 0 else None) for k in leave]
         gone += [(sl, msg) for sl, msg in failed.items() if sl not in dict(gone)]
         for sl, e in gone:
@@ -886,7 +926,8 @@ class Server:
             self.step()
             if on_iteration is not None:
                 on_iteration(self)
-        self.ctx.sync()
+        for p in self._pipes:
+            p.ctx.sync()
         return self.results
 
 

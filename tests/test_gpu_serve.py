@@ -51,6 +51,15 @@ def test_same_result_alone_and_in_a_mix(ctx, precision):
         assert a[f].tobytes() == b[f].tobytes(), f
     assert alone[0].steps == mixed[0].steps
     assert np.all(b["t"] == 0.25)
+    # the same mix on two pipes (two streams, systems split between them)
+    two, srv2 = _serve(ctx, mix, precision, max_slots=3, pipes=2)
+    assert len(srv2._pipes) == 2
+    for rid, r in mixed.items():
+        assert two[rid].error is None
+        for f in FIELDS:
+            assert r.final[f].tobytes() == two[rid].final[f].tobytes(), (rid, f)
+        assert (r.steps, r.interactions, r.energy1) == (two[rid].steps, two[rid].interactions,
+                                                        two[rid].energy1)
 
 
 @pytest.mark.parametrize("order", [4, 6])
@@ -73,6 +82,9 @@ def test_lane_target_alone_and_in_a_mix(ctx, order):
     a, b = alone[0].final, mixed[0].final
     for f in FIELDS:
         assert a[f].tobytes() == b[f].tobytes(), f
+    two, _ = _serve(ctx, mix, "mixed", max_slots=3, lanes=lanes, order=order, pipes=2)
+    for f in FIELDS:
+        assert a[f].tobytes() == two[0].final[f].tobytes(), f
     assert alone[0].steps == mixed[0].steps
     assert np.all(b["t"] == 0.125)
     assert alone[0].energy_error < 1e-5
@@ -103,16 +115,19 @@ def _target_log(rid):
     log, seen = [], []
 
     def hook(srv):
-        for k, sl in enumerate(srv.slots):
+        for sl in srv.slots:
             if sl.req.rid != rid:
                 continue
             if not seen:
                 seen.append(True)       # admitted this iteration: the startup step
                 return
-            # the item array is rebuilt after a retirement; its values are then in sl.item
-            t_next, m, done, err = ((float(srv._view["t_next"][k]), int(srv._view["m"][k]),
-                                     int(srv._view["done"][k]), int(srv._view["error"][k]))
-                                    if srv._arr is not None else
+            # the item array of the slot's pipe is rebuilt after a retirement; its
+            # values are then in sl.item
+            p = sl.pipe
+            k = p.slots.index(sl)
+            t_next, m, done, err = ((float(p.view["t_next"][k]), int(p.view["m"][k]),
+                                     int(p.view["done"][k]), int(p.view["error"][k]))
+                                    if p.arr is not None else
                                     (sl.item.t_next, sl.item.m, sl.item.done, sl.item.error))
             if not done and not err:
                 log.append((t_next, sl.i_idx[:m].cpu().numpy().astype(np.int64)))
