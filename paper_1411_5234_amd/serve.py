@@ -108,6 +108,9 @@ class _Slot:
         self.result = Result(req.rid, snap.n, req.arrival, now, float("nan"))
         if self.ps is not None:
             self.result.pairs = self.ps.np
+        self.pipe = None                   # the server pipe it is stepped on
+        self.capture_pass = 0              # capture passes run on this system
+        self.refused = {}                  # candidate pair -> pass at which it was refused
 
     def _work_buffers(self):
         """Active list and force outputs sized for the system, pointed to by the item."""
@@ -569,7 +572,7 @@ class Server:
         for sl, m in cand:
             r_, n_ = rows_h[off: off + m], nn_h[off: off + m]
             off += m
-            sl.capture_pass = getattr(sl, "capture_pass", 0) + 1
+            sl.capture_pass += 1
             ok = n_ >= 0
             if not np.any(ok):
                 continue
@@ -580,9 +583,10 @@ class Server:
                 continue
             p, q = r_[mutual], n_[mutual]
             # candidates refused in the last CAPTURE_RETRY passes wait
-            refused = getattr(sl, "refused", None)
-            if refused is None:
-                refused = sl.refused = {}
+            refused = sl.refused
+            if len(refused) > 4096:          # forget refusals that have expired
+                sl.refused = refused = {key: at for key, at in refused.items()
+                                        if sl.capture_pass - at < self.CAPTURE_RETRY}
             keys = list(zip(sl.ps.singles[p].tolist(), sl.ps.singles[q].tolist()))
             fresh = np.array([sl.capture_pass - refused.get(key, -self.CAPTURE_RETRY)
                               >= self.CAPTURE_RETRY for key in keys])
