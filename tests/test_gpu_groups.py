@@ -293,3 +293,49 @@ def test_queued_advances_run_in_call_order(ctx):
     assert ctx.L.nb_groups_wait(ctx.h) == -7
     assert list(st) == [0, 0, -7, 0, 0, 0]
     assert ctx.L.nb_groups_wait(ctx.h) == 0
+
+
+def test_capture_calls_refuse_bad_arguments(ctx, orc):
+    """nb_tidal_points and nb_nearest_active_batch check their arguments before
+    anything is enqueued; an active index outside the system is reported in the
+    item's status word and its row is not searched."""
+    from paper_1411_5234_amd._lib import NbError, NbNearestItem
+    s = inputs.plummer(300, 5)
+    sys = device_system(s.x, s.v, s.m)
+    P = torch.zeros(3, dtype=torch.float64, device="cuda")
+    T = torch.zeros(9, dtype=torch.float64, device="cuda")
+    for k, pts, eps in ((1, P.data_ptr(), -1.0), (-1, P.data_ptr(), 1e-3), (1, None, 1e-3)):
+        with pytest.raises(NbError) as e:
+            ctx._check(ctx.L.nb_tidal_points(ctx.h, sys.ref, k, pts, None, eps, T.data_ptr()))
+        assert e.value.name == "NB_EINVAL"
+    ctx._check(ctx.L.nb_tidal_points(ctx.h, sys.ref, 0, None, None, 1e-3, None))   # no-op
+
+    idx = torch.as_tensor(np.array([3, 300, 7], dtype=np.int32), device="cuda")
+    nn = torch.full((3,), -7, dtype=torch.int32, device="cuda")
+    r2 = torch.zeros(3, dtype=torch.float64, device="cuda")
+    word = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def item(m=3, cap=np.inf, nnp=None):
+        it = (NbNearestItem * 1)()
+        it[0].sys = sys._struct
+        it[0].i_idx = idx.data_ptr()
+        it[0].m = m
+        it[0].row_end = 300
+        it[0].dt_cap = cap
+        it[0].nn = nn.data_ptr() if nnp is None else nnp
+        it[0].r2 = r2.data_ptr()
+        it[0].status = word.data_ptr()
+        return it
+
+    for bad in (item(m=301), item(cap=float("nan")), item(nnp=0)):
+        with pytest.raises(NbError) as e:
+            ctx._check(ctx.L.nb_nearest_active_batch(ctx.h, bad, 1))
+        assert e.value.name == "NB_EINVAL"
+    ctx._check(ctx.L.nb_nearest_active_batch(ctx.h, item(m=0), 1))           # skipped
+    ctx._check(ctx.L.nb_nearest_active_batch(ctx.h, item(), 1))
+    ctx.sync()
+    got = nn.cpu().numpy()
+    assert got[1] == -1 and got[0] >= 0 and got[2] >= 0
+    assert word.item() != 0                     # the bad index was reported
+    onn, _ = orc.nearest(s.x, [3, 7])
+    assert [got[0], got[2]] == onn.tolist()
