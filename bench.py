@@ -43,7 +43,7 @@ PEAK_FP64_TFLOPS = 78.6
 # plain-copy calibration: x2.0 fetch, x1.0 write), keyed by the hash of the force
 # kernel's sources, the precision, N and the launch plan.  Reported only for that
 # exact kernel and launch; null otherwise.  Taken with the current sources.
-TRAFFIC = {("69214b403c3b8785", "mixed", 1 << 20, (2, 1, 4)): 2.7709e9 + 2.0133e8}
+TRAFFIC = {("5fcf579e3352ce45", "mixed", 1 << 20, (2, 1, 4)): 2.7712e9 + 2.0133e8}
 
 
 def _kernel_source_hash(order=4):
