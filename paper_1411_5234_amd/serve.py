@@ -29,7 +29,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import NbBatchItem, NbError, NbHermite6, NbTidalItem, PRECISIONS
+from ._lib import FIELDS32, FIELDS64, NbBatchItem, NbError, NbHermite6, NbTidalItem, PRECISIONS
 from .groups import PairSet, PairTable
 from .nbody import Context, Hermite6, System
 
@@ -115,9 +115,10 @@ class _Slot:
     def _work_buffers(self):
         """Active list and force outputs sized for the system, pointed to by the item."""
         n1 = max(self.n, 1)
-        self.i_idx = torch.zeros(n1, dtype=torch.int32, device=self.device)
-        self.acc = torch.zeros(3 * n1, dtype=torch.float64, device=self.device)
-        self.jerk = torch.zeros(3 * n1, dtype=torch.float64, device=self.device)
+        # written by the selection and the force before they are read
+        self.i_idx = torch.empty(n1, dtype=torch.int32, device=self.device)
+        self.acc = torch.empty(3 * n1, dtype=torch.float64, device=self.device)
+        self.jerk = torch.empty(3 * n1, dtype=torch.float64, device=self.device)
         self.item.sys = self.sys._struct
         self.item.i_idx = self.i_idx.data_ptr()
         self.item.acc = self.acc.data_ptr()
@@ -423,7 +424,13 @@ class Server:
         new64[:, -1 - src[r]] (FIELDS64 order, its predicted set equal to its state),
         with FP32 copies rounded from them."""
         n_new = src.size
-        sysn = System(n_new, self.device, fp32_copies=(self.precision != "fp64"))
+        fp32 = self.precision != "fp64"
+        # every column is written below
+        sysn = System(n_new, self.device, fp32_copies=fp32,
+                      buf64=torch.empty((len(FIELDS64), max(n_new, 1)), dtype=torch.float64,
+                                        device=self.device),
+                      buf32=torch.empty((len(FIELDS32), max(n_new, 1)), dtype=torch.float32,
+                                        device=self.device) if fp32 else None)
         old = src >= 0
         with torch.cuda.stream(self.ctx.stream):
             if np.any(old):
@@ -466,7 +473,7 @@ class Server:
         ps.drain(ctx)
         ps.advance(ctx, ks, t_prev, Tk, self.per_period, self.max_sub, queue=False)
         cm_rows = ps.cm0 + ks
-        T = torch.zeros(9 * ks.size, dtype=torch.float64, device=self.device)
+        T = torch.empty(9 * ks.size, dtype=torch.float64, device=self.device)
         rows_dev = torch.as_tensor(cm_rows.astype(np.int32), device=self.device)
         self._check(self.L.nb_tidal_active(ctx.h, sl.sys.ref, rows_dev.data_ptr(), ks.size, 0,
                                            sl.n, eps, T.data_ptr()))
@@ -511,8 +518,8 @@ class Server:
         new_rows = np.flatnonzero(~old).astype(np.int32)
         idx = torch.as_tensor(new_rows, device=self.device)
         k = new_rows.size
-        acc = torch.zeros(3 * k, dtype=torch.float64, device=self.device)
-        jerk = torch.zeros(3 * k, dtype=torch.float64, device=self.device)
+        acc = torch.empty(3 * k, dtype=torch.float64, device=self.device)
+        jerk = torch.empty(3 * k, dtype=torch.float64, device=self.device)
         ctx.predict(sysn, t_now)
         ctx.force_active(sysn, idx, k, 0, n_new, eps, self.precision, acc, jerk)
         tick = math.ldexp(1.0, -40)
