@@ -96,11 +96,11 @@ def parse():
     ap.add_argument("--groups", action="store_true",
                     help="serve mode, C5 stream: carry each primordial binary as one body at its "
                          "centre of mass, its relative orbit advanced on CPU threads")
-    ap.add_argument("--capture-every", type=int, default=16,
+    ap.add_argument("--capture-every", type=int, default=64,
                     help="serve mode, C5 stream with --groups: every that many block steps of "
                          "a system, single bodies of its block that are each other's nearest "
                          "neighbours, bound and weakly perturbed become a pair (0: off; "
-                         "16 was the fastest of 4, 16 and off)")
+                         "64 was the fastest of 4, 16, 32, 64, 128 and off)")
     ap.add_argument("--precisions", default="mixed,fp64",
                     help="serve mode, C5 stream: the precisions each request is served in")
     ap.add_argument("--pipes", type=int, default=1, choices=[1, 2],
