@@ -66,15 +66,20 @@ class System:
         v = np.asarray(v, dtype=np.float64)
         m = np.asarray(m, dtype=np.float64)
         s = cls(m.shape[0], device, fp32_copies)
-        host = torch.zeros((len(FIELDS64), max(s.n, 1)), dtype=torch.float64)
+        # staged in pinned host memory (pageable copies go through a slow bounce
+        # path); torch's pinned-block cache keeps the block until the copy is done
+        pinned = s.buf64.is_cuda
+        host = torch.empty((len(FIELDS64), max(s.n, 1)), dtype=torch.float64, pin_memory=pinned)
+        h = host.numpy()
+        h[:] = 0.0
         if s.n:
-            host[0:3, : s.n] = torch.from_numpy(np.ascontiguousarray(x.T))
-            host[3:6, : s.n] = torch.from_numpy(np.ascontiguousarray(v.T))
-            host[12, : s.n] = torch.from_numpy(m)
+            h[0:3, : s.n] = x.T
+            h[3:6, : s.n] = v.T
+            h[12, : s.n] = m
             # the predicted set starts equal to the state (t = 0, nothing to extrapolate)
-            host[15:18, : s.n] = host[0:3, : s.n]
-            host[18:21, : s.n] = host[3:6, : s.n]
-        s.buf64.copy_(host)
+            h[15:18, : s.n] = h[0:3, : s.n]
+            h[18:21, : s.n] = h[3:6, : s.n]
+        s.buf64.copy_(host, non_blocking=pinned)
         if s.buf32 is not None:
             s.buf32[0:3].copy_(s.buf64[18:21].float())
             s.buf32[3].copy_(s.buf64[12].float())
@@ -82,7 +87,12 @@ class System:
 
     def state_numpy(self) -> dict:
         """Copy the FP64 state back as numpy: x, v, a, j (n, 3); m, t, dt (n,)."""
-        h = self.buf64[:, : self.n].cpu().numpy()
+        if self.buf64.is_cuda:
+            pin = torch.empty((self.buf64.shape[0], self.n), dtype=torch.float64, pin_memory=True)
+            pin.copy_(self.buf64[:, : self.n])          # synchronous: pin is filled on return
+            h = pin.numpy()
+        else:
+            h = self.buf64[:, : self.n].numpy()
         return {"x": h[0:3].T.copy(), "v": h[3:6].T.copy(), "a": h[6:9].T.copy(),
                 "j": h[9:12].T.copy(), "m": h[12].copy(), "t": h[13].copy(), "dt": h[14].copy(),
                 "xp": h[15:18].T.copy(), "vp": h[18:21].T.copy()}
@@ -114,7 +124,12 @@ class Hermite6:
 
     def state_numpy(self) -> dict:
         """Snap s, crackle c and predicted acceleration ap as numpy (n, 3)."""
-        h = self.buf64[:, : self.n].cpu().numpy()
+        if self.buf64.is_cuda:
+            pin = torch.empty((self.buf64.shape[0], self.n), dtype=torch.float64, pin_memory=True)
+            pin.copy_(self.buf64[:, : self.n])          # synchronous: pin is filled on return
+            h = pin.numpy()
+        else:
+            h = self.buf64[:, : self.n].numpy()
         return {"s": h[0:3].T.copy(), "c": h[3:6].T.copy(), "ap": h[6:9].T.copy()}
 
 
