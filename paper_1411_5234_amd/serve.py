@@ -247,6 +247,7 @@ class Server:
         self._tid_dev = None
         self._tid_host = None
         self._tid_slots = []
+        self._q_sets = []
         self._returned = set()
         self.order = order
         _lib.force_plan(1, 1, "mixed", lanes)     # raises on a target out of range
@@ -365,17 +366,18 @@ class Server:
         iteration, `stepped`: slot -> its block time).  Returns {slot: message} of
         systems whose pair return failed."""
         tab = self.ptab
-        live = set(id(ps) for ps in tab.sets)
-        sets = [(sl, sl.ps) for sl in self._tid_slots
-                if sl.ps is not None and id(sl.ps) in live and sl.ps.np and sl in self.slots]
-        if self._tid_host is None or not sets:
+        if self._tid_host is None or not self._q_sets:
             return {}
-        k = np.array([ps.np for _, ps in sets], dtype=np.int64)
-        tot = int(k.sum())
-        local = np.arange(tot) - np.repeat(np.cumsum(k) - k, k)
-        rows = np.repeat([ps.base for _, ps in sets], k) + local        # table rows
-        tid = np.repeat([ps.tid_base for _, ps in sets], k)             # their tidal offsets
-        owner = np.repeat(np.arange(len(sets)), k)
+        # the sets of the last tidal layout, whose tensors and times are in the host
+        # buffers (only admissions happen between that layout and this call, and
+        # they add sets); the table rows from the sets' current bases, which a
+        # compaction may have moved since
+        sets, k, local = self._q_sets, self._q_k, self._q_local
+        tid, owner = self._q_tid, self._q_owner                          # tidal offsets
+        if any(sl.ps is not ps for sl, ps in sets):
+            raise RuntimeError("pair sets changed without a new tidal layout")
+        rows = np.repeat(np.fromiter((ps.base for _, ps in sets), dtype=np.int64,
+                                     count=len(sets)), k) + local        # table rows
         pt = tab.prev_t[rows]
         tcm = self._tcm_host.numpy()[tid + local]
         due = np.flatnonzero((tcm == pt) & (tab.tpair[rows] < pt))
@@ -740,6 +742,20 @@ class Server:
             it.nrows = sl.ps.np
         self._tid_items = items
         self._tid_ext = max([sl.ps.tid_base + sl.ps.np for sl in gs], default=0)
+        # per layout: the numpy view of the items' i_idx and m, each slot's two lists
+        # (its block's active list, its centres of mass), and the pair-queue arrays
+        raw = (C.c_char * C.sizeof(items)).from_address(C.addressof(items))
+        self._tid_view = np.frombuffer(raw, dtype=self._TID_DTYPE)
+        self._tid_index = {id(sl): q for q, sl in enumerate(gs)}
+        self._tid_iidx = np.array([sl.i_idx.data_ptr() for sl in gs], dtype=np.uint64)
+        self._tid_cmidx = np.array([sl.cm_idx.data_ptr() for sl in gs], dtype=np.uint64)
+        self._tid_np = np.array([sl.ps.np for sl in gs], dtype=np.int32)
+        k = self._tid_np.astype(np.int64)
+        self._q_sets = [(sl, sl.ps) for sl in gs]
+        self._q_k = k
+        self._q_local = np.arange(int(k.sum())) - np.repeat(np.cumsum(k) - k, k)
+        self._q_tid = np.repeat(np.array([sl.ps.tid_base for sl in gs], dtype=np.int64), k)
+        self._q_owner = np.repeat(np.arange(len(gs)), k)
         self._tid_stale = False
 
     def _tidal(self, ran_slots):
@@ -751,16 +767,22 @@ class Server:
         if not self._tid_slots:
             return
         items = self._tid_items
-        for q, sl in enumerate(self._tid_slots):
-            if sl in self._returned:
-                # pairs returned this iteration: the system's bodies were renumbered
-                # after its block, so every pair's tensor is taken (the times tell
-                # the pairs of the block from the others)
-                items[q].i_idx = sl.cm_idx.data_ptr()
-                items[q].m = sl.ps.np if sl in ran_slots else 0
-            else:
-                items[q].i_idx = sl.i_idx.data_ptr()
-                items[q].m = ran_slots.get(sl, 0)
+        ptr = self._tid_iidx.copy()
+        m = np.zeros(len(self._tid_slots), dtype=np.int32)
+        for sl, mb in ran_slots.items():
+            q = self._tid_index.get(id(sl))
+            if q is not None:
+                m[q] = mb
+        for sl in self._returned:
+            # pairs returned or formed this iteration: the system's bodies were
+            # renumbered after its block, so every pair's tensor is taken (the times
+            # tell the pairs of the block from the others)
+            q = self._tid_index.get(id(sl))
+            if q is not None:
+                ptr[q] = self._tid_cmidx[q]
+                m[q] = self._tid_np[q] if sl in ran_slots else 0
+        self._tid_view["i_idx"] = ptr
+        self._tid_view["m"] = m
         self._check(self.L.nb_tidal_active_batch(self.ctx.h, items, len(self._tid_slots)))
         e = self._tid_ext
         with torch.cuda.stream(self.ctx.stream):
@@ -808,6 +830,9 @@ class Server:
         if rc != 0:
             raise NbError(rc, self.L.nb_last_error((ctx or self.ctx).h).decode())
 
+    _TID_DTYPE = np.dtype({"names": ["i_idx", "m"], "formats": ["<u8", "<i4"],
+                           "offsets": [NbTidalItem.i_idx.offset, NbTidalItem.m.offset],
+                           "itemsize": C.sizeof(NbTidalItem)})
     _FIELDS = ("t_next", "m", "startup", "error", "done")
     _DTYPE = np.dtype({"names": list(_FIELDS), "formats": ["<f8", "<i4", "<i4", "<i4", "<i4"],
                        "offsets": [getattr(NbBatchItem, f).offset for f in _FIELDS],
