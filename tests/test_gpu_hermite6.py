@@ -39,6 +39,29 @@ def test_force6_plummer_1024_all_active(ctx, orc, precision):
     check6(orc, precision, g, s.x, s.v, ap, s.m, 1e-3, tag="N=1024")
 
 
+@pytest.mark.parametrize("precision", ["mixed", "ds", "fp64"])
+def test_force6_plummer_2pow20_all_active_sampled(ctx, orc, precision):
+    """The 6th-order launch of `bench.py --order 6` (m = N = 2^20) on 256 random
+    bodies and on the 128 bodies whose acceleration or jerk cancels most.  The
+    predicted accelerations are the smooth mean field of the Plummer model,
+    -r / (r^2 + a^2)^(3/2) with a = 3 pi / 16, a seeded input that both sides take
+    (an oracle pass over all 2^20 bodies would take the CPU too long)."""
+    from test_gpu_force import top_kappa_2pow20
+    n = 1 << 20
+    s = inputs.plummer(n, 3)
+    a2 = (3.0 * np.pi / 16.0) ** 2
+    ap = -s.x / ((s.x ** 2).sum(1) + a2)[:, None] ** 1.5
+    sys, h6 = device_system6(s.x, s.v, s.m, ap)
+    g = gpu_force6(ctx, sys, h6, 1e-4, precision)
+    pick = np.sort(np.random.default_rng(31).choice(n, 256, replace=False))
+    check6(orc, precision, tuple(q[pick] for q in g), s.x, s.v, ap, s.m, 1e-4, pick,
+           tag="N=2^20 all active (256 sampled)")
+    top_a, top_j = top_kappa_2pow20()
+    top = np.unique(np.concatenate([top_a, top_j]))
+    check6(orc, precision, tuple(q[top] for q in g), s.x, s.v, ap, s.m, 1e-4, top,
+           tag="N=2^20 all active (the 128 largest kappa)")
+
+
 @pytest.fixture(scope="module")
 def salpeter16k(orc):
     n = 16384
