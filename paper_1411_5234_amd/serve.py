@@ -152,6 +152,38 @@ def footprint_bytes(n: int, precision: str = "mixed", order: int = 4) -> int:
     return per_body * max(n, 1) + 4 + 1024
 
 
+def return_layout(old_singles, new_singles, members, old_cm0, keep_pairs):
+    """Rows of a reduced system after pairs return to the N-body system: for each row
+    of the new system (its bodies in no pair, in index order, then the kept pairs'
+    centres of mass), the row of the old system it continues (>= 0), or -1 - q for
+    the q-th returning member (`members`, original indices).  old_singles and
+    new_singles are the sorted original indices of the bodies in no pair."""
+    ns = np.asarray(new_singles, dtype=np.int64)
+    os_ = np.asarray(old_singles, dtype=np.int64)
+    members = np.asarray(members, dtype=np.int64)
+    keep_pairs = np.asarray(keep_pairs, dtype=np.int64)
+    src = np.empty(ns.size + keep_pairs.size, dtype=np.int64)
+    at = np.minimum(np.searchsorted(os_, ns), max(os_.size - 1, 0))
+    is_old = (os_[at] == ns) if os_.size else np.zeros(ns.size, dtype=bool)
+    src[: ns.size][is_old] = at[is_old]
+    order = np.argsort(members)
+    src[: ns.size][~is_old] = -1 - order[np.searchsorted(members[order], ns[~is_old])]
+    src[ns.size:] = old_cm0 + keep_pairs
+    return src
+
+
+def mutual_nearest(rows, nn, n):
+    """Pairs (p, q), p < q, of listed bodies that are each other's nearest neighbour:
+    rows[k] lists a body, nn[k] its nearest neighbour (-1: not searched)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    nn = np.asarray(nn, dtype=np.int64)
+    ok = nn >= 0
+    nbr = np.full(n, -1, dtype=np.int64)
+    nbr[rows[ok]] = nn[ok]
+    mutual = ok & (nbr[np.maximum(nn, 0)] == rows) & (rows < nn)
+    return rows[mutual], nn[mutual]
+
+
 class Admission:
     """Admission policy and slot/memory accounting of the server (no device work).
 
@@ -500,17 +532,8 @@ class Server:
         # the new reduced system: bodies in no pair in index order, then the
         # remaining pairs' centres of mass (the layout nb_pairs_reduce makes)
         keep_pairs = np.setdiff1d(np.arange(ps.np), ks)
-        n_new = new_ps.cm0 + new_ps.np
-        src = np.empty(n_new, dtype=np.int64)          # old row, or -1 - member slot
-        # both lists of single bodies are sorted: rows by binary search
-        ns = new_ps.singles
-        at = np.minimum(np.searchsorted(ps.singles, ns), max(ps.singles.size - 1, 0))
-        was = ps.singles.size > 0
-        is_old = (ps.singles[at] == ns) if was else np.zeros(ns.size, dtype=bool)
-        src[: ns.size][is_old] = at[is_old]
-        order = np.argsort(members)
-        src[: ns.size][~is_old] = -1 - order[np.searchsorted(members[order], ns[~is_old])]
-        src[new_ps.cm0:] = ps.cm0 + keep_pairs
+        src = return_layout(ps.singles, new_ps.singles, members, ps.cm0, keep_pairs)
+        n_new = src.size
         km = members.size
         new64 = self._new_rows(xm, vm, np.zeros((km, 3)), np.zeros((km, 3)), ps.m[members],
                                np.full(km, t_now), np.full(km, cap_cm))
@@ -585,12 +608,9 @@ class Server:
             ok = n_ >= 0
             if not np.any(ok):
                 continue
-            nbr = np.full(sl.n, -1, dtype=np.int64)
-            nbr[r_[ok]] = n_[ok]
-            mutual = ok & (nbr[np.maximum(n_, 0)] == r_) & (r_ < n_)
-            if not np.any(mutual):
+            p, q = mutual_nearest(r_, n_, sl.n)
+            if p.size == 0:
                 continue
-            p, q = r_[mutual], n_[mutual]
             # candidates refused in the last CAPTURE_RETRY passes wait
             refused = sl.refused
             if len(refused) > 4096:          # forget refusals that have expired

@@ -208,6 +208,29 @@ def test_plummer_2pow20_all_active_sampled(ctx, orc, precision):
     assert np.all(np.abs(ma) <= 1e-6 * (s.m[:, None] * np.abs(ga)).sum(0))
 
 
+@pytest.mark.parametrize("precision", ["mixed", "ds", "fp64"])
+def test_c5_binaries_65536(ctx, orc, precision):
+    """The precision-stress workload: a Kroupa cluster of 65536 bodies with 10% of
+    them in binaries (separations 1e-4 .. 1e-2 at positions of order 1), eps = 1e-5.
+    All bodies active, and a block made of binary members only (the small block of
+    tiny steps such a cluster keeps running), each checked on every member of 64
+    binaries and on 128 random bodies."""
+    n = 1 << 16
+    s = inputs.with_binaries(n, 5001)
+    pairs = np.asarray(s.meta["pairs"])
+    rng = np.random.default_rng(32)
+    members = np.sort(pairs[rng.choice(len(pairs), 64, replace=False)].ravel())
+    pick = np.unique(np.concatenate([members, rng.choice(n, 128, replace=False)]))
+    sys = device_system(s.x, s.v, s.m)
+    ga, gj = gpu_force(ctx, sys, 1e-5, precision)
+    check(orc, precision, ga[pick], gj[pick], s.x, s.v, s.m, 1e-5, pick,
+          tag="C5 N=65536 all active (binary members and random bodies)")
+    block = np.sort(pairs[rng.choice(len(pairs), 200, replace=False)].ravel())
+    ga, gj = gpu_force(ctx, sys, 1e-5, precision, block)
+    check(orc, precision, ga, gj, s.x, s.v, s.m, 1e-5, block,
+          tag="C5 N=65536 block of %d binary members" % block.size)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 def test_single_body_and_coincident_bodies(ctx, precision):
     """A lone body feels exactly zero.  Bodies at one point (eps > 0) exert exactly

@@ -3,10 +3,13 @@
 A test-only stub stands in for the device: each admitted request needs a fixed
 number of iterations.  The policy must keep the slot and memory limits at every
 iteration, admit in arrival order as soon as capacity frees up (continuous
-batching), and refuse requests that could never fit.
+batching), and refuse requests that could never fit.  Also the server's host-side
+bookkeeping of grouped pairs: the row layout after pairs return, and the mutual
+nearest neighbours from which new pairs are taken.
 """
 from dataclasses import dataclass
 
+import numpy as np
 import pytest
 
 from paper_1411_5234_amd.serve import Admission, footprint_bytes
@@ -117,3 +120,46 @@ def test_summary_names_the_request_with_the_largest_energy_error():
     assert s["energy_error_worst_request"] == {"rid": 1, "n": 900}
     assert s["energy_error_max"] == pytest.approx(0.0001 / 0.25)
     assert s["solves_per_s"] == pytest.approx(0.75)
+
+
+def test_return_layout_matches_a_plain_mapping():
+    """The rows of a reduced system after pairs return: every body in no pair keeps
+    its old row or is a returning member, the kept pairs' centres of mass follow;
+    against a plain dictionary mapping on random pair sets."""
+    from paper_1411_5234_amd.serve import return_layout
+    rng = np.random.default_rng(7)
+    for n, npairs, kret in ((40, 10, 3), (12, 6, 6), (30, 1, 1), (9, 0, 0), (50, 20, 0)):
+        perm = rng.permutation(n)
+        pairs = perm[: 2 * npairs].reshape(-1, 2)
+        ks = np.sort(rng.choice(npairs, kret, replace=False)) if npairs else np.zeros(0, int)
+        old_singles = np.setdiff1d(np.arange(n), pairs.ravel())
+        keep = np.setdiff1d(np.arange(npairs), ks)
+        new_singles = np.setdiff1d(np.arange(n), pairs[keep].ravel())
+        members = pairs[ks].ravel()
+        src = return_layout(old_singles, new_singles, members, old_singles.size, keep)
+        old_row = {int(i): r for r, i in enumerate(old_singles)}
+        mem_row = {int(i): q for q, i in enumerate(members)}
+        want = [old_row[int(i)] if int(i) in old_row else -1 - mem_row[int(i)]
+                for i in new_singles] + [old_singles.size + int(k) for k in keep]
+        assert src.tolist() == want, (n, npairs, kret)
+
+
+def test_mutual_nearest_neighbours():
+    from paper_1411_5234_amd.serve import mutual_nearest
+    rows = np.array([3, 5, 7, 9, 11, 2])
+    nn = np.array([5, 3, 9, 4, -1, 7])      # 3<->5 mutual; 7->9 but 9->4; 11 unsearched
+    p, q = mutual_nearest(rows, nn, 12)
+    assert p.tolist() == [3] and q.tolist() == [5]
+    # a body whose neighbour is not listed (not in the block) pairs with nobody
+    p, q = mutual_nearest(np.array([1]), np.array([0]), 2)
+    assert p.size == 0
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        n = 40
+        rows = np.sort(rng.choice(n, 25, replace=False))
+        nn = np.where(rng.random(25) < 0.8, rng.choice(n, 25), -1)
+        nn[nn == rows] = -1
+        p, q = mutual_nearest(rows, nn, n)
+        d = dict(zip(rows.tolist(), nn.tolist()))
+        want = sorted((i, j) for i, j in d.items() if j >= 0 and d.get(j) == i and i < j)
+        assert sorted(zip(p.tolist(), q.tolist())) == want
