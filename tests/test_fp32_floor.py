@@ -98,3 +98,43 @@ def test_fp32_arithmetic_error_is_a_few_units_of_the_scale(case):
     assert plain > 1e-6                      # what the GPU shows for this body (4.1e-6)
     assert over <= 1e-6                      # the scale gate holds
     assert np.linalg.norm(a - oa) / np.linalg.norm(oa) <= 1e-6
+
+
+# ---- the velocity copies -----------------------------------------------------------------
+# The pair arithmetic takes velocity differences from FP32 copies of the predicted
+# velocities (Sec. 2 item 4 keeps only the position differences and the sums in FP64).
+# Rounding v_i and v_j to FP32 moves dv = v_j - v_i by at most u (|v_i| + |v_j|),
+# u = 2^-24.  A jerk term is m L(dv) / s^(3/2) with L(dv) = dv - 3 (r.dv) r / s,
+# whose eigenvalues are 1 (across r) and 1 - 3 r^2 / s in [-2, 1] (along r), so the
+# term moves by at most 2 u m (|v_i| + |v_j|) / s^(3/2).  For a binary whose members
+# move slowly against each other (|dv| much below |v|) that is more than 1e-6 of the
+# jerk, whatever the rest of the arithmetic does.
+
+C5_N, C5_SEED, C5_EPS = 1 << 16, 5001, 1e-5
+C5_BODY = 2393   # a member of a wide, light binary: |dv| = 0.013 against |v| = 0.31
+
+
+def velocity_bound(x, v, m, eps, i):
+    """2 u sum_{j != i} m_j (|v_i| + |v_j|) / (|r_ij|^2 + eps^2)^(3/2)."""
+    d = np.delete(x, i, axis=0) - x[i]
+    s = (d * d).sum(1) + eps * eps
+    vn = np.linalg.norm(v, axis=1)
+    w = np.delete(m, i) * (vn[i] + np.delete(vn, i)) / s ** 1.5
+    return 2.0 * 2.0 ** -24 * w.sum()
+
+
+def test_fp32_velocities_set_the_jerk_floor_of_slow_binaries(orc):
+    s = inputs.with_binaries(C5_N, C5_SEED)
+    v32 = s.v.astype(np.float32).astype(np.float64)
+    _, oj = orc.force(s.x, s.v, s.m, C5_EPS, [C5_BODY])
+    _, oj32 = orc.force(s.x, v32, s.m, C5_EPS, [C5_BODY])   # only the velocities rounded
+    _, sj = orc.force_scale(s.x, s.v, s.m, C5_EPS, [C5_BODY])
+    err = np.linalg.norm(oj32 - oj)
+    plain = err / np.linalg.norm(oj)
+    kappa = sj[0] / np.linalg.norm(oj)
+    bound = velocity_bound(s.x, s.v, s.m, C5_EPS, C5_BODY)
+    print("FP32 velocities alone: plain jerk error %.3e (kappa_j %.2f), bound %.3e" % (
+        plain, kappa, bound / np.linalg.norm(oj)))
+    assert plain > 1e-6          # above the 1e-6 target from the velocity rounding alone,
+    assert kappa < 1.1           # on a body whose jerk is one term (no cancellation),
+    assert err <= bound          # and within the bound the GPU gate adds for it
