@@ -8,7 +8,9 @@ more than 1e-6 of its value.  These tests emulate that on the CPU for such a bod
 of the N = 2^20 Plummer sphere (seed 3, eps = 1e-4) and check the figures the
 GPU gates rest on: the plain error of that body exceeds 1e-6 from the rounding of
 the inputs alone, while its error over the magnitude scale sum_j |jerk_ij| stays
-a few FP32 units.  The reference is the FP64 oracle.
+a few FP32 units.  The reference is the FP64 oracle.  The last test does the same
+for the FP32 copies of the velocities on a member of a slow binary of the C5
+workload, and checks the bound that the GPU jerk gates allow for that rounding.
 """
 import numpy as np
 import pytest
