@@ -78,6 +78,9 @@ def lib():
         L.orc_tidal.restype = C.c_int
         L.orc_tidal.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, C.c_int64, C.c_int64,
                                 C.c_double, _dp]
+        L.orc_velocity_scale.restype = C.c_int
+        L.orc_velocity_scale.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int64, _ip, C.c_int64,
+                                         C.c_int64, C.c_double, _dp]
         L.orc_tidal_points.restype = C.c_int
         L.orc_tidal_points.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _dp, _ip, C.c_double,
                                        _dp]
@@ -146,6 +149,17 @@ def force_scale(x, v, m, eps, ilist=None, j0=0, j1=None):
     sj = np.zeros(ilist.size)
     _check(lib().orc_force_scale(n, x, v, m, ilist.size, ilist, int(j0), j1, float(eps), sa, sj))
     return sa, sj
+
+
+def velocity_scale(x, v, m, eps, ilist=None, j0=0, j1=None):
+    """Per body: sum_j m_j (|v_i| + |v_j|) / (|r_ij|^2 + eps^2)^(3/2)."""
+    x, v, m = _c(x), _c(v), _c(m)
+    n = m.shape[0]
+    ilist = np.arange(n, dtype=np.int64) if ilist is None else _c(ilist, np.int64)
+    j1 = n if j1 is None else int(j1)
+    sv = np.zeros(ilist.size)
+    _check(lib().orc_velocity_scale(n, x, v, m, ilist.size, ilist, int(j0), j1, float(eps), sv))
+    return sv
 
 
 def energy(x, v, m, eps):

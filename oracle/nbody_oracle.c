@@ -153,6 +153,44 @@ int orc_force_scale(int64_t n, const double *x, const double *v, const double *m
     return 0;
 }
 
+/* ---- velocity magnitude scale ------------------------------------------------
+ * Per listed body: sum_j m_j (|v_i| + |v_j|) / (|r_ij|^2 + eps^2)^(3/2) over j in
+ * [j0, j1), j != i.  A scale for the error that rounding the velocities to FP32
+ * (before their difference is formed) can cause in the jerk sum.
+ */
+int orc_velocity_scale(int64_t n, const double *x, const double *v, const double *m,
+                       int64_t ni, const int64_t *ilist, int64_t j0, int64_t j1, double eps,
+                       double *sv)
+{
+    if (j0 < 0 || j1 > n || j0 > j1)
+        return -1;
+    for (int64_t k = 0; k < ni; k++)
+        if (ilist[k] < 0 || ilist[k] >= n)
+            return -1;
+    const double eps2 = eps * eps;
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < ni; k++) {
+        const int64_t i = ilist[k];
+        const double vi = sqrt(v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
+                               v[3 * i + 2] * v[3 * i + 2]);
+        csum t = {0, 0};
+        for (int64_t j = j0; j < j1; j++) {
+            if (j == i)
+                continue;
+            double dr[3];
+            for (int d = 0; d < 3; d++)
+                dr[d] = x[3 * j + d] - x[3 * i + d];
+            const double s = dr[0] * dr[0] + dr[1] * dr[1] + dr[2] * dr[2] + eps2;
+            const double vj = sqrt(v[3 * j] * v[3 * j] + v[3 * j + 1] * v[3 * j + 1] +
+                                   v[3 * j + 2] * v[3 * j + 2]);
+            cs_add(&t, m[j] * (vi + vj) / (s * sqrt(s)));
+        }
+        sv[k] = cs_val(&t);
+    }
+    return 0;
+}
+
 /* ---- total energy ------------------------------------------------------------
  * E = sum_i m_i |v_i|^2 / 2  -  sum_{i<j} m_i m_j / sqrt(|r_ij|^2 + eps^2)
  * (the softened potential whose gradient is the force of Eq. 2; the self term

@@ -70,25 +70,11 @@ def report(tag, g_a, g_j, o_a, o_j):
     return ea, ej
 
 
-def velocity_bound(x, v, m, eps, ilist, j0=0, j1=None):
+def velocity_bound(orc, x, v, m, eps, ilist, j0=0, j1=None):
     """Per listed body: 2 u sum_{j != i} m_j (|v_i| + |v_j|) / (|r_ij|^2 + eps^2)^(3/2)
     over j in [j0, j1), the most the FP32 rounding of the velocities can move its
-    jerk (numpy, a few bodies at a time)."""
-    x, v, m = np.asarray(x), np.asarray(v), np.asarray(m)
-    j1 = len(m) if j1 is None else j1
-    xj, mj = x[j0:j1], m[j0:j1]
-    vn = np.linalg.norm(v, axis=1)
-    vj = vn[j0:j1]
-    out = np.empty(len(ilist))
-    for a in range(0, len(ilist), 8):
-        ii = np.asarray(ilist[a: a + 8])
-        d = xj[None, :, :] - x[ii][:, None, :]
-        s = (d * d).sum(2) + eps * eps
-        w = mj[None, :] * (vn[ii][:, None] + vj[None, :]) / s ** 1.5
-        self_j = (ii >= j0) & (ii < j1)
-        w[np.flatnonzero(self_j), ii[self_j] - j0] = 0.0
-        out[a: a + 8] = 2.0 * U32 * w.sum(1)
-    return out
+    jerk."""
+    return 2.0 * U32 * orc.velocity_scale(x, v, m, eps, ilist, j0, j1)
 
 
 def plain_gate(tag, g, o, scale, kmax, tol=1e-6, allow=None):
@@ -122,7 +108,7 @@ def check(orc, precision, ga, gj, x, v, m, eps, ilist=None, j0=0, j1=None, tag="
     else:
         sa, sj = orc.force_scale(x, v, m, eps, ilist, j0, j1)
         il = np.arange(len(m)) if ilist is None else np.asarray(ilist)
-        vb = velocity_bound(x, v, m, eps, il[keep], j0, j1)
+        vb = velocity_bound(orc, x, v, m, eps, il[keep], j0, j1)
         plain_gate("acc", ga[keep], oa[keep], sa[keep], KAPPA_PLAIN["acc"], TOL[precision])
         plain_gate("jerk", gj[keep], oj[keep], sj[keep], KAPPA_PLAIN["jerk"], TOL[precision],
                    allow=vb)
@@ -169,7 +155,7 @@ def check6(orc, precision, g, x, v, ap, m, eps, ilist=None, j0=0, j1=None, tag="
     vb = None
     if precision != "fp64":
         il = np.arange(len(m)) if ilist is None else np.asarray(ilist)
-        vb = velocity_bound(x, v, m, eps, il[keep], j0, j1)
+        vb = velocity_bound(orc, x, v, m, eps, il[keep], j0, j1)
     dj = np.linalg.norm(gj[keep] - oj[keep], axis=1)
     nj = (dj if vb is None else np.maximum(dj - vb, 0.0)) / sj[keep]
     ns = np.linalg.norm(gs[keep] - os_[keep], axis=1) / ss[keep]

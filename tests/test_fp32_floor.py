@@ -140,3 +140,23 @@ def test_fp32_velocities_set_the_jerk_floor_of_slow_binaries(orc):
     assert plain > 1e-6          # above the 1e-6 target from the velocity rounding alone,
     assert kappa < 1.1           # on a body whose jerk is one term (no cancellation),
     assert err <= bound          # and within the bound the GPU gate adds for it
+
+
+def test_velocity_scale_is_the_plain_sum(orc):
+    """The oracle's velocity scale (the sum the GPU jerk gates' allowance is built on)
+    against plain loops, with a j-range and the self term left out."""
+    rng = np.random.default_rng(9)
+    x, v, m = rng.normal(size=(30, 3)), rng.normal(size=(30, 3)), rng.random(30)
+    il, j0, j1, eps = [0, 4, 29, 11], 3, 25, 0.1
+    got = orc.velocity_scale(x, v, m, eps, il, j0, j1)
+    for k, i in enumerate(il):
+        want = 0.0
+        for j in range(j0, j1):
+            if j == i:
+                continue
+            s = sum((float(x[j][c]) - float(x[i][c])) ** 2 for c in range(3)) + eps * eps
+            want += float(m[j]) * (float(np.linalg.norm(v[i])) + float(np.linalg.norm(v[j]))) / s ** 1.5
+        assert abs(got[k] - want) <= 1e-13 * want
+    s = inputs.with_binaries(C5_N, C5_SEED)
+    b = 2.0 * 2.0 ** -24 * orc.velocity_scale(s.x, s.v, s.m, C5_EPS, [C5_BODY])[0]
+    assert abs(b - velocity_bound(s.x, s.v, s.m, C5_EPS, C5_BODY)) <= 1e-12 * b
