@@ -138,9 +138,11 @@ nb_status ensure_res(nb_ctx *ctx, size_t bytes)
 }
 
 // Copy `bytes` of host data into the pinned ring and enqueue its upload to the
-// device ring; returns the device address.  Regions are reused only after the
-// stream has drained (a wrap waits for the stream), so an upload is never
-// overwritten before the copy and the kernels that read it have run.
+// device ring; returns the device address.  The upload is a small kernel on
+// `stream` that reads the mapped ring (no copy engine, so no wait between
+// queues).  Regions are reused only after the stream has drained (a wrap waits
+// for the stream), so an upload is never overwritten before the copy and the
+// kernels that read it have run.
 nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
 {
     const size_t need = (bytes + 255) / 256 * 256;
@@ -149,14 +151,22 @@ nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
         if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
         if (ctx->stage_dev) (void)hipFree(ctx->stage_dev);
         ctx->stage_host = nullptr;
+        ctx->stage_host_dev = nullptr;
         ctx->stage_dev = nullptr;
+        ctx->stage_bytes = 0;
         const size_t want = std::max(need * 2, (size_t)8 << 20);
-        if (hipHostMalloc((void **)&ctx->stage_host, want, hipHostMallocDefault) != hipSuccess ||
+        void *hd = nullptr;
+        if (hipHostMalloc((void **)&ctx->stage_host, want,
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer(&hd, ctx->stage_host, 0) != hipSuccess || !hd ||
             hipMalloc((void **)&ctx->stage_dev, want) != hipSuccess) {
             (void)hipGetLastError();
-            ctx->stage_bytes = 0;
+            if (ctx->stage_host) (void)hipHostFree(ctx->stage_host);
+            ctx->stage_host = nullptr;
+            ctx->stage_dev = nullptr;
             return fail(ctx, NB_ENOMEM, "item table staging");
         }
+        ctx->stage_host_dev = (const char *)hd;
         ctx->stage_bytes = want;
         ctx->stage_off = 0;
     }
@@ -165,8 +175,9 @@ nb_status upload(nb_ctx *ctx, const void *src, size_t bytes, const void **dev)
         ctx->stage_off = 0;
     }
     memcpy(ctx->stage_host + ctx->stage_off, src, bytes);
-    NB_HIP(ctx, hipMemcpyAsync(ctx->stage_dev + ctx->stage_off, ctx->stage_host + ctx->stage_off,
-                               bytes, hipMemcpyHostToDevice, ctx->stream));
+    hipError_t e = nbk::launch_upload(ctx->stage_host_dev + ctx->stage_off,
+                                      ctx->stage_dev + ctx->stage_off, need, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "table upload launch");
     *dev = ctx->stage_dev + ctx->stage_off;
     ctx->stage_off += need;
     return NB_OK;
@@ -332,6 +343,7 @@ struct ForceLaunch {
     int il, s;
     bool h6;
     Table t;
+    double work;   // pair interactions of the launch
 };
 struct ForcePlan {
     std::vector<ForceLaunch> launches;   // reserved up front: staged Tables stay in place
@@ -412,11 +424,13 @@ nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec, Forc
         const int il = std::get<0>(kv.first), s = std::get<1>(kv.first);
         std::vector<Item> items;
         std::vector<int64_t> blocks;
+        double work = 0.0;
         for (size_t k : kv.second) {
             items.push_back(jobs[k].it);
             blocks.push_back(force_blocks(jobs[k].it, jobs[k].plan));
+            work += (double)jobs[k].it.m * (double)(jobs[k].it.j1 - jobs[k].it.j0);
         }
-        fp->launches.push_back(ForceLaunch{il, s, std::get<2>(kv.first), Table{}});
+        fp->launches.push_back(ForceLaunch{il, s, std::get<2>(kv.first), Table{}, work});
         NB_TRY(make_table(ctx, items, blocks, &fp->launches.back().t, st));
     }
     std::vector<Item> red;
@@ -431,13 +445,17 @@ nb_status prepare_force(nb_ctx *ctx, std::vector<ForceJob> &jobs, int prec, Forc
 }
 
 // One launch per plan shape.  Several shapes (ragged batches) run side by side:
-// the first on the context's stream, the others on side streams forked after the
-// table uploads and joined back before the partial reduction.  Every item writes
-// only its own outputs and partials, so the results do not depend on how the
-// launches overlap.
+// the one with the most pair interactions on the context's stream, the others on
+// side streams forked after the table uploads and joined back before the partial
+// reduction (the longest launch on the joining stream: the join then seldom
+// waits).  Every item writes only its own outputs and partials, so the results do
+// not depend on how the launches overlap.
 nb_status launch_force(nb_ctx *ctx, const ForcePlan &fp, int prec)
 {
     const int nl = (int)fp.launches.size();
+    int heavy = 0;
+    for (int k = 1; k < nl; ++k)
+        if (fp.launches[k].work > fp.launches[heavy].work) heavy = k;
     if (nl > 1) {
         NB_TRY(ensure_side_streams(ctx));
         NB_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
@@ -445,9 +463,9 @@ nb_status launch_force(nb_ctx *ctx, const ForcePlan &fp, int prec)
             NB_HIP(ctx, hipStreamWaitEvent(ctx->side[q], ctx->fork, 0));
     }
     hipError_t e = hipSuccess;
-    for (int k = 0; k < nl && e == hipSuccess; ++k) {
+    for (int k = 0, q = 0; k < nl && e == hipSuccess; ++k) {
         const ForceLaunch &l = fp.launches[k];
-        hipStream_t st = k == 0 ? ctx->stream : ctx->side[(k - 1) % nb_ctx::NSIDE];
+        hipStream_t st = k == heavy ? ctx->stream : ctx->side[q++ % nb_ctx::NSIDE];
         e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
                  : nbk::launch_force(prec, l.il, l.s, l.t, st);
     }

@@ -26,7 +26,8 @@ struct nb_ctx {
     void *res_host = nullptr;         // pinned, mapped: the results as the host reads them
     void *res_host_dev = nullptr;     // device address of res_host
     size_t res_bytes = 0;
-    char *stage_host = nullptr;       // pinned ring for item tables
+    char *stage_host = nullptr;       // pinned, mapped, coherent ring for item tables
+    const char *stage_host_dev = nullptr;   // device address of stage_host
     char *stage_dev = nullptr;        // device ring mirrored by stage_host
     size_t stage_bytes = 0, stage_off = 0;
     std::string err;

@@ -24,6 +24,9 @@ hipError_t launch_nearest(const Table &t, hipStream_t st);
 // Selection: two passes over per-item workgroup slices, then per-item results.
 hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, SelResult *res,
                          hipStream_t st);
+// Copy `bytes` (a multiple of 16) from mapped pinned host memory `src` (its
+// device address) to device memory `dst`, in stream order.
+hipError_t launch_upload(const char *src, char *dst, size_t bytes, hipStream_t st);
 // Copy each item's status word into res[k].status, then clear the words; host
 // (mapped pinned memory, or null) also receives every item's whole result.
 hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,

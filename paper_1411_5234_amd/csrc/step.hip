@@ -196,6 +196,21 @@ __global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, i
         *items[k].status = 0;
 }
 
+__global__ __launch_bounds__(WG) void upload_kernel(const uint4 *src, uint4 *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_upload(const char *src, char *dst, size_t bytes, hipStream_t st)
+{
+    const int64_t n = (int64_t)(bytes / sizeof(uint4));
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(upload_kernel, dim3((unsigned)((n + WG - 1) / WG)), dim3(WG), 0, st,
+                       (const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,
                                  hipStream_t st)
 {
