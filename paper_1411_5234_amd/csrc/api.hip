@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -20,6 +21,9 @@
 #define NB_VERSION "0.5.0"
 
 using nbk::Item;
+
+// Longest host spin on the selection flag before an event wait, in microseconds.
+constexpr long SEL_SPIN_US = 5000;
 using nbk::SelResult;
 using nbk::Table;
 
@@ -108,6 +112,11 @@ nb_status grow(nb_ctx *ctx, void **buf, size_t *have, size_t bytes, const char *
     return NB_OK;
 }
 
+// The flag word that follows the selection results in the mapped ring, as the
+// host and the device address it.
+unsigned *sel_flag_host(nb_ctx *ctx) { return (unsigned *)((char *)ctx->res_host + ctx->res_bytes); }
+unsigned *sel_flag_dev(nb_ctx *ctx) { return (unsigned *)((char *)ctx->res_host_dev + ctx->res_bytes); }
+
 nb_status ensure_res(nb_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->res_bytes) return NB_OK;
@@ -118,8 +127,9 @@ nb_status ensure_res(nb_ctx *ctx, size_t bytes)
     ctx->res_host_dev = nullptr;
     ctx->res_bytes = 0;
     // Coherent and mapped: the status kernel writes the results here directly,
-    // and the host reads them once that kernel has completed (no copy).
-    if (hipHostMalloc(&ctx->res_host, have, hipHostMallocMapped | hipHostMallocCoherent) !=
+    // then a flag word after them (at offset `have`), and the host reads them once
+    // it sees the flag or that kernel has completed (no copy).
+    if (hipHostMalloc(&ctx->res_host, have + 64, hipHostMallocMapped | hipHostMallocCoherent) !=
         hipSuccess) {
         (void)hipGetLastError();
         ctx->res_host = nullptr;
@@ -134,6 +144,7 @@ nb_status ensure_res(nb_ctx *ctx, size_t bytes)
         return fail(ctx, NB_EDEVICE, "device address of the pinned selection results");
     }
     ctx->res_bytes = have;
+    __atomic_store_n(sel_flag_host(ctx), 0u, __ATOMIC_RELAXED);
     return NB_OK;
 }
 
@@ -456,19 +467,22 @@ nb_status launch_force(nb_ctx *ctx, const ForcePlan &fp, int prec)
     int heavy = 0;
     for (int k = 1; k < nl; ++k)
         if (fp.launches[k].work > fp.launches[heavy].work) heavy = k;
+    auto launch = [&](const ForceLaunch &l, hipStream_t st) {
+        return l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
+                    : nbk::launch_force(prec, l.il, l.s, l.t, st);
+    };
     if (nl > 1) {
         NB_TRY(ensure_side_streams(ctx));
         NB_HIP(ctx, hipEventRecord(ctx->fork, ctx->stream));
+    }
+    // the largest launch first: it does not wait behind the side streams' set-up
+    // (each cross-stream wait costs the host several microseconds)
+    hipError_t e = nl > 0 ? launch(fp.launches[heavy], ctx->stream) : hipSuccess;
+    if (nl > 1)
         for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q)
             NB_HIP(ctx, hipStreamWaitEvent(ctx->side[q], ctx->fork, 0));
-    }
-    hipError_t e = hipSuccess;
-    for (int k = 0, q = 0; k < nl && e == hipSuccess; ++k) {
-        const ForceLaunch &l = fp.launches[k];
-        hipStream_t st = k == heavy ? ctx->stream : ctx->side[q++ % nb_ctx::NSIDE];
-        e = l.h6 ? nbk::launch_force6(prec, l.il, l.s, l.t, st)
-                 : nbk::launch_force(prec, l.il, l.s, l.t, st);
-    }
+    for (int k = 0, q = 0; k < nl && e == hipSuccess; ++k)
+        if (k != heavy) e = launch(fp.launches[k], ctx->side[q++ % nb_ctx::NSIDE]);
     // Joined even after a failed launch: the staging ring's reuse waits on
     // `stream` alone, so every side stream's work must sit behind it.
     for (int q = 0; q < std::min(nl - 1, nb_ctx::NSIDE); ++q) {
@@ -609,15 +623,29 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
     if (t.n != (int)items.size()) return fail(ctx, NB_EINVAL, "selection of an empty system");
     hipError_t e = nbk::launch_select(t, blockval, blockcnt, dres, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "selection launch");
+    const unsigned seq = ++ctx->sel_seq ? ctx->sel_seq : ++ctx->sel_seq;   // never 0
     e = nbk::launch_collect_status(t.items, t.n, dres, (SelResult *)ctx->res_host_dev,
-                                   ctx->stream);
+                                   predict ? sel_flag_dev(ctx) : nullptr, seq, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "status collection launch");
     if (predict) {
         NB_HIP(ctx, hipEventRecord(ctx->sel_done, ctx->stream));
         e = predict == 6 ? nbk::launch_predict6(tp, dres, ctx->stream)
                          : nbk::launch_predict(tp, dres, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
-        NB_HIP(ctx, hipEventSynchronize(ctx->sel_done));
+        // The results are complete once the status kernel has written the flag:
+        // spinning on it reacts within about a microsecond, where the event wait
+        // wakes the thread tens of microseconds late.  The spin is bounded (a
+        // long wait, or a device error, falls through to the event wait).
+        const unsigned *flag = sel_flag_host(ctx);
+        const auto t0 = std::chrono::steady_clock::now();
+        bool seen = false;
+        for (int k = 0; !seen; ++k) {
+            seen = __atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq;
+            if (!seen && (k & 1023) == 1023 &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(SEL_SPIN_US))
+                break;
+        }
+        if (!seen) NB_HIP(ctx, hipEventSynchronize(ctx->sel_done));
     } else {
         NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }

@@ -40,6 +40,8 @@ struct nb_ctx {
     bool side_ready = false;
     // Recorded after the selection's status kernel when a prediction follows it.
     hipEvent_t sel_done = nullptr;
+    // Sequence number the status kernel writes into the flag word after the results.
+    unsigned sel_seq = 0;
     // Host thread for pair advances (started on first use): a FIFO of jobs run in
     // call order; result is the first failure since the last wait.
     struct Worker {

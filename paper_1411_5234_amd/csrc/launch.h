@@ -28,9 +28,10 @@ hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, Se
 // device address) to device memory `dst`, in stream order.
 hipError_t launch_upload(const char *src, char *dst, size_t bytes, hipStream_t st);
 // Copy each item's status word into res[k].status, then clear the words; host
-// (mapped pinned memory, or null) also receives every item's whole result.
+// (mapped pinned memory, or null) also receives every item's whole result, and
+// then, when `flag` (mapped pinned memory) is set, the value `seq` in *flag.
 hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,
-                                 hipStream_t st);
+                                 unsigned *flag, unsigned seq, hipStream_t st);
 // sel: null, or the device selection results of the same items (see predict_kernel).
 hipError_t launch_predict(const Table &t, const SelResult *sel, hipStream_t st);
 hipError_t launch_correct(const Table &t, double eta, double dt_max, double dt_min,

@@ -180,10 +180,13 @@ hipError_t launch_select(const Table &t, double *blockval, int32_t *blockcnt, Se
 
 // One workgroup: read every item's status word into res[k].status and, when
 // `host` is set, write each item's whole result there (mapped pinned memory that
-// the host reads once this kernel has completed); then clear the words (several
-// items may share one word, so all reads finish before any clear).
+// the host reads once this kernel has completed, or once it sees `seq` in *flag);
+// then clear the words (several items may share one word, so all reads finish
+// before any clear).  Every lane's result stores reach host memory (system-scope
+// fence) before the barrier, and the flag is stored after it with release order.
 __global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, int n, SelResult *res,
-                                                            SelResult *host)
+                                                            SelResult *host, unsigned *flag,
+                                                            unsigned seq)
 {
     for (int k = threadIdx.x; k < n; k += WG) {
         SelResult r = res[k];
@@ -191,9 +194,12 @@ __global__ __launch_bounds__(WG) void collect_status_kernel(const Item *items, i
         res[k].status = r.status;
         if (host) host[k] = r;
     }
+    if (flag) __threadfence_system();
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += WG)
         *items[k].status = 0;
+    if (flag && threadIdx.x == 0)
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ __launch_bounds__(WG) void upload_kernel(const uint4 *src, uint4 *dst, int64_t n)
@@ -212,10 +218,11 @@ hipError_t launch_upload(const char *src, char *dst, size_t bytes, hipStream_t s
 }
 
 hipError_t launch_collect_status(const Item *items, int n, SelResult *res, SelResult *host,
-                                 hipStream_t st)
+                                 unsigned *flag, unsigned seq, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(collect_status_kernel, dim3(1), dim3(WG), 0, st, items, n, res, host);
+    hipLaunchKernelGGL(collect_status_kernel, dim3(1), dim3(WG), 0, st, items, n, res, host, flag,
+                       seq);
     return hipGetLastError();
 }
 
