@@ -280,6 +280,7 @@ class Server:
         self._tid_host = None
         self._tid_slots = []
         self._q_sets = []
+        self._q_rows = None
         self._returned = set()
         self.order = order
         _lib.force_plan(1, 1, "mixed", lanes)     # raises on a target out of range
@@ -408,8 +409,10 @@ class Server:
         tid, owner = self._q_tid, self._q_owner                          # tidal offsets
         if any(sl.ps is not ps for sl, ps in sets):
             raise RuntimeError("pair sets changed without a new tidal layout")
-        rows = np.repeat(np.fromiter((ps.base for _, ps in sets), dtype=np.int64,
-                                     count=len(sets)), k) + local        # table rows
+        bases = tuple(ps.base for _, ps in sets)
+        if self._q_rows is None or self._q_rows[0] != bases:
+            self._q_rows = (bases, np.repeat(np.array(bases, dtype=np.int64), k) + local)
+        rows = self._q_rows[1]                                           # table rows
         pt = tab.prev_t[rows]
         tcm = self._tcm_host.numpy()[tid + local]
         due = np.flatnonzero((tcm == pt) & (tab.tpair[rows] < pt))
@@ -711,8 +714,15 @@ class Server:
         # pairs' centres of mass, then the new ones (the layout nb_pairs_reduce makes)
         n_new = new_ps.cm0 + new_ps.np
         src = np.empty(n_new, dtype=np.int64)            # old row, or -1 - new pair
-        # the new singles are old ones; both lists are sorted
-        src[: new_ps.cm0] = np.searchsorted(ps.singles, new_ps.singles)
+        # the new singles are the old ones (rows 0 .. cm0 - 1, in order) but the
+        # members of the new pairs
+        keep = np.ones(ps.cm0, dtype=bool)
+        keep[p[sel]] = False
+        keep[q[sel]] = False
+        old_rows = np.flatnonzero(keep)
+        if old_rows.size != new_ps.cm0:
+            raise ValueError("capture candidates are not distinct single bodies")
+        src[: new_ps.cm0] = old_rows
         src[new_ps.cm0: new_ps.cm0 + ps.np] = ps.cm0 + np.arange(ps.np)
         src[new_ps.cm0 + ps.np:] = -1 - np.arange(kt)
         new64 = self._new_rows(xc, vc, ac, jc, M, np.full(kt, t_b), dts)
@@ -776,6 +786,7 @@ class Server:
         self._q_local = np.arange(int(k.sum())) - np.repeat(np.cumsum(k) - k, k)
         self._q_tid = np.repeat(np.array([sl.ps.tid_base for sl in gs], dtype=np.int64), k)
         self._q_owner = np.repeat(np.arange(len(gs)), k)
+        self._q_rows = None                      # (set bases, table rows), cached
         self._tid_stale = False
 
     def _tidal(self, ran_slots):
