@@ -610,8 +610,6 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
                 "selection temporaries"));
     ctx->selbuf_bytes = have;
     NB_TRY(ensure_res(ctx, items.size() * sizeof(SelResult)));
-    if (predict && !ctx->sel_done)
-        NB_HIP(ctx, hipEventCreateWithFlags(&ctx->sel_done, hipEventDisableTiming));
     double *blockval = (double *)ctx->selbuf;
     int32_t *blockcnt = (int32_t *)(blockval + total);
     SelResult *dres = (SelResult *)ctx->res;
@@ -628,14 +626,15 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
                                    predict ? sel_flag_dev(ctx) : nullptr, seq, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "status collection launch");
     if (predict) {
-        NB_HIP(ctx, hipEventRecord(ctx->sel_done, ctx->stream));
         e = predict == 6 ? nbk::launch_predict6(tp, dres, ctx->stream)
                          : nbk::launch_predict(tp, dres, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "predict launch");
         // The results are complete once the status kernel has written the flag:
-        // spinning on it reacts within about a microsecond, where the event wait
-        // wakes the thread tens of microseconds late.  The spin is bounded (a
-        // long wait, or a device error, falls through to the event wait).
+        // spinning on it reacts within about a microsecond, where an event wait
+        // woke the thread tens of microseconds late (and the event's record in
+        // the stream held the prediction back by about 6 us).  The spin is
+        // bounded: a long wait, or a device error, falls through to a stream
+        // synchronization (which also waits for the prediction).
         const unsigned *flag = sel_flag_host(ctx);
         const auto t0 = std::chrono::steady_clock::now();
         bool seen = false;
@@ -645,7 +644,7 @@ nb_status run_select(nb_ctx *ctx, std::vector<Item> &items, std::vector<SelResul
                 std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(SEL_SPIN_US))
                 break;
         }
-        if (!seen) NB_HIP(ctx, hipEventSynchronize(ctx->sel_done));
+        if (!seen) NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     } else {
         NB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
@@ -1019,7 +1018,6 @@ nb_status nb_ctx_destroy(nb_ctx *ctx)
         if (ctx->join[q]) (void)hipEventDestroy(ctx->join[q]);
     }
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
-    if (ctx->sel_done) (void)hipEventDestroy(ctx->sel_done);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->selbuf) (void)hipFree(ctx->selbuf);
     if (ctx->res) (void)hipFree(ctx->res);

@@ -38,8 +38,6 @@ struct nb_ctx {
     hipStream_t side[NSIDE] = {};
     hipEvent_t fork = nullptr, join[NSIDE] = {};
     bool side_ready = false;
-    // Recorded after the selection's status kernel when a prediction follows it.
-    hipEvent_t sel_done = nullptr;
     // Sequence number the status kernel writes into the flag word after the results.
     unsigned sel_seq = 0;
     // Host thread for pair advances (started on first use): a FIFO of jobs run in
