@@ -250,8 +250,10 @@ nb_status nb_force_active_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t
 nb_status nb_correct_batch(nb_ctx *ctx, const nb_batch_item *items, int32_t n_items,
                            double eta, double eta_s, double dt_max, double dt_min);
 
-/* One iteration of an ensemble loop in one call: a1 for every item (waits for
- * the stream), then, for every item without an error whose next block time is
+/* One iteration of an ensemble loop in one call: a1 for every item (waits until
+ * the selection's results have reached the host, by a bounded spin on a flag the
+ * device writes after them, else a stream synchronization), then, for every item
+ * without an error whose next block time is
  * not past its t_end, a2 + a3 + a4 + a5 as in the four calls above (startup
  * items: force + startup steps, after which their startup flag is cleared).
  * Here a2 is enqueued right after the selection and runs while the host reads
