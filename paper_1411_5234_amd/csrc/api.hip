@@ -21,11 +21,12 @@
 #define NB_VERSION "0.5.0"
 
 using nbk::Item;
-
-// Longest host spin on the selection flag before an event wait, in microseconds.
-constexpr long SEL_SPIN_US = 5000;
 using nbk::SelResult;
 using nbk::Table;
+
+// Longest host spin on the selection flag before a stream synchronization, in
+// microseconds.
+constexpr long SEL_SPIN_US = 5000;
 
 namespace {
 
