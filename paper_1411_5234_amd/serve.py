@@ -172,6 +172,29 @@ def return_layout(old_singles, new_singles, members, old_cm0, keep_pairs):
     return src
 
 
+def capture_layout(old_cm0, old_np, p, q):
+    """Rows of a reduced system after the single bodies at rows p[k] and q[k] (rows
+    below old_cm0, all distinct) become the k-th new pair: for each row of the new
+    system (its bodies in no pair, in index order, then the old pairs' centres of
+    mass, then the new pairs'; the layout nb_pairs_reduce makes), the row of the old
+    system it continues (>= 0), or -1 - k for the k-th new pair's centre of mass."""
+    p = np.asarray(p, dtype=np.int64)
+    q = np.asarray(q, dtype=np.int64)
+    kt = p.size
+    keep = np.ones(old_cm0, dtype=bool)
+    keep[p] = False
+    keep[q] = False
+    old_rows = np.flatnonzero(keep)
+    if q.size != kt or old_rows.size != old_cm0 - 2 * kt:
+        raise ValueError("capture candidates are not distinct single bodies")
+    ns = old_rows.size
+    src = np.empty(ns + old_np + kt, dtype=np.int64)
+    src[:ns] = old_rows
+    src[ns: ns + old_np] = old_cm0 + np.arange(old_np)
+    src[ns + old_np:] = -1 - np.arange(kt)
+    return src
+
+
 def mutual_nearest(rows, nn, n):
     """Pairs (p, q), p < q, of listed bodies that are each other's nearest neighbour:
     rows[k] lists a body, nn[k] its nearest neighbour (-1: not searched)."""
@@ -713,18 +736,9 @@ class Server:
         # the new reduced system: bodies in no pair in index order, then the old
         # pairs' centres of mass, then the new ones (the layout nb_pairs_reduce makes)
         n_new = new_ps.cm0 + new_ps.np
-        src = np.empty(n_new, dtype=np.int64)            # old row, or -1 - new pair
-        # the new singles are the old ones (rows 0 .. cm0 - 1, in order) but the
-        # members of the new pairs
-        keep = np.ones(ps.cm0, dtype=bool)
-        keep[p[sel]] = False
-        keep[q[sel]] = False
-        old_rows = np.flatnonzero(keep)
-        if old_rows.size != new_ps.cm0:
-            raise ValueError("capture candidates are not distinct single bodies")
-        src[: new_ps.cm0] = old_rows
-        src[new_ps.cm0: new_ps.cm0 + ps.np] = ps.cm0 + np.arange(ps.np)
-        src[new_ps.cm0 + ps.np:] = -1 - np.arange(kt)
+        src = capture_layout(ps.cm0, ps.np, p[sel], q[sel])   # old row, or -1 - new pair
+        if src.size != n_new:
+            raise ValueError("capture layout does not match the new pair set")
         new64 = self._new_rows(xc, vc, ac, jc, M, np.full(kt, t_b), dts)
         sysn = self._rebuild(sl, src, new64)
         ctx.sync()

@@ -144,6 +144,31 @@ def test_return_layout_matches_a_plain_mapping():
         assert src.tolist() == want, (n, npairs, kret)
 
 
+def test_capture_layout_matches_a_plain_mapping():
+    """The rows of a reduced system after single bodies pair up: the other singles
+    keep their old rows in order, the old centres of mass follow, then the new
+    ones; against a plain dictionary mapping on random systems, and refused when
+    the candidates are not distinct single bodies."""
+    from paper_1411_5234_amd.serve import capture_layout
+    rng = np.random.default_rng(11)
+    for n, npairs, knew in ((40, 10, 3), (12, 0, 6), (30, 1, 1), (9, 2, 0), (50, 20, 5)):
+        perm = rng.permutation(n)
+        pairs = perm[: 2 * npairs].reshape(-1, 2)
+        singles = np.setdiff1d(np.arange(n), pairs.ravel())
+        cm0 = singles.size
+        rows = rng.choice(cm0, 2 * knew, replace=False)
+        p, q = rows[:knew], rows[knew:]
+        src = capture_layout(cm0, npairs, p, q)
+        new_pairs = np.stack([singles[p], singles[q]], axis=1)
+        new_singles = np.setdiff1d(singles, new_pairs.ravel())
+        old_row = {int(i): r for r, i in enumerate(singles)}
+        want = ([old_row[int(i)] for i in new_singles] + [cm0 + k for k in range(npairs)]
+                + [-1 - k for k in range(knew)])
+        assert src.tolist() == want, (n, npairs, knew)
+    with pytest.raises(ValueError):
+        capture_layout(10, 0, np.array([1, 2]), np.array([2, 3]))   # body 2 twice
+
+
 def test_mutual_nearest_neighbours():
     from paper_1411_5234_amd.serve import mutual_nearest
     rows = np.array([3, 5, 7, 9, 11, 2])
