@@ -17,6 +17,7 @@ import test_oracle_force as tf
 import test_oracle_hermite as th
 import test_oracle_hermite6 as t6
 import test_oracle_groups as tg
+import test_fp32_floor as tfl
 
 SRC = os.path.join(os.path.dirname(real_oracle.__file__), "nbody_oracle.c")
 
@@ -130,6 +131,16 @@ MUTANTS = [
      lambda o: tg.test_tidal_at_points_is_minus_hessian_of_the_rest(o)),
     ("tidal at points measured from the origin", "d[c] = x[3 * j + c] - p[3 * k + c];", "d[c] = x[3 * j + c];",
      lambda o: tg.test_tidal_at_points_is_minus_hessian_of_the_rest(o)),
+    ("velocity scale without |v_j|", "cs_add(&t, m[j] * (vi + vj) / (s * sqrt(s)));",
+     "cs_add(&t, m[j] * vi / (s * sqrt(s)));",
+     lambda o: tfl.test_velocity_scale_is_the_plain_sum(o)),
+    ("velocity scale with s^-1 instead of s^-3/2", "cs_add(&t, m[j] * (vi + vj) / (s * sqrt(s)));",
+     "cs_add(&t, m[j] * (vi + vj) / s);",
+     lambda o: tfl.test_velocity_scale_is_the_plain_sum(o)),
+    ("velocity scale counts the body itself",
+     "            if (j == i)\n                continue;\n            double dr[3];",
+     "            if (0)\n                continue;\n            double dr[3];",
+     lambda o: tfl.test_velocity_scale_is_the_plain_sum(o)),
 ]
 
 
